@@ -1,0 +1,257 @@
+"""Seeded synthetic inputs for the (1,2)-symmetric sparse tensor workloads.
+
+This module only draws inputs: coordinates, values, random start matrices and
+arrival times. It performs none of the method's arithmetic (no contractions,
+no orthogonalisation), so both the FP64 oracle and the HIP path can consume
+the same inputs without sharing any computation.
+
+The shapes and value laws follow the paper's experiments (Section 5.2):
+sparse (1,2)-symmetric tensors A in R^{m x m x n} whose mode-3 slices are
+symmetric (Definition of a (1,2)-symmetric tensor, Section 2.1), with
+power-law mode-1/2 indices (social-network and word co-occurrence tensors)
+and uniform mode-3 indices.  Indices are 0-based.
+
+Every stored entry is one distinct position (i, j, k) with i <= j; the full
+tensor holds it at (i, j, k) and (j, i, k).
+"""
+from __future__ import annotations
+
+import dataclasses
+import numpy as np
+
+
+@dataclasses.dataclass
+class SymCOO:
+    """Stored upper-triangular entries of a (1,2)-symmetric tensor."""
+
+    m: int
+    n: int
+    i: np.ndarray  # int32, i <= j
+    j: np.ndarray  # int32
+    k: np.ndarray  # int32
+    val: np.ndarray  # float32 or float64
+
+    @property
+    def nnz(self) -> int:
+        return int(self.i.shape[0])
+
+    def astype(self, dtype) -> "SymCOO":
+        return dataclasses.replace(self, val=self.val.astype(dtype))
+
+
+def _zipf_labels(rng, m: int, size: int, s: float, perm: np.ndarray) -> np.ndarray:
+    """Draw labels in [0, m): rank r (1-based) has probability ~ r^-s, then a
+    fixed permutation maps ranks to labels so heavy rows are not at index 0.
+    s == 0 gives the uniform law."""
+    if s == 0.0:
+        return rng.integers(0, m, size=size, dtype=np.int64)
+    w = np.arange(1, m + 1, dtype=np.float64) ** (-s)
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    u = rng.random(size)
+    r = np.searchsorted(cdf, u, side="right")
+    np.minimum(r, m - 1, out=r)
+    return perm[r]
+
+
+def sparse_sym(m: int, n: int, nnz: int, zipf: float = 0.0, values: str = "normal",
+               seed: int = 0, dtype=np.float32) -> SymCOO:
+    """Generator G(m, n, nnz, s, values): exactly ``nnz`` distinct stored
+    positions (i <= j, k).  i and j are drawn from a truncated Zipf(s) law on
+    the (permuted) row labels, k uniformly; positions are canonicalised to
+    (min, max), deduplicated, oversampled until enough distinct positions
+    exist, and a seeded subset of exactly ``nnz`` is kept.
+
+    values: "normal" -> N(0,1); "abs" -> |N(0,1)|; "ones" -> 1.
+    """
+    if nnz < 0:
+        raise ValueError("nnz must be >= 0")
+    cap = (m * (m + 1) // 2) * n
+    if nnz > cap:
+        raise ValueError(f"nnz={nnz} exceeds the {cap} available positions")
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(m).astype(np.int64)
+    keys = np.empty(0, dtype=np.int64)
+    want = nnz
+    rounds = 0
+    while keys.shape[0] < nnz:
+        draw = int(max(1024, (want - keys.shape[0]) * 1.25 + 64))
+        a = _zipf_labels(rng, m, draw, zipf, perm)
+        b = _zipf_labels(rng, m, draw, zipf, perm)
+        kk = rng.integers(0, n, size=draw, dtype=np.int64)
+        lo = np.minimum(a, b)
+        hi = np.maximum(a, b)
+        new = (kk * m + lo) * m + hi
+        keys = np.union1d(keys, new)
+        rounds += 1
+        if rounds > 200:
+            raise RuntimeError("could not draw enough distinct positions")
+    if keys.shape[0] > nnz:
+        keep = rng.choice(keys.shape[0], size=nnz, replace=False)
+        keep.sort()
+        keys = keys[keep]
+    j = keys % m
+    t = keys // m
+    i = t % m
+    k = t // m
+    if values == "normal":
+        v = rng.standard_normal(nnz)
+    elif values == "abs":
+        v = np.abs(rng.standard_normal(nnz))
+    elif values == "ones":
+        v = np.ones(nnz)
+    else:
+        raise ValueError(values)
+    # shuffle the order so no consumer can rely on sorted input
+    order = rng.permutation(nnz)
+    return SymCOO(m, n, i[order].astype(np.int32), j[order].astype(np.int32),
+                  k[order].astype(np.int32), v[order].astype(dtype))
+
+
+def planted(m: int, n: int, core_diag, rows_per_col: int, slices_per_col: int,
+            seed: int) -> SymCOO:
+    """A planted (1,2)-symmetric tensor sum_t f_t u_t o u_t o w_t with a
+    superdiagonal core f (``core_diag``) and factors that are orthonormal by
+    construction: column t of U is N(0,1) on its own block of ``rows_per_col``
+    random rows (disjoint across columns) scaled to unit length, and the same
+    for W with ``slices_per_col`` slices.  Multilinear rank (r, r, r) with
+    r = len(core_diag).  Returned as stored entries (i <= j)."""
+    rng = np.random.default_rng(seed)
+    r = len(core_diag)
+    rows = rng.choice(m, size=r * rows_per_col, replace=False).reshape(r, rows_per_col)
+    sl = rng.choice(n, size=r * slices_per_col, replace=False).reshape(r, slices_per_col)
+    ii, jj, kk, vv = [], [], [], []
+    for t in range(r):
+        u = rng.standard_normal(rows_per_col)
+        u /= np.sqrt(np.sum(u * u))
+        w = rng.standard_normal(slices_per_col)
+        w /= np.sqrt(np.sum(w * w))
+        ridx = rows[t]
+        for a in range(rows_per_col):
+            for b in range(rows_per_col):
+                if ridx[a] > ridx[b]:
+                    continue
+                for c in range(slices_per_col):
+                    ii.append(ridx[a]); jj.append(ridx[b]); kk.append(sl[t, c])
+                    vv.append(core_diag[t] * u[a] * u[b] * w[c])
+    return SymCOO(m, n, np.asarray(ii, np.int32), np.asarray(jj, np.int32),
+                  np.asarray(kk, np.int32), np.asarray(vv, np.float64))
+
+
+def merge(a: SymCOO, b: SymCOO) -> SymCOO:
+    """Union of two stored-entry sets of the same shape; values at common
+    positions are added."""
+    assert a.m == b.m and a.n == b.n
+    m = a.m
+    ka = (a.k.astype(np.int64) * m + a.i) * m + a.j
+    kb = (b.k.astype(np.int64) * m + b.i) * m + b.j
+    keys = np.concatenate([ka, kb])
+    vals = np.concatenate([a.val.astype(np.float64), b.val.astype(np.float64)])
+    uk, inv = np.unique(keys, return_inverse=True)
+    v = np.zeros(uk.shape[0])
+    np.add.at(v, inv, vals)
+    j = uk % m
+    t = uk // m
+    return SymCOO(m, a.n, (t % m).astype(np.int32), j.astype(np.int32),
+                  (t // m).astype(np.int32), v.astype(a.val.dtype))
+
+
+def random_start(m: int, n: int, r: int, r3: int, seed: int):
+    """N(0,1) start matrices (m x r, n x r3) for BKS and HOOI.  Both the oracle
+    and the library orthonormalise them themselves."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((m, r)), rng.standard_normal((n, r3))
+
+
+def random_block(rows: int, cols: int, seed: int, dtype=np.float64):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((rows, cols)).astype(dtype)
+
+
+def dense_signal_noise(m: int, n: int, r: int, r3: int, rho: float, seed: int):
+    """Example-1-like dense tensor (Section 5.2.1): an (r, r, r3) N(0,1) block,
+    symmetrised in modes 1-2, placed in the leading corner of an m x m x n zero
+    tensor, plus rho times a symmetrised N(0,1) noise tensor; then one random
+    permutation applied to modes 1 and 2 and an independent one to mode 3.
+    Returned as the stored entries (i <= j) of the dense tensor.  Symmetrising
+    is done by averaging a block with its 1-2 transpose (input shaping only)."""
+    rng = np.random.default_rng(seed)
+    S = rng.standard_normal((r, r, r3))
+    S = 0.5 * (S + S.transpose(1, 0, 2))
+    N = rng.standard_normal((m, m, n))
+    N = 0.5 * (N + N.transpose(1, 0, 2))
+    A = rho * N
+    A[:r, :r, :r3] += S
+    p12 = rng.permutation(m)
+    p3 = rng.permutation(n)
+    A = A[np.ix_(p12, p12, p3)]
+    iu, ju = np.triu_indices(m)
+    i = np.repeat(iu, n)
+    j = np.repeat(ju, n)
+    k = np.tile(np.arange(n), iu.shape[0])
+    v = A[i, j, k]
+    return SymCOO(m, n, i.astype(np.int32), j.astype(np.int32), k.astype(np.int32), v)
+
+
+# ---------------------------------------------------------------- configs
+# Workloads shaped like the benchmark configurations.  Seeds are 1000 + index.
+
+def c1(seed: int = 1000) -> SymCOO:
+    """500 x 500 x 100: 5e4 uniform stored positions with N(0,1) values (FP64)
+    plus a planted rank-(2,2,2) part with superdiagonal core (10, 5) whose
+    factors live on 10 rows and 5 slices per column."""
+    noise = sparse_sym(500, 100, 50_000, zipf=0.0, values="normal", seed=seed,
+                       dtype=np.float64)
+    plant = planted(500, 100, (10.0, 5.0), 10, 5, seed + 7)
+    return merge(noise, plant)
+
+
+def c2(seed: int = 1001) -> SymCOO:
+    """20000 x 20000 x 2000, 2e6 stored, Zipf(1.3) modes 1-2, |N(0,1)| FP32."""
+    return sparse_sym(20_000, 2_000, 2_000_000, zipf=1.3, values="abs", seed=seed)
+
+
+def c3(seed: int = 1002) -> SymCOO:
+    """200000 x 200000 x 10000, 5e7 stored, Zipf(1.5) modes 1-2, |N(0,1)| FP32."""
+    return sparse_sym(200_000, 10_000, 50_000_000, zipf=1.5, values="abs", seed=seed)
+
+
+def c5(seed: int = 1004) -> SymCOO:
+    """1e6 x 1e6 x 500, 2e8 stored, Zipf(1.6) modes 1-2, |N(0,1)| FP32."""
+    return sparse_sym(1_000_000, 500, 200_000_000, zipf=1.6, values="abs", seed=seed)
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival_s: float
+    m: int
+    n: int
+    nnz: int
+    r: int
+    seed: int
+
+
+def c4_requests(count: int = 512, rate_per_s: float = 10.0, seed: int = 1003,
+                m_range=(1_000, 100_000), n_range=(100, 5_000),
+                nnz_range=(10_000, 5_000_000), ranks=(2, 3, 5, 8, 10)):
+    """Serving trace: Poisson arrivals at ``rate_per_s``; per request I, K and
+    nnz uniform on their ranges, r1 = r2 = r3 = r drawn from ``ranks``.  The
+    tensor of request ``rid`` is ``sparse_sym(m, n, nnz, 1.3, 'abs', seed)``
+    with seed 4000 + rid."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate_per_s, size=count)
+    t = np.cumsum(gaps) - gaps[0]
+    out = []
+    for q in range(count):
+        m = int(rng.integers(m_range[0], m_range[1] + 1))
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        nnz = int(rng.integers(nnz_range[0], nnz_range[1] + 1))
+        nnz = min(nnz, (m * (m + 1) // 2) * n // 4)
+        r = int(rng.choice(ranks))
+        out.append(Request(q, float(t[q]), m, n, nnz, r, 4000 + q))
+    return out
+
+
+def request_tensor(req: Request) -> SymCOO:
+    return sparse_sym(req.m, req.n, req.nnz, zipf=1.3, values="abs", seed=req.seed)

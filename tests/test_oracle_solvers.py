@@ -1,0 +1,177 @@
+"""Pins for the oracle's solvers (Algorithm 5, Section 5.1 HOOI, the inner
+Newton-Grassmann solve): closed forms (n = 1 and rank-1-in-mode-3 reduce to a
+symmetric eigenproblem), exact recovery of a planted tensor, the Pythagoras
+identity behind eq. Rayleigh, local = global gradient (Section 2.5 and
+Proposition 3.2), the S-value identity (Section 2.6, Lemma 3.1), the
+non-decreasing objective (eq. Fnon-decr), BKS = HOOI on a well-conditioned
+problem (Section 5.2.1) and the Newton model against finite differences."""
+import numpy as np
+import pytest
+
+from oracle import bks, core, hooi, sptensor, ttmc
+from oracle.orth import orthonormalize
+from paper_2012_07595_amd import workloads
+
+
+def to_T(c):
+    return sptensor.from_coo(c.m, c.n, c.i, c.j, c.k, c.val)
+
+
+def sym_matrix(m, seed, density=0.3):
+    """Sparse positive semidefinite S = G G^T.  For PSD S the only local
+    maximiser of ||U^T S U|| is the top-r eigenspace (with mixed signs every
+    eigenset whose positive eigenvalues exceed, and negative ones undercut,
+    all excluded ones is a local maximum)."""
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((m, m // 3)) * (rng.random((m, m // 3)) < density)
+    return G @ G.T
+
+
+def test_n1_reduces_to_symmetric_eigenproblem():
+    m, r = 30, 3
+    S = sym_matrix(m, 1)
+    T = sptensor.from_dense(S[:, :, None])
+    lam, V = np.linalg.eigh(S)
+    top = np.argsort(-np.abs(lam))[:r]
+    U_init, W_init = workloads.random_start(m, 1, r, 1, 5)
+    for res in (bks.bks_solve(T, r, 1, U_init, W_init),
+                hooi.hooi_solve(T, r, 1, U_init, W_init)):
+        assert res["converged"]
+        assert bks.subspace_distance(V[:, top], res["U"]) < 1e-10
+        nf2 = np.sum(res["F"] ** 2)
+        assert abs(nf2 - np.sum(lam[top] ** 2)) < 1e-10 * nf2
+
+
+def test_rank1_in_mode3_closed_form():
+    m, n, r = 25, 6, 2
+    S = sym_matrix(m, 2)
+    c = np.random.default_rng(3).standard_normal(n)
+    T = sptensor.from_dense(S[:, :, None] * c[None, None, :])
+    lam, V = np.linalg.eigh(S)
+    top = np.argsort(-np.abs(lam))[:r]
+    U_init, W_init = workloads.random_start(m, n, r, 1, 8)
+    res = bks.bks_solve(T, r, 1, U_init, W_init)
+    assert res["converged"]
+    assert bks.subspace_distance(V[:, top], res["U"]) < 1e-10
+    assert bks.subspace_distance((c / np.linalg.norm(c))[:, None], res["W"]) < 1e-10
+    nf2 = np.sum(res["F"] ** 2)
+    assert abs(nf2 - (c @ c) * np.sum(lam[top] ** 2)) < 1e-10 * nf2
+
+
+def test_planted_exact_recovery():
+    """A noise-free planted tensor of multilinear rank (2, 2, 2) is recovered
+    exactly: ||F|| = ||A|| and the planted subspaces are found."""
+    P = workloads.planted(60, 15, (10.0, 5.0), 6, 4, seed=3)
+    T = to_T(P)
+    A = sptensor.dense(T)
+    # planted factor spans from the dense tensor (rank-2 unfoldings)
+    Uref = np.linalg.svd(A.reshape(60, -1), full_matrices=False)[0][:, :2]
+    Wref = np.linalg.svd(A.transpose(2, 0, 1).reshape(15, -1), full_matrices=False)[0][:, :2]
+    U_init, W_init = workloads.random_start(60, 15, 2, 2, 4)
+    res = bks.bks_solve(T, 2, 2, U_init, W_init)
+    assert res["converged"]
+    assert abs(np.sqrt(np.sum(res["F"] ** 2)) - res["normA"]) < 1e-12 * res["normA"]
+    assert bks.subspace_distance(Uref, res["U"]) < 1e-10
+    assert bks.subspace_distance(Wref, res["W"]) < 1e-10
+
+
+def test_pythagoras_at_any_orthonormal_point():
+    """||A||^2 = ||F||^2 + ||A - (U,U,W).F||^2 with F = A.(U,U,W) (eq. Rayleigh)."""
+    c = workloads.sparse_sym(12, 5, 120, values="normal", seed=4, dtype=np.float64)
+    T = to_T(c)
+    A = sptensor.dense(T)
+    rng = np.random.default_rng(0)
+    U = orthonormalize(rng.standard_normal((12, 3)))
+    W = orthonormalize(rng.standard_normal((5, 2)))
+    F = core.mprod(A, U, U, W)
+    B = np.einsum("ijk,ai,bj,ck->abc", F, U, U, W)
+    assert abs(np.sum(A * A) - np.sum(F * F) - np.sum((A - B) ** 2)) < 1e-12 * np.sum(A * A)
+
+
+def test_local_gradient_equals_global_and_svalue_identity():
+    c = workloads.sparse_sym(14, 6, 200, values="normal", seed=6, dtype=np.float64)
+    T = to_T(c)
+    A = sptensor.dense(T)
+    rng = np.random.default_rng(1)
+    U = orthonormalize(rng.standard_normal((14, 2)))
+    W = orthonormalize(rng.standard_normal((6, 2)))
+    st = bks.bk_step(T, U, W)
+    rel_g, F = hooi.global_gradient(T, U, W)
+    assert abs(st["rel"] - rel_g) < 1e-12 * rel_g
+    # gradient through explicit complements: <F_perp^1, F>_{-1}, <F_perp^3, F>_{-3}
+    Up = core.complement(U)
+    Wp = core.complement(W)
+    F1p = core.mprod(A, Up, U, W)
+    F3p = core.mprod(A, U, U, Wp)
+    g1 = np.einsum("xbc,abc->xa", F1p, F)
+    g3 = np.einsum("abz,abc->zc", F3p, F)
+    nf = np.sqrt(np.sum(F * F))
+    assert abs(np.sqrt(2 * np.sum(g1 ** 2) + np.sum(g3 ** 2)) / nf - st["rel"]) < 1e-12 * st["rel"]
+    # S-values: s_{r+1}^(k) = sqrt(lambda_max(<F_perp, F_perp>_{-k}))
+    s1 = np.sqrt(np.linalg.eigvalsh(np.einsum("xbc,ybc->xy", F1p, F1p)).max())
+    s3 = np.sqrt(np.linalg.eigvalsh(np.einsum("abx,aby->xy", F3p, F3p)).max())
+    assert abs(st["svals1"][-1] - s1) < 1e-12 * s1
+    assert abs(st["svals3"][-1] - s3) < 1e-12 * s3
+    S1 = np.sqrt(np.linalg.eigvalsh(np.einsum("abc,dbc->ad", F, F))[::-1])
+    np.testing.assert_allclose(st["svals1"][:-1], S1, rtol=1e-12)
+
+
+def test_monotone_objective_bounded_by_norm():
+    c = workloads.sparse_sym(80, 20, 3000, values="abs", seed=9, dtype=np.float64)
+    T = to_T(c)
+    U_init, W_init = workloads.random_start(80, 20, 3, 3, 2)
+    res = bks.bks_solve(T, 3, 3, U_init, W_init, max_outer=40)
+    f = np.array(res["normF_hist"])
+    assert np.all(np.diff(f) >= -1e-12 * f[-1])
+    assert f[-1] <= res["normA"] * (1 + 1e-14)
+
+
+@pytest.mark.parametrize("rho", [1e-2, 1e-4])
+def test_bks_equals_hooi_well_conditioned(rho):
+    """Example-1-like signal plus noise: BKS and HOOI reach the same subspaces
+    (Section 5.2.1 compares the solutions by their subspace angles)."""
+    c = workloads.dense_signal_noise(40, 40, 2, 2, rho, seed=3)
+    T = to_T(c)
+    U_init, W_init = workloads.random_start(40, 40, 2, 2, 5)
+    rb = bks.bks_solve(T, 2, 2, U_init, W_init)
+    rh = hooi.hooi_solve(T, 2, 2, U_init, W_init)
+    assert rb["converged"] and rh["converged"]
+    assert bks.subspace_distance(rh["U"], rb["U"]) < 1e-10
+    assert bks.subspace_distance(rh["W"], rb["W"]) < 1e-10
+    assert rb["outer_iters"] < 15
+
+
+def test_newton_model_against_finite_differences():
+    rng = np.random.default_rng(0)
+    k1, k3, r, r3 = 7, 5, 2, 2
+    C = rng.standard_normal((k1, k1, k3))
+    C = 0.5 * (C + C.transpose(1, 0, 2))
+    P = orthonormalize(rng.standard_normal((k1, r)))
+    S = orthonormalize(rng.standard_normal((k3, r3)))
+    bl = core.blocks(C, P, S)
+    b, A = core.newton_model(bl)
+    nd = (k1 - r) * r
+    N = nd + (k3 - r3) * r3
+
+    def phi(d):
+        return core.objective(C, core.retract(bl["Qp"], d[:nd].reshape(k1 - r, r)),
+                              core.retract(bl["Qs"], d[nd:].reshape(k3 - r3, r3)))
+    h = 1e-4
+    E = np.eye(N)
+    g = np.array([(phi(h * E[i]) - phi(-h * E[i])) / (2 * h) for i in range(N)])
+    H = np.array([[(phi(h * (E[i] + E[j])) - phi(h * (E[i] - E[j])) - phi(h * (E[j] - E[i]))
+                    + phi(-h * (E[i] + E[j]))) / (4 * h * h) for j in range(N)] for i in range(N)])
+    assert np.abs(g - b).max() < 1e-5 * np.abs(b).max()
+    assert np.abs(H - 2 * A).max() < 1e-4 * np.abs(A).max()
+
+
+def test_newton_grassmann_converges_quadratically():
+    rng = np.random.default_rng(2)
+    C = 0.05 * rng.standard_normal((9, 9, 6))
+    C[:2, :2, :2] += rng.standard_normal((2, 2, 2))
+    C = 0.5 * (C + C.transpose(1, 0, 2))
+    P, S = core.hosvd(C, 2, 2)
+    for _ in range(5):
+        P, S = core.hooi_step(C, P, S)
+    P2, S2, it, rel, newton = core.newton_grassmann(C, P, S, 1e-13, 50)
+    assert rel <= 1e-13 and it <= 8
