@@ -1,0 +1,248 @@
+"""ctypes binding of libbks (the C ABI in include/bks.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Device buffers are passed as raw pointers (torch tensors are used
+for device memory and streams).  Loading fails loudly when the library has
+not been built; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libbks.so")
+
+OK, EINVAL, EINDEX, EVALUE, EASYM, ENOMEM, EDEVICE, ENOTFOUND, EDUP = 0, -1, -2, -3, -4, -5, -6, -7, -8
+ENOTCONV = 1
+F32, F64, F32IN_F64ACC = 0, 1, 2
+FREE3, FREE1, MODE3 = 0, 1, 2
+DEVICE_PTRS, SUM_DUPLICATES, FULL_SYMMETRIC = 1, 2, 4
+VARIANT = {"bk": 0, "min": 1, "max": 2}
+PREC_FP64, PREC_MIXED = 0, 1
+
+SYMBOLS = [
+    "bks_ctx_create", "bks_ctx_destroy", "bks_last_error", "bks_version",
+    "bks_tensor_upload", "bks_tensor_info", "bks_tensor_pairs", "bks_tensor_free",
+    "bks_ttmc", "bks_solve", "hooi_solve",
+    "bks_server_create", "bks_server_submit", "bks_server_submit_coo", "bks_server_poll",
+    "bks_server_wait", "bks_server_now", "bks_server_destroy",
+]
+
+
+class BksError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libbks error {code}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("r", C.c_int), ("r3", C.c_int), ("s", C.c_int), ("p", C.c_int),
+                ("variant", C.c_int), ("precision", C.c_int), ("tol", C.c_double),
+                ("inner_tol", C.c_double), ("max_outer", C.c_int), ("hooi_warm", C.c_int),
+                ("ng_max", C.c_int), ("U0", C.c_void_p), ("W0", C.c_void_p),
+                ("seed", C.c_uint64)]
+
+
+class HooiParams(C.Structure):
+    _fields_ = [("r", C.c_int), ("r3", C.c_int), ("precision", C.c_int), ("tol", C.c_double),
+                ("max_iter", C.c_int), ("grad_every", C.c_int), ("U0", C.c_void_p),
+                ("W0", C.c_void_p), ("seed", C.c_uint64)]
+
+
+class Info(C.Structure):
+    _fields_ = [("outer_iters", C.c_int), ("converged", C.c_int), ("k1", C.c_int),
+                ("k3", C.c_int), ("rel_grad", C.c_double), ("normF", C.c_double),
+                ("normA", C.c_double), ("svals1", C.c_double * 65), ("svals3", C.c_double * 65),
+                ("t_expand", C.c_double), ("t_core", C.c_double), ("t_inner", C.c_double),
+                ("t_step", C.c_double), ("t_total", C.c_double), ("n_hist", C.c_int),
+                ("rel_hist", C.c_double * 512), ("normF_hist", C.c_double * 512)]
+
+
+class ServerParams(C.Structure):
+    _fields_ = [("max_active", C.c_int), ("host_workers", C.c_int),
+                ("mem_budget_bytes", C.c_size_t)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int), ("done", C.c_int), ("t_submit", C.c_double),
+                ("t_start", C.c_double), ("t_end", C.c_double), ("info", Info)]
+
+
+_lib = None
+
+
+def load(path: str = LIBPATH):
+    """Load libbks.so; raises if it is missing (build it with build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run paper_2012_07595_amd/build.py")
+    lib = C.CDLL(path)
+    vp, i64, i32p = C.c_void_p, C.c_int64, C.POINTER(C.c_int32)
+    lib.bks_ctx_create.argtypes = [C.c_int, C.c_size_t, C.POINTER(vp)]
+    lib.bks_ctx_destroy.argtypes = [vp]
+    lib.bks_ctx_destroy.restype = None
+    lib.bks_last_error.argtypes = [vp]
+    lib.bks_last_error.restype = C.c_char_p
+    lib.bks_version.restype = C.c_char_p
+    lib.bks_tensor_upload.argtypes = [vp, i64, i64, i64, vp, vp, vp, vp, C.c_int, C.c_uint,
+                                      C.POINTER(vp)]
+    lib.bks_tensor_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64),
+                                    C.POINTER(i64), C.POINTER(C.c_double), C.POINTER(C.c_size_t)]
+    lib.bks_tensor_pairs.argtypes = [vp, i32p, i32p]
+    lib.bks_tensor_free.argtypes = [vp]
+    lib.bks_tensor_free.restype = None
+    lib.bks_ttmc.argtypes = [vp, vp, C.c_int, vp, i64, C.c_int, vp, i64, C.c_int, C.c_int,
+                             C.c_int, vp, i64, vp]
+    lib.bks_solve.argtypes = [vp, vp, C.POINTER(Params), vp, vp, vp, C.POINTER(Info)]
+    lib.hooi_solve.argtypes = [vp, vp, C.POINTER(HooiParams), vp, vp, vp, C.POINTER(Info)]
+    lib.bks_server_create.argtypes = [vp, C.POINTER(ServerParams), C.POINTER(vp)]
+    lib.bks_server_submit.argtypes = [vp, vp, C.POINTER(Params), vp, vp, vp, C.POINTER(C.c_uint64)]
+    lib.bks_server_submit_coo.argtypes = [vp, i64, i64, i64, vp, vp, vp, vp, C.POINTER(Params),
+                                          vp, vp, vp, C.POINTER(C.c_uint64)]
+    lib.bks_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(Result)]
+    lib.bks_server_wait.argtypes = [vp, C.c_uint64, C.POINTER(Result)]
+    lib.bks_server_now.argtypes = [vp]
+    lib.bks_server_now.restype = C.c_double
+    lib.bks_server_destroy.argtypes = [vp]
+    lib.bks_server_destroy.restype = None
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    """Raw pointer of a numpy array or torch tensor (no copy)."""
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return C.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Ctx:
+    def __init__(self, device: int = 0, mem_budget: int = 0):
+        self.lib = load()
+        h = C.c_void_p()
+        rc = self.lib.bks_ctx_create(device, mem_budget, C.byref(h))
+        if rc != OK:
+            raise BksError(rc, "bks_ctx_create failed")
+        self.h = h
+
+    def check(self, rc):
+        if rc < 0:
+            raise BksError(rc, self.lib.bks_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        if self.h:
+            self.lib.bks_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def upload(self, m, n, i, j, k, val, flags=0):
+        """Upload host coordinates (numpy int32 arrays, float32/float64 values)."""
+        i = np.ascontiguousarray(i, dtype=np.int32)
+        j = np.ascontiguousarray(j, dtype=np.int32)
+        k = np.ascontiguousarray(k, dtype=np.int32)
+        val = np.ascontiguousarray(val)
+        dt = F64 if val.dtype == np.float64 else F32
+        if dt == F32:
+            val = np.ascontiguousarray(val, dtype=np.float32)
+        h = C.c_void_p()
+        self.check(self.lib.bks_tensor_upload(self.h, m, n, int(i.shape[0]), _ptr(i), _ptr(j),
+                                              _ptr(k), _ptr(val), dt, flags, C.byref(h)))
+        return Tensor(self, h)
+
+    def upload_coo(self, coo, flags=0):
+        return self.upload(coo.m, coo.n, coo.i, coo.j, coo.k, coo.val, flags)
+
+    def ttmc(self, t, op, B1, B2, out, sym_half=False, prec=F32, stream=None):
+        """out <- product; B1, B2, out are 2-D row-major device tensors."""
+        p1 = B1.shape[1] if B1 is not None else 0
+        ld1 = B1.stride(0) if B1 is not None else 0
+        p2 = B2.shape[1] if B2 is not None else 0
+        ld2 = B2.stride(0) if B2 is not None else 0
+        s = C.c_void_p(stream) if stream else None
+        self.check(self.lib.bks_ttmc(self.h, t.h, op, _ptr(B1), ld1, p1, _ptr(B2), ld2, p2,
+                                     1 if sym_half else 0, prec, _ptr(out), out.stride(0), s))
+
+    def solve(self, t, r, r3, U0=None, W0=None, p=4, s=2, variant="bk", precision=PREC_FP64,
+              tol=0.0, inner_tol=0.0, max_outer=0, hooi_warm=-1, ng_max=0, seed=0):
+        """bks_solve: returns (U, W, F, info, status)."""
+        m, n = t.m, t.n
+        keep = []
+        prm = Params(r, r3, s, p, VARIANT[variant], precision, tol, inner_tol, max_outer,
+                     hooi_warm, ng_max, None, None, seed)
+        if U0 is not None:
+            u = np.asfortranarray(U0, dtype=np.float64)
+            w = np.asfortranarray(W0, dtype=np.float64)
+            keep += [u, w]
+            prm.U0 = u.ctypes.data
+            prm.W0 = w.ctypes.data
+        U = np.zeros((m, r), order="F")
+        W = np.zeros((n, r3), order="F")
+        F = np.zeros((r, r, r3), order="F")
+        info = Info()
+        rc = self.check(self.lib.bks_solve(self.h, t.h, C.byref(prm), _ptr(U), _ptr(W), _ptr(F),
+                                           C.byref(info)))
+        return U, W, F, info, rc
+
+    def hooi(self, t, r, r3, U0=None, W0=None, precision=PREC_FP64, tol=0.0, max_iter=0,
+             grad_every=0, seed=0):
+        m, n = t.m, t.n
+        prm = HooiParams(r, r3, precision, tol, max_iter, grad_every, None, None, seed)
+        keep = []
+        if U0 is not None:
+            u = np.asfortranarray(U0, dtype=np.float64)
+            w = np.asfortranarray(W0, dtype=np.float64)
+            keep += [u, w]
+            prm.U0 = u.ctypes.data
+            prm.W0 = w.ctypes.data
+        U = np.zeros((m, r), order="F")
+        W = np.zeros((n, r3), order="F")
+        F = np.zeros((r, r, r3), order="F")
+        info = Info()
+        rc = self.check(self.lib.hooi_solve(self.h, t.h, C.byref(prm), _ptr(U), _ptr(W), _ptr(F),
+                                            C.byref(info)))
+        return U, W, F, info, rc
+
+
+class Tensor:
+    def __init__(self, ctx: Ctx, h):
+        self.ctx = ctx
+        self.h = h
+        m, n, nnz, npairs = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        fro = C.c_double()
+        db = C.c_size_t()
+        ctx.lib.bks_tensor_info(h, C.byref(m), C.byref(n), C.byref(nnz), C.byref(npairs),
+                                C.byref(fro), C.byref(db))
+        self.m, self.n, self.nnz, self.npairs = m.value, n.value, nnz.value, npairs.value
+        self.frob = fro.value
+        self.dev_bytes = db.value
+
+    def pairs(self):
+        pi = np.zeros(self.npairs, np.int32)
+        pj = np.zeros(self.npairs, np.int32)
+        self.ctx.check(self.ctx.lib.bks_tensor_pairs(self.h, pi.ctypes.data_as(C.POINTER(C.c_int32)),
+                                                     pj.ctypes.data_as(C.POINTER(C.c_int32))))
+        return pi, pj
+
+    def free(self):
+        if self.h:
+            self.ctx.lib.bks_tensor_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

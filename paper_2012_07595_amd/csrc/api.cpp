@@ -1,0 +1,194 @@
+// C ABI entry points of libbks: context, tensor upload, tensor-times-block
+// products.  Solver and server entry points live in solver.cpp / server.cpp.
+#include <cstring>
+#include <new>
+
+#include "bks_internal.h"
+
+namespace bks {
+
+void fail(int code, const std::string &msg) { throw Error{code, msg}; }
+
+void check_hip(hipError_t e, const char *what) {
+    if (e == hipSuccess) return;
+    if (e == hipErrorOutOfMemory) fail(BKS_ENOMEM, std::string("out of device memory: ") + what);
+    fail(BKS_EDEVICE, std::string(hipGetErrorString(e)) + " in " + what);
+}
+
+DevBuf::~DevBuf() { release(); }
+
+void DevBuf::alloc(size_t b) {
+    release();
+    if (b == 0) return;
+    if (const char *f = std::getenv("BKS_FAIL_NEXT_ALLOC")) {
+        if (f[0] == '1') {
+            unsetenv("BKS_FAIL_NEXT_ALLOC");
+            fail(BKS_ENOMEM, "injected allocation failure");
+        }
+    }
+    hipError_t e = hipMalloc(&ptr, b);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        (void)hipGetLastError();
+        fail(BKS_ENOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed");
+    }
+    bytes = b;
+}
+
+void DevBuf::ensure(size_t b) {
+    if (b <= bytes) return;
+    alloc(b + b / 4);
+}
+
+void DevBuf::release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+}  // namespace bks
+
+using namespace bks;
+
+struct bks_ctx_s : public Ctx {};
+struct bks_tensor_s : public Tensor {};
+
+namespace {
+
+template <class F>
+int guard(Ctx *c, F f) {
+    try {
+        f();
+        return BKS_OK;
+    } catch (const Error &e) {
+        if (c) c->last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        if (c) c->last_error = "host allocation failed";
+        return BKS_ENOMEM;
+    } catch (const std::exception &e) {
+        if (c) c->last_error = e.what();
+        return BKS_EDEVICE;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *bks_version(void) { return "libbks 0.1 (gfx950)"; }
+
+int bks_ctx_create(int device, size_t mem_budget_bytes, bks_ctx *out) {
+    if (!out) return BKS_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+        (void)hipGetLastError();
+        return BKS_EDEVICE;
+    }
+    if (device < 0 || device >= ndev) return BKS_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return BKS_EDEVICE;
+    auto *c = new (std::nothrow) bks_ctx_s();
+    if (!c) return BKS_ENOMEM;
+    c->device = device;
+    c->budget = mem_budget_bytes;
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return BKS_EDEVICE;
+    }
+    *out = c;
+    return BKS_OK;
+}
+
+void bks_ctx_destroy(bks_ctx ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+const char *bks_last_error(bks_ctx ctx) {
+    if (!ctx) return "null context";
+    return ctx->last_error.c_str();
+}
+
+int bks_tensor_upload(bks_ctx ctx, int64_t m, int64_t n, int64_t nnz, const int32_t *i,
+                      const int32_t *j, const int32_t *k, const void *val, int val_dtype,
+                      unsigned flags, bks_tensor *out) {
+    if (!ctx || !out) return BKS_EINVAL;
+    *out = nullptr;
+    return guard(ctx, [&] {
+        if (m < 1 || n < 1 || nnz < 0) fail(BKS_EINVAL, "m, n must be >= 1 and nnz >= 0");
+        if (m > (int64_t)INT32_MAX || n > (int64_t)INT32_MAX) fail(BKS_EINVAL, "m or n too large");
+        if (val_dtype != BKS_F32 && val_dtype != BKS_F64) fail(BKS_EINVAL, "val_dtype");
+        if (nnz > 0 && (!i || !j || !k || !val)) fail(BKS_EINVAL, "null coordinate array");
+        HIPCHECK(hipSetDevice(ctx->device));
+        std::vector<int32_t> hi, hj, hk;
+        std::vector<char> hv;
+        const int32_t *I = i, *J = j, *K = k;
+        const void *V = val;
+        const size_t vb = val_dtype == BKS_F64 ? 8 : 4;
+        if (flags & BKS_DEVICE_PTRS) {
+            hi.resize(nnz); hj.resize(nnz); hk.resize(nnz); hv.resize(nnz * vb);
+            if (nnz) {
+                HIPCHECK(hipMemcpy(hi.data(), i, nnz * 4, hipMemcpyDeviceToHost));
+                HIPCHECK(hipMemcpy(hj.data(), j, nnz * 4, hipMemcpyDeviceToHost));
+                HIPCHECK(hipMemcpy(hk.data(), k, nnz * 4, hipMemcpyDeviceToHost));
+                HIPCHECK(hipMemcpy(hv.data(), val, nnz * vb, hipMemcpyDeviceToHost));
+            }
+            I = hi.data(); J = hj.data(); K = hk.data(); V = hv.data();
+        }
+        auto t = std::make_unique<bks_tensor_s>();
+        t->ctx = ctx;
+        t->m = m;
+        t->n = n;
+        t->nnz = nnz;
+        build_formats(*t, I, J, K, V, val_dtype, flags);
+        if (ctx->budget && ctx->used + t->dev_bytes > ctx->budget)
+            fail(BKS_ENOMEM, "tensor exceeds the context memory budget");
+        ctx->used += t->dev_bytes;
+        *out = t.release();
+    });
+}
+
+int bks_tensor_info(bks_tensor t, int64_t *m, int64_t *n, int64_t *nnz_stored, int64_t *npairs,
+                    double *frob_norm, size_t *dev_bytes) {
+    if (!t) return BKS_EINVAL;
+    if (m) *m = t->m;
+    if (n) *n = t->n;
+    if (nnz_stored) *nnz_stored = t->nnz;
+    if (npairs) *npairs = t->npairs;
+    if (frob_norm) *frob_norm = std::sqrt(t->frob2);
+    if (dev_bytes) *dev_bytes = t->dev_bytes;
+    return BKS_OK;
+}
+
+int bks_tensor_pairs(bks_tensor t, int32_t *pi, int32_t *pj) {
+    if (!t || !pi || !pj) return BKS_EINVAL;
+    std::memcpy(pi, t->pair_i.data(), t->pair_i.size() * 4);
+    std::memcpy(pj, t->pair_j.data(), t->pair_j.size() * 4);
+    return BKS_OK;
+}
+
+void bks_tensor_free(bks_tensor t) {
+    if (!t) return;
+    if (t->ctx) {
+        (void)hipSetDevice(t->ctx->device);
+        if (t->ctx->used >= t->dev_bytes) t->ctx->used -= t->dev_bytes;
+    }
+    delete t;
+}
+
+int bks_ttmc(bks_ctx ctx, bks_tensor t, int op, const void *B1, int64_t ld1, int p1,
+             const void *B2, int64_t ld2, int p2, int sym_half, int prec, void *out, int64_t ldo,
+             void *stream) {
+    if (!ctx || !t) return BKS_EINVAL;
+    return guard(ctx, [&] {
+        HIPCHECK(hipSetDevice(ctx->device));
+        ttmc(*ctx, *t, op, B1, ld1, p1, B2, ld2, p2, sym_half != 0, prec, out, ldo,
+             static_cast<hipStream_t>(stream));
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,147 @@
+// Internal declarations of libbks (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/bks.h"
+
+namespace bks {
+
+// ---------------------------------------------------------------- errors
+struct Error {
+    int code;
+    std::string msg;
+};
+[[noreturn]] void fail(int code, const std::string &msg);
+void check_hip(hipError_t e, const char *what);
+#define HIPCHECK(x) ::bks::check_hip((x), #x)
+
+// ---------------------------------------------------------------- device memory
+// A device buffer owned by the library.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf();
+    void alloc(size_t b);
+    void ensure(size_t b);  // grow-only
+    void release();
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+// ---------------------------------------------------------------- formats
+// A segmented entry stream: segments (slices, rows or pairs) own contiguous
+// runs of entries; entry e carries two indices c1[e], c2[e] and a value.
+struct Segmented {
+    int64_t nseg = 0;
+    int64_t nent = 0;
+    DevBuf segptr;   // int64 [nseg + 1]
+    DevBuf c1;       // int32 [nent] (may be empty)
+    DevBuf c2;       // int32 [nent]
+    DevBuf v32;      // float [nent]
+    DevBuf v64;      // double [nent] (only for FP64-valued tensors)
+    std::vector<int64_t> h_segptr;  // host copy for schedule building
+};
+
+// One wave-sized unit of work.  Heavy items cover [beg, end) of a single
+// long segment; light items cover whole short segments seg .. seg_end-1.
+struct Item {
+    int32_t seg;
+    int32_t seg_end;  // light: one past the last segment; heavy: -1
+    int64_t beg, end; // heavy entry range
+    int32_t slot;     // heavy split segment: partial slot, else -1
+    int32_t pad;
+};
+
+struct Fixup {
+    int32_t seg;
+    int32_t first_slot;
+    int32_t nslots;
+    int32_t pad;
+};
+
+struct Schedule {
+    int64_t nitems = 0;
+    int64_t nfix = 0;
+    int64_t nslots = 0;
+    DevBuf items;  // Item[nitems]
+    DevBuf fix;    // Fixup[nfix]
+};
+
+struct Tensor;
+
+struct Ctx {
+    int device = 0;
+    size_t budget = 0;
+    size_t used = 0;
+    std::string last_error;
+    hipStream_t stream = nullptr;   // ctx-owned stream for solver work
+    DevBuf ws_partial;              // TTMc partial rows
+    DevBuf ws_pack1, ws_pack2;      // packed factor copies
+    std::mutex mu;
+};
+
+struct Tensor {
+    Ctx *ctx = nullptr;
+    int64_t m = 0, n = 0, nnz = 0, npairs = 0;
+    bool has64 = false;
+    double frob2 = 0.0;
+    size_t dev_bytes = 0;
+    Segmented o3;    // slices k: entries (i, j) with i <= j          (FREE3)
+    Segmented o1;    // rows r: entries (col, k), both orientations   (FREE1)
+    Segmented op;    // pairs (i <= j): entries (-, k)                (MODE3)
+    std::vector<int32_t> pair_i, pair_j;
+    std::mutex sched_mu;
+    std::map<std::pair<int, int>, std::unique_ptr<Schedule>> sched;  // (order, E) -> schedule
+    const Schedule &schedule(int order, int E);
+};
+
+// Build formats from host COO (validated, canonicalised).  Throws Error.
+void build_formats(Tensor &t, const int32_t *i, const int32_t *j, const int32_t *k,
+                   const void *val, int val_dtype, unsigned flags);
+
+// Schedules: heavy items take CH = E * kHeavySteps entries; light segments
+// are at most kLightMax entries long.
+constexpr int kHeavySteps = 32;
+constexpr int kLightMax = 48;
+void build_schedule(const std::vector<int64_t> &segptr, int E, std::vector<Item> &items,
+                    std::vector<Fixup> &fix, int64_t &nslots);
+
+// ---------------------------------------------------------------- TTMc
+// Launch a TTMc on device buffers; dtype of B/out follows prec.
+void ttmc(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, int p1, const void *B2,
+          int64_t ld2, int p2, bool sym_half, int prec, void *out, int64_t ldo,
+          hipStream_t s);
+
+// ---------------------------------------------------------------- dense kernels (dense.hip)
+// out(k x q, ldo) = A^T B with A (rows x k, lda), B (rows x q, ldb); FP64 out.
+void gemm_tn_f64(const double *A, int64_t lda, const double *B, int64_t ldb, int64_t rows,
+                 int k, int q, double *out, int64_t ldo, Ctx &c, hipStream_t s);
+void gemm_tn_f32f64(const double *A, int64_t lda, const float *B, int64_t ldb, int64_t rows,
+                    int k, int q, double *out, int64_t ldo, Ctx &c, hipStream_t s);
+// C(rows x q, ldc) = beta*C + alpha * A(rows x k, lda) H(k x q, ldh)
+void gemm_nn_f64(const double *A, int64_t lda, const double *H, int64_t ldh, int64_t rows,
+                 int k, int q, double alpha, double beta, double *C, int64_t ldc, hipStream_t s);
+// G (q x q, double-double hi/lo, upper triangle) = B^T B, B rows x q (ldb)
+void gram_dd(const double *B, int64_t ldb, int64_t rows, int q, double *Ghi, double *Glo,
+             Ctx &c, hipStream_t s);
+// column squared norms (FP64)
+void colnorm2(const double *B, int64_t ldb, int64_t rows, int q, double *out, Ctx &c,
+              hipStream_t s);
+void convert_f64_f32(const double *src, int64_t lds, float *dst, int64_t ldd, int64_t rows,
+                     int cols, hipStream_t s);
+void convert_f32_f64(const float *src, int64_t lds, double *dst, int64_t ldd, int64_t rows,
+                     int cols, hipStream_t s);
+void copy2d_f64(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t rows,
+                int cols, hipStream_t s);
+
+}  // namespace bks

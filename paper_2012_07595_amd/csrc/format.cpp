@@ -1,0 +1,356 @@
+// Host-side build of the device formats of a (1,2)-symmetric tensor.
+//
+// A (1,2)-symmetric tensor (Definition in Section 2.1) is stored once per
+// (i <= j, k) position.  The paper reorganises its sparse tensor before every
+// product (Section 3.3, discussion of block-Krylov methods; Section 5.2.5); here
+// the reorganisation is paid once at upload, into three sorted segmented
+// streams:
+//   o3: slice-major (k, i, j) -- A.(X, Y)_{1,2} reduces within a slice
+//   o1: row-major (r, c, k) over both orientations -- A.(Y, Z)_{2,3}
+//       reduces within a row without atomics
+//   op: the stored pair pattern (i <= j) with its k-fibres -- A.(Z)_3
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <thread>
+
+#include "bks_internal.h"
+
+namespace bks {
+
+namespace {
+
+struct KV {
+    uint64_t key;
+    uint64_t idx;
+};
+
+unsigned nthreads() {
+    unsigned h = std::thread::hardware_concurrency();
+    if (h == 0) h = 4;
+    return std::min(h, 16u);
+}
+
+template <class F>
+void parallel_for(int64_t n, F f) {
+    unsigned T = nthreads();
+    if (n < 65536 || T == 1) {
+        f(0, n, 0);
+        return;
+    }
+    std::vector<std::thread> th;
+    int64_t chunk = (n + T - 1) / T;
+    for (unsigned t = 0; t < T; ++t) {
+        int64_t b = t * chunk, e = std::min<int64_t>(n, b + chunk);
+        if (b >= e) break;
+        th.emplace_back(f, b, e, (int)t);
+    }
+    for (auto &x : th) x.join();
+}
+
+// LSD radix sort of (key, idx) by key, 11-bit digits, multithreaded
+// histogram/scatter per pass.  Stable.
+void radix_sort(std::vector<KV> &a, int key_bits) {
+    const int D = 11, B = 1 << D;
+    std::vector<KV> tmp(a.size());
+    unsigned T = nthreads();
+    int64_t n = (int64_t)a.size();
+    if (n < 65536) T = 1;
+    int64_t chunk = (n + T - 1) / T;
+    std::vector<int64_t> hist((size_t)T * B);
+    for (int shift = 0; shift < key_bits; shift += D) {
+        std::fill(hist.begin(), hist.end(), 0);
+        auto count = [&](unsigned t) {
+            int64_t b = t * chunk, e = std::min<int64_t>(n, b + chunk);
+            int64_t *h = &hist[(size_t)t * B];
+            for (int64_t x = b; x < e; ++x) h[(a[x].key >> shift) & (B - 1)]++;
+        };
+        {
+            std::vector<std::thread> th;
+            for (unsigned t = 1; t < T; ++t) th.emplace_back(count, t);
+            count(0);
+            for (auto &x : th) x.join();
+        }
+        // exclusive prefix over (digit, thread)
+        int64_t run = 0;
+        for (int d = 0; d < B; ++d)
+            for (unsigned t = 0; t < T; ++t) {
+                int64_t c = hist[(size_t)t * B + d];
+                hist[(size_t)t * B + d] = run;
+                run += c;
+            }
+        auto scatter = [&](unsigned t) {
+            int64_t b = t * chunk, e = std::min<int64_t>(n, b + chunk);
+            int64_t *h = &hist[(size_t)t * B];
+            for (int64_t x = b; x < e; ++x) tmp[h[(a[x].key >> shift) & (B - 1)]++] = a[x];
+        };
+        {
+            std::vector<std::thread> th;
+            for (unsigned t = 1; t < T; ++t) th.emplace_back(scatter, t);
+            scatter(0);
+            for (auto &x : th) x.join();
+        }
+        a.swap(tmp);
+    }
+}
+
+int bits_for(uint64_t maxv) {
+    int b = 1;
+    while (b < 64 && (maxv >> b) != 0) ++b;
+    return b;
+}
+
+void upload(DevBuf &d, const void *h, size_t bytes) {
+    if (bytes == 0) return;
+    d.alloc(bytes);
+    HIPCHECK(hipMemcpy(d.ptr, h, bytes, hipMemcpyHostToDevice));
+}
+
+}  // namespace
+
+void build_formats(Tensor &t, const int32_t *I, const int32_t *J, const int32_t *K,
+                   const void *val, int val_dtype, unsigned flags) {
+    const int64_t m = t.m, n = t.n, nnz = t.nnz;
+    const bool f64 = (val_dtype == BKS_F64);
+    const float *v32in = static_cast<const float *>(val);
+    const double *v64in = static_cast<const double *>(val);
+    auto value = [&](int64_t e) -> double { return f64 ? v64in[e] : (double)v32in[e]; };
+
+    // 1. validate, canonicalise, key = ((k*m + lo)*m + hi) << 1 | orientation
+    std::vector<KV> a((size_t)nnz);
+    std::atomic<int> bad{0};
+    parallel_for(nnz, [&](int64_t b, int64_t e, int) {
+        for (int64_t x = b; x < e; ++x) {
+            int64_t i = I[x], j = J[x], k = K[x];
+            if (i < 0 || j < 0 || k < 0 || i >= m || j >= m || k >= n) {
+                bad.store(1);
+                continue;
+            }
+            if (!std::isfinite(value(x))) {
+                int z = 0;
+                bad.compare_exchange_strong(z, 2);
+                continue;
+            }
+            int64_t lo = std::min(i, j), hi = std::max(i, j);
+            uint64_t orient = (flags & BKS_FULL_SYMMETRIC) && (i > j) ? 1u : 0u;
+            a[(size_t)x].key = ((((uint64_t)k * m + lo) * m + hi) << 1) | orient;
+            a[(size_t)x].idx = (uint64_t)x;
+        }
+    });
+    if (bad.load() == 1) fail(BKS_EINDEX, "coordinate out of range");
+    if (bad.load() == 2) fail(BKS_EVALUE, "non-finite value");
+    int kb = bits_for((((uint64_t)n * m) * m) << 1);
+    radix_sort(a, kb);
+
+    // 2. merge repeated canonical positions
+    std::vector<int64_t> si, sj, sk;
+    std::vector<double> sv;
+    si.reserve(nnz); sj.reserve(nnz); sk.reserve(nnz); sv.reserve(nnz);
+    int64_t x = 0;
+    while (x < nnz) {
+        uint64_t canon = a[x].key >> 1;
+        double s0 = 0.0, s1 = 0.0;
+        int c0 = 0, c1 = 0;
+        int64_t y = x;
+        while (y < nnz && (a[y].key >> 1) == canon) {
+            if (a[y].key & 1) { s1 += value((int64_t)a[y].idx); c1++; }
+            else { s0 += value((int64_t)a[y].idx); c0++; }
+            ++y;
+        }
+        int64_t hi = (int64_t)(canon % (uint64_t)m);
+        uint64_t rest = canon / (uint64_t)m;
+        int64_t lo = (int64_t)(rest % (uint64_t)m);
+        int64_t k = (int64_t)(rest / (uint64_t)m);
+        double v;
+        if (flags & BKS_FULL_SYMMETRIC) {
+            if (lo != hi) {
+                if (c0 > 1 || c1 > 1) {
+                    if (!(flags & BKS_SUM_DUPLICATES)) fail(BKS_EDUP, "repeated position");
+                }
+                if (c0 == 0 || c1 == 0 || std::fabs(s0 - s1) > 1e-12 * std::max(std::fabs(s0), std::fabs(s1)))
+                    fail(BKS_EASYM, "(i,j,k) and (j,i,k) values differ or one is missing");
+            } else if (c0 > 1 && !(flags & BKS_SUM_DUPLICATES)) {
+                fail(BKS_EDUP, "repeated position");
+            }
+            v = s0;
+        } else {
+            if (c0 > 1 && !(flags & BKS_SUM_DUPLICATES)) fail(BKS_EDUP, "repeated position");
+            v = s0;
+        }
+        si.push_back(lo); sj.push_back(hi); sk.push_back(k); sv.push_back(v);
+        x = y;
+    }
+    a.clear();
+    a.shrink_to_fit();
+    const int64_t S = (int64_t)sv.size();
+    t.nnz = S;
+    double f2 = 0.0;
+    for (int64_t e = 0; e < S; ++e) f2 += (si[e] == sj[e] ? 1.0 : 2.0) * sv[e] * sv[e];
+    t.frob2 = f2;
+    t.has64 = f64;
+
+    // 3. o3: already sorted by (k, i, j)
+    {
+        std::vector<int64_t> ptr(n + 1, 0);
+        for (int64_t e = 0; e < S; ++e) ptr[sk[e] + 1]++;
+        for (int64_t q = 0; q < n; ++q) ptr[q + 1] += ptr[q];
+        std::vector<int32_t> c1(S), c2(S);
+        std::vector<float> v32(S);
+        for (int64_t e = 0; e < S; ++e) {
+            c1[e] = (int32_t)si[e];
+            c2[e] = (int32_t)sj[e];
+            v32[e] = (float)sv[e];
+        }
+        Segmented &o = t.o3;
+        o.nseg = n;
+        o.nent = S;
+        upload(o.segptr, ptr.data(), ptr.size() * 8);
+        upload(o.c1, c1.data(), S * 4);
+        upload(o.c2, c2.data(), S * 4);
+        upload(o.v32, v32.data(), S * 4);
+        if (f64) upload(o.v64, sv.data(), S * 8);
+        o.h_segptr = std::move(ptr);
+    }
+
+    // 4. o1: both orientations sorted by (row, col, k); op from row <= col
+    {
+        int64_t off = 0;
+        for (int64_t e = 0; e < S; ++e) off += (si[e] != sj[e]);
+        const int64_t F = S + off;
+        std::vector<KV> b((size_t)F);
+        int64_t w = 0;
+        for (int64_t e = 0; e < S; ++e) {
+            b[w].key = ((uint64_t)si[e] * m + sj[e]) * n + sk[e];
+            b[w].idx = (uint64_t)e;
+            ++w;
+            if (si[e] != sj[e]) {
+                b[w].key = ((uint64_t)sj[e] * m + si[e]) * n + sk[e];
+                b[w].idx = (uint64_t)e;
+                ++w;
+            }
+        }
+        radix_sort(b, bits_for(((uint64_t)m * m) * n));
+        std::vector<int64_t> rptr(m + 1, 0);
+        std::vector<int32_t> c1(F), c2(F);
+        std::vector<float> v32(F);
+        std::vector<double> v64(f64 ? F : 0);
+        std::vector<int64_t> pptr;
+        std::vector<int32_t> pk;
+        std::vector<float> pv32;
+        std::vector<double> pv64;
+        t.pair_i.clear();
+        t.pair_j.clear();
+        pptr.push_back(0);
+        int64_t last_pair = -1;
+        for (int64_t q = 0; q < F; ++q) {
+            uint64_t key = b[q].key;
+            int64_t kk = (int64_t)(key % (uint64_t)n);
+            uint64_t rc = key / (uint64_t)n;
+            int64_t col = (int64_t)(rc % (uint64_t)m), row = (int64_t)(rc / (uint64_t)m);
+            double v = sv[b[q].idx];
+            rptr[row + 1]++;
+            c1[q] = (int32_t)col;
+            c2[q] = (int32_t)kk;
+            v32[q] = (float)v;
+            if (f64) v64[q] = v;
+            if (row <= col) {
+                int64_t pid = (int64_t)rc;
+                if (pid != last_pair) {
+                    if (last_pair >= 0) pptr.push_back((int64_t)pk.size());
+                    t.pair_i.push_back((int32_t)row);
+                    t.pair_j.push_back((int32_t)col);
+                    last_pair = pid;
+                }
+                pk.push_back((int32_t)kk);
+                pv32.push_back((float)v);
+                if (f64) pv64.push_back(v);
+            }
+        }
+        pptr.push_back((int64_t)pk.size());
+        if (S == 0) pptr.assign(1, 0);
+        for (int64_t r = 0; r < m; ++r) rptr[r + 1] += rptr[r];
+        Segmented &o = t.o1;
+        o.nseg = m;
+        o.nent = F;
+        upload(o.segptr, rptr.data(), rptr.size() * 8);
+        upload(o.c1, c1.data(), F * 4);
+        upload(o.c2, c2.data(), F * 4);
+        upload(o.v32, v32.data(), F * 4);
+        if (f64) upload(o.v64, v64.data(), F * 8);
+        o.h_segptr = std::move(rptr);
+        Segmented &p = t.op;
+        p.nseg = (int64_t)t.pair_i.size();
+        p.nent = (int64_t)pk.size();
+        t.npairs = p.nseg;
+        upload(p.segptr, pptr.data(), pptr.size() * 8);
+        upload(p.c2, pk.data(), pk.size() * 4);
+        upload(p.v32, pv32.data(), pv32.size() * 4);
+        if (f64) upload(p.v64, pv64.data(), pv64.size() * 8);
+        p.h_segptr = std::move(pptr);
+    }
+    auto bytes = [](const Segmented &o) {
+        return o.segptr.bytes + o.c1.bytes + o.c2.bytes + o.v32.bytes + o.v64.bytes;
+    };
+    t.dev_bytes = bytes(t.o3) + bytes(t.o1) + bytes(t.op);
+}
+
+void build_schedule(const std::vector<int64_t> &segptr, int E, std::vector<Item> &items,
+                    std::vector<Fixup> &fix, int64_t &nslots) {
+    const int64_t nseg = (int64_t)segptr.size() - 1;
+    const int64_t CH = (int64_t)E * kHeavySteps;
+    items.clear();
+    fix.clear();
+    nslots = 0;
+    int64_t s = 0;
+    while (s < nseg) {
+        int64_t len = segptr[s + 1] - segptr[s];
+        if (len > kLightMax) {
+            int64_t nch = (len + CH - 1) / CH;
+            if (nch == 1) {
+                items.push_back({(int32_t)s, -1, segptr[s], segptr[s + 1], -1, 0});
+            } else {
+                fix.push_back({(int32_t)s, (int32_t)nslots, (int32_t)nch, 0});
+                for (int64_t c = 0; c < nch; ++c) {
+                    int64_t b = segptr[s] + c * CH, e = std::min(segptr[s + 1], b + CH);
+                    items.push_back({(int32_t)s, -1, b, e, (int32_t)(nslots + c), 0});
+                }
+                nslots += nch;
+            }
+            ++s;
+        } else {
+            int64_t s0 = s;
+            while (s < nseg && s - s0 < E && segptr[s + 1] - segptr[s] <= kLightMax) ++s;
+            items.push_back({(int32_t)s0, (int32_t)s, 0, 0, -1, 0});
+        }
+    }
+}
+
+const Schedule &Tensor::schedule(int order, int E) {
+    std::lock_guard<std::mutex> g(sched_mu);
+    auto key = std::make_pair(order, E);
+    auto it = sched.find(key);
+    if (it != sched.end()) return *it->second;
+    const Segmented &o = order == 0 ? o3 : (order == 1 ? o1 : op);
+    std::vector<Item> items;
+    std::vector<Fixup> fx;
+    auto sc = std::make_unique<Schedule>();
+    build_schedule(o.h_segptr, E, items, fx, sc->nslots);
+    sc->nitems = (int64_t)items.size();
+    sc->nfix = (int64_t)fx.size();
+    if (!items.empty()) {
+        sc->items.alloc(items.size() * sizeof(Item));
+        HIPCHECK(hipMemcpy(sc->items.ptr, items.data(), items.size() * sizeof(Item),
+                           hipMemcpyHostToDevice));
+    }
+    if (!fx.empty()) {
+        sc->fix.alloc(fx.size() * sizeof(Fixup));
+        HIPCHECK(hipMemcpy(sc->fix.ptr, fx.data(), fx.size() * sizeof(Fixup),
+                           hipMemcpyHostToDevice));
+    }
+    auto &ref = *sc;
+    sched[key] = std::move(sc);
+    return ref;
+}
+
+}  // namespace bks
