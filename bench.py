@@ -1,0 +1,234 @@
+#!/usr/bin/env python3
+"""Benchmark: served-style BKS solves on one MI355X.
+
+One step = one mixed-precision block Krylov-Schur solve (Algorithm 5,
+BKS(2,4; k1, k3), rank (5,5,5)) of the C2-shaped workload to the solver's
+tolerance, from a fixed seeded start, with the tensor already resident in
+HBM.  `value` = solves/s over the K timed steps; p50/p99 are per-solve
+latencies.  The roofline object reports the dominant tensor-product kernel
+class, timed live with HIP events on the stream it runs on.  The CPU
+baseline is the FP64 NumPy oracle timed on one outer iteration of the same
+workload and scaled by the GPU's outer-iteration count.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py --ttmc-sweep      # C3-shaped product sweep (one JSON line per product)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2012_07595_amd import bks, workloads  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+
+
+def dist(Ua, Ub):
+    Qa = np.linalg.qr(Ua)[0]
+    Qb = np.linalg.qr(Ub)[0]
+    return float(np.linalg.norm(Qb - Qa @ (Qa.T @ Qb), 2))
+
+
+def roofline_of(stats):
+    """Dominant kernel class (by total event time) and its roofline."""
+    if not stats:
+        return None
+    name, (calls, ms, by, fl) = max(stats.items(), key=lambda kv: kv[1][1])
+    avg_s = ms / calls / 1e3
+    if name.startswith("free3_sym_wide"):
+        peak = FP32_PEAK_TFLOPS if name.endswith("_f32") else FP64_PEAK_TFLOPS
+        ach = fl / calls / avg_s / 1e12
+        return {"kernel": "ttmc_" + name, "bound": "alu", "achieved": round(ach, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": None,
+                "launches": calls, "avg_launch_us": round(avg_s * 1e6, 2),
+                "algorithmic_flops_per_launch": fl / calls}
+    ach = by / calls / avg_s / 1e9
+    return {"kernel": "ttmc_" + name, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "launches": calls, "avg_launch_us": round(avg_s * 1e6, 2),
+            "algorithmic_bytes_per_launch": by / calls}
+
+
+def cpu_baseline(coo, r, U0, W0, gpu_iters):
+    """The FP64 oracle, one outer iteration of BKS on the same workload
+    (initial expansion, core, inner solve, restart, BK step), one thread."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_limits = None
+    from oracle import bk, bks as obks, core, sptensor
+    from oracle.orth import orthonormalize
+    T = sptensor.from_coo(coo.m, coo.n, coo.i, coo.j, coo.k, coo.val.astype(np.float64))
+    ctxm = threadpool_limits(limits=1) if threadpool_limits else None
+    t0 = time.perf_counter()
+    basis = bk.Basis(orthonormalize(U0), orthonormalize(W0))
+    for st in (1, 2):
+        bk.run_stage(T, basis, "bk", st, 4)
+    C = obks.core_tensor(T, basis.X, basis.Z)
+    P, S, _ = core.inner_solve(C, r, r, 1e-13)
+    U1 = orthonormalize(basis.X @ P)
+    W1 = orthonormalize(basis.Z @ S)
+    obks.bk_step(T, U1, W1)
+    dt = time.perf_counter() - t0
+    if ctxm is not None:
+        ctxm.unregister() if hasattr(ctxm, "unregister") else None
+    return {"value": round(1.0 / (dt * max(gpu_iters, 1)), 6), "unit": "solves/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"one outer BKS iteration of the same workload on the FP64 NumPy oracle "
+                      f"({dt:.1f} s, 1 BLAS thread), scaled by the GPU solve's {gpu_iters} outer "
+                      f"iterations"}
+
+
+def run_bks(args):
+    import torch
+    rank = 5
+    t_gen = time.perf_counter()
+    coo = workloads.c2_planted() if args.workload == "c2p" else workloads.c2()
+    U0, W0 = workloads.random_start(coo.m, coo.n, rank, rank, 2024)
+    t_gen = time.perf_counter() - t_gen
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    ctx = bks.Ctx(0)
+    t = ctx.upload_coo(coo)
+    kw = dict(U0=U0, W0=W0, p=4, s=2, max_outer=args.max_outer)
+    # FP64 GPU solve as the accuracy reference (untimed)
+    Ur, Wr, Fr, info_r, rc_r = ctx.solve(t, rank, rank, precision=bks.PREC_FP64, **kw)
+    for _ in range(args.warmup):
+        ctx.solve(t, rank, rank, precision=bks.PREC_MIXED, **kw)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    lat = []
+    results = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        a = time.perf_counter()
+        res = ctx.solve(t, rank, rank, precision=bks.PREC_MIXED, **kw)
+        lat.append(time.perf_counter() - a)
+        results.append(res)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stats = ctx.profile_read()
+    ctx.profile(False)
+    U, W, F, info, rc = results[0]
+    iters = info.outer_iters
+    out = {
+        "metric": "BKS solves/s + p50/p99 latency at 1e-8 subspace angle; TTMc HBM GB/s vs peak",
+        "value": round(args.steps / elapsed, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 products + f64 orthogonalisation/inner solve (mixed)",
+        "data": "synthetic",
+        "config": {
+            "workload": ("C2-shaped (1,2)-symmetric 20000x20000x2000, 2e6 stored, Zipf(1.3) modes 1-2, "
+                         "uniform mode 3, |N(0,1)| FP32" +
+                         (" + planted rank-(5,5,5)" if args.workload == "c2p" else "")),
+            "rank": [rank, rank, rank], "method": f"BKS(2,4;{info.k1},{info.k3})",
+            "precision": "mixed", "tol": 1e-11, "max_outer": args.max_outer,
+        },
+        "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 2),
+        "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 2),
+        "converged": bool(info.converged),
+        "outer_iters": iters,
+        "rel_grad": info.rel_grad,
+        "angle_U_vs_fp64": dist(Ur, U),
+        "angle_W_vs_fp64": dist(Wr, W),
+        "fp64_converged": bool(info_r.converged),
+        "fp64_outer_iters": info_r.outer_iters,
+        "phase_s": {"expand": round(info.t_expand, 4), "core": round(info.t_core, 4),
+                    "inner_host": round(info.t_inner, 4), "bk_step": round(info.t_step, 4)},
+        "svals1": list(np.round(info.svals1[:rank + 1], 4)),
+        "svals3": list(np.round(info.svals3[:rank + 1], 4)),
+        "kernels": {k: {"calls": v[0], "ms": round(v[1], 3)} for k, v in stats.items()},
+        "roofline": roofline_of(stats),
+        "gen_s": round(t_gen, 2),
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(coo, rank, U0, W0, iters)
+    print(json.dumps(out), flush=True)
+
+
+def ttmc_sweep(args):
+    """C3-shaped standalone products (one JSON line each)."""
+    import torch
+    t_gen = time.perf_counter()
+    coo = workloads.c3()
+    print(json.dumps({"stage": "generated", "seconds": round(time.perf_counter() - t_gen, 1)}), flush=True)
+    ctx = bks.Ctx(0)
+    t0 = time.perf_counter()
+    t = ctx.upload_coo(coo)
+    print(json.dumps({"stage": "uploaded", "seconds": round(time.perf_counter() - t0, 1),
+                      "dev_bytes": t.dev_bytes, "pairs": t.npairs}), flush=True)
+    del coo
+    dev = "cuda:0"
+    cases = []
+    for p in args.widths:
+        cases += [("free3_sym", p, p), ("free3", p, p), ("free1", p, p), ("mode3", 0, p)]
+    for name, p1, p2 in cases:
+        X = torch.randn(t.m, max(p1, 1), device=dev, dtype=torch.float32)
+        Y = torch.randn(t.m, max(p1, 1), device=dev, dtype=torch.float32)
+        Z = torch.randn(t.n, p2, device=dev, dtype=torch.float32)
+        if name == "free3_sym":
+            out = torch.empty(t.n, p1 * (p1 + 1) // 2, device=dev)
+            call = lambda: ctx.ttmc(t, bks.FREE3, X, None, out, sym_half=True)
+        elif name == "free3":
+            Y2 = torch.randn(t.m, p2, device=dev)
+            out = torch.empty(t.n, p1 * p2, device=dev)
+            call = lambda: ctx.ttmc(t, bks.FREE3, X, Y2, out)
+        elif name == "free1":
+            out = torch.empty(t.m, p1 * p2, device=dev)
+            call = lambda: ctx.ttmc(t, bks.FREE1, Y, Z, out)
+        else:
+            out = torch.empty(t.npairs, p2, device=dev)
+            call = lambda: ctx.ttmc(t, bks.MODE3, None, Z, out)
+        for _ in range(3):
+            call()
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        for _ in range(args.steps):
+            call()
+        torch.cuda.synchronize()
+        st = ctx.profile_read()
+        ctx.profile(False)
+        rl = roofline_of(st)
+        print(json.dumps({"op": name, "p": p2, "roofline": rl}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["c2p", "c2"], default="c2p")
+    ap.add_argument("--max-outer", type=int, default=200)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--ttmc-sweep", action="store_true")
+    ap.add_argument("--widths", type=int, nargs="*", default=[5, 10, 20])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              "(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+    if args.ttmc_sweep:
+        ttmc_sweep(args)
+    else:
+        run_bks(args)
+
+
+if __name__ == "__main__":
+    main()

@@ -84,6 +84,18 @@ const char *bks_last_error(bks_ctx ctx);
 /* Library version string. */
 const char *bks_version(void);
 
+/* Kernel timing on ctx: with enable = 1 every tensor-times-block launch made
+ * through ctx (bks_ttmc and the solvers) is bracketed by HIP events on the
+ * stream it runs on; statistics are reset.  enable = 0 stops recording. */
+int bks_ctx_profile(bks_ctx ctx, int enable);
+/* Read profile entry `idx` (0-based; BKS_ENOTFOUND past the end): kernel
+ * class name, launches, total milliseconds (from the events), and the
+ * algorithmic bytes and flops summed over those launches (the stored tensor
+ * read once, factors read once, output written once; 2 flops per FMA).
+ * Synchronises the recorded streams. */
+int bks_ctx_profile_read(bks_ctx ctx, int idx, char *name, int name_len, int64_t *calls,
+                         double *ms, double *bytes, double *flops);
+
 /* Upload a (1,2)-symmetric tensor given as coordinates (Definition of a
  * (1,2)-symmetric tensor, Section 2.1).  Each entry (i, j, k, val) names the
  * positions (i,j,k) and (j,i,k) of A; (i,j) is canonicalised to
@@ -144,6 +156,9 @@ typedef struct {
     const double *U0;   /* optional host start, m x r column-major (orthonormalised here) */
     const double *W0;   /* optional host start, n x r3 column-major */
     uint64_t seed;      /* start drawn from this seed when U0/W0 are NULL */
+    int inner_start;    /* 0: HOSVD + HOOI warm-up (Section 5.2); 1: the current
+                           point (the restart point is the projected problem's
+                           leading coordinates) */
 } bks_params;
 
 typedef struct {

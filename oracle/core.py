@@ -174,11 +174,18 @@ def retract(Q, D):
 
 def newton_grassmann(C, P, S, tol, maxit):
     """Newton-Grassmann iterations from (P, S) until the relative local
-    gradient is <= tol.  Returns (P, S, iterations, rel, newton_steps)."""
+    gradient is <= tol.  Returns (P, S, iterations, rel, newton_steps).
+
+    Safeguard (a reading; the paper only cites the method): the step solves
+    (-2A + mu I) d = b with mu = 0 when -2A is positive definite and the
+    step increases g (the plain Newton step near a maximum); otherwise mu is
+    raised (to beyond the most negative eigenvalue of -2A, then by factors
+    of 4) until both hold.  After 40 failed shifts one HOOI step is taken."""
     r, r3 = P.shape[1], S.shape[1]
     it = 0
     newton = 0
     rel = np.inf
+    mu = 0.0
     while True:
         bl = blocks(C, P, S)
         _, _, rel = local_gradient(bl)
@@ -186,20 +193,32 @@ def newton_grassmann(C, P, S, tol, maxit):
             break
         b, A = newton_model(bl)
         H = -2.0 * A
-        try:
-            Lc = np.linalg.cholesky(H)
-        except np.linalg.LinAlgError:
-            P, S = hooi_step(C, P, S)
-            it += 1
-            continue
-        d = np.linalg.solve(Lc.T, np.linalg.solve(Lc, b))
+        mu0 = 1e-8 * max(np.abs(np.diag(H)).max(), 1e-300)
+        g0 = float(np.sum(bl["F"] ** 2))
         nd = (C.shape[0] - r) * r
-        D = d[:nd].reshape(C.shape[0] - r, r)
-        T = d[nd:].reshape(C.shape[2] - r3, r3)
-        P = retract(bl["Qp"], D)
-        S = retract(bl["Qs"], T)
+        accepted = False
+        for _ in range(40):
+            Hs = H + mu * np.eye(H.shape[0])
+            try:
+                Lc = np.linalg.cholesky(Hs)
+            except np.linalg.LinAlgError:
+                lam_min = np.linalg.eigvalsh(Hs)[0]
+                mu = max(4.0 * mu, mu0, mu + 2.0 * abs(lam_min))
+                continue
+            d = np.linalg.solve(Lc.T, np.linalg.solve(Lc, b))
+            Pn = retract(bl["Qp"], d[:nd].reshape(C.shape[0] - r, r))
+            Sn = retract(bl["Qs"], d[nd:].reshape(C.shape[2] - r3, r3))
+            if objective(C, Pn, Sn) >= g0 * (1.0 - 4e-16):
+                P, S = Pn, Sn
+                accepted = True
+                mu = mu / 4.0 if mu > mu0 else 0.0
+                break
+            mu = max(4.0 * mu, mu0)
         it += 1
-        newton += 1
+        if accepted:
+            newton += 1
+        else:
+            P, S = hooi_step(C, P, S)
     return P, S, it, rel, newton
 
 

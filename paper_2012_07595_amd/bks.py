@@ -25,6 +25,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 
 SYMBOLS = [
     "bks_ctx_create", "bks_ctx_destroy", "bks_last_error", "bks_version",
+    "bks_ctx_profile", "bks_ctx_profile_read",
     "bks_tensor_upload", "bks_tensor_info", "bks_tensor_pairs", "bks_tensor_free",
     "bks_ttmc", "bks_solve", "hooi_solve",
     "bks_server_create", "bks_server_submit", "bks_server_submit_coo", "bks_server_poll",
@@ -43,7 +44,7 @@ class Params(C.Structure):
                 ("variant", C.c_int), ("precision", C.c_int), ("tol", C.c_double),
                 ("inner_tol", C.c_double), ("max_outer", C.c_int), ("hooi_warm", C.c_int),
                 ("ng_max", C.c_int), ("U0", C.c_void_p), ("W0", C.c_void_p),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("inner_start", C.c_int)]
 
 
 class HooiParams(C.Structure):
@@ -89,6 +90,10 @@ def load(path: str = LIBPATH):
     lib.bks_last_error.argtypes = [vp]
     lib.bks_last_error.restype = C.c_char_p
     lib.bks_version.restype = C.c_char_p
+    lib.bks_ctx_profile.argtypes = [vp, C.c_int]
+    lib.bks_ctx_profile_read.argtypes = [vp, C.c_int, C.c_char_p, C.c_int, C.POINTER(i64),
+                                         C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                         C.POINTER(C.c_double)]
     lib.bks_tensor_upload.argtypes = [vp, i64, i64, i64, vp, vp, vp, vp, C.c_int, C.c_uint,
                                       C.POINTER(vp)]
     lib.bks_tensor_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64),
@@ -139,6 +144,11 @@ class Ctx:
 
     def close(self):
         if self.h:
+            # tensors go before their context
+            for t in list(getattr(self, "_tensors", [])):
+                obj = t()
+                if obj is not None:
+                    obj.free()
             self.lib.bks_ctx_destroy(self.h)
             self.h = None
 
@@ -147,6 +157,25 @@ class Ctx:
             self.close()
         except Exception:
             pass
+
+    def profile(self, enable=True):
+        """Start (and reset) or stop event timing of the tensor products."""
+        self.check(self.lib.bks_ctx_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{class: (calls, ms, algorithmic bytes, flops)} of the recorded launches."""
+        out = {}
+        idx = 0
+        name = C.create_string_buffer(128)
+        calls, ms, by, fl = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
+        while True:
+            rc = self.lib.bks_ctx_profile_read(self.h, idx, name, 128, C.byref(calls), C.byref(ms),
+                                               C.byref(by), C.byref(fl))
+            if rc == ENOTFOUND:
+                return out
+            self.check(rc)
+            out[name.value.decode()] = (calls.value, ms.value, by.value, fl.value)
+            idx += 1
 
     def upload(self, m, n, i, j, k, val, flags=0):
         """Upload host coordinates (numpy int32 arrays, float32/float64 values)."""
@@ -160,7 +189,12 @@ class Ctx:
         h = C.c_void_p()
         self.check(self.lib.bks_tensor_upload(self.h, m, n, int(i.shape[0]), _ptr(i), _ptr(j),
                                               _ptr(k), _ptr(val), dt, flags, C.byref(h)))
-        return Tensor(self, h)
+        t = Tensor(self, h)
+        import weakref
+        if not hasattr(self, "_tensors"):
+            self._tensors = []
+        self._tensors = [w for w in self._tensors if w() is not None] + [weakref.ref(t)]
+        return t
 
     def upload_coo(self, coo, flags=0):
         return self.upload(coo.m, coo.n, coo.i, coo.j, coo.k, coo.val, flags)
@@ -176,12 +210,13 @@ class Ctx:
                                      1 if sym_half else 0, prec, _ptr(out), out.stride(0), s))
 
     def solve(self, t, r, r3, U0=None, W0=None, p=4, s=2, variant="bk", precision=PREC_FP64,
-              tol=0.0, inner_tol=0.0, max_outer=0, hooi_warm=-1, ng_max=0, seed=0):
+              tol=0.0, inner_tol=0.0, max_outer=0, hooi_warm=-1, ng_max=0, seed=0,
+              inner_start=0):
         """bks_solve: returns (U, W, F, info, status)."""
         m, n = t.m, t.n
         keep = []
         prm = Params(r, r3, s, p, VARIANT[variant], precision, tol, inner_tol, max_outer,
-                     hooi_warm, ng_max, None, None, seed)
+                     hooi_warm, ng_max, None, None, seed, inner_start)
         if U0 is not None:
             u = np.asfortranarray(U0, dtype=np.float64)
             w = np.asfortranarray(W0, dtype=np.float64)

@@ -31,7 +31,8 @@ def compile_one(src: str) -> str:
     if src.endswith(".hip"):
         cmd += DEVICE
     else:
-        cmd += ["-x", "c++"]
+        # host code: AVX2 + FMA (every x86-64 host of an MI355X has them)
+        cmd += ["-x", "c++", "-mavx2", "-mfma"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

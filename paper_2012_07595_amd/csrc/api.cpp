@@ -1,5 +1,6 @@
 // C ABI entry points of libbks: context, tensor upload, tensor-times-block
 // products.  Solver and server entry points live in solver.cpp / server.cpp.
+#include <algorithm>
 #include <cstring>
 #include <new>
 
@@ -104,7 +105,18 @@ void bks_ctx_destroy(bks_ctx ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    {
+        // tensors still alive become empty handles (bks_tensor_free stays valid)
+        std::lock_guard<std::mutex> g(ctx->tensors_mu);
+        for (Tensor *t : ctx->tensors) {
+            t->release_device();
+            t->ctx = nullptr;
+        }
+        ctx->tensors.clear();
+    }
+    ctx->prof_flush();
     (void)hipStreamDestroy(ctx->stream);
+    (void)hipGetLastError();
     delete ctx;
 }
 
@@ -148,6 +160,10 @@ int bks_tensor_upload(bks_ctx ctx, int64_t m, int64_t n, int64_t nnz, const int3
         if (ctx->budget && ctx->used + t->dev_bytes > ctx->budget)
             fail(BKS_ENOMEM, "tensor exceeds the context memory budget");
         ctx->used += t->dev_bytes;
+        {
+            std::lock_guard<std::mutex> g(ctx->tensors_mu);
+            ctx->tensors.push_back(t.get());
+        }
         *out = t.release();
     });
 }
@@ -173,11 +189,47 @@ int bks_tensor_pairs(bks_tensor t, int32_t *pi, int32_t *pj) {
 
 void bks_tensor_free(bks_tensor t) {
     if (!t) return;
-    if (t->ctx) {
-        (void)hipSetDevice(t->ctx->device);
-        if (t->ctx->used >= t->dev_bytes) t->ctx->used -= t->dev_bytes;
+    if (Ctx *c = t->ctx) {
+        (void)hipSetDevice(c->device);
+        if (c->used >= t->dev_bytes) c->used -= t->dev_bytes;
+        std::lock_guard<std::mutex> g(c->tensors_mu);
+        auto &v = c->tensors;
+        v.erase(std::remove(v.begin(), v.end(), static_cast<Tensor *>(t)), v.end());
     }
     delete t;
+    (void)hipGetLastError();
+}
+
+int bks_ctx_profile(bks_ctx ctx, int enable) {
+    if (!ctx) return BKS_EINVAL;
+    return guard(ctx, [&] {
+        ctx->prof_flush();
+        std::lock_guard<std::mutex> g(ctx->prof_mu);
+        ctx->prof_stats.clear();
+        ctx->prof = enable != 0;
+    });
+}
+
+int bks_ctx_profile_read(bks_ctx ctx, int idx, char *name, int name_len, int64_t *calls,
+                         double *ms, double *bytes, double *flops) {
+    if (!ctx || idx < 0) return BKS_EINVAL;
+    int rc = guard(ctx, [&] { ctx->prof_flush(); });
+    if (rc) return rc;
+    std::lock_guard<std::mutex> g(ctx->prof_mu);
+    int i = 0;
+    for (auto &kv : ctx->prof_stats) {
+        if (i++ != idx) continue;
+        if (name && name_len > 0) {
+            std::strncpy(name, kv.first.c_str(), name_len - 1);
+            name[name_len - 1] = 0;
+        }
+        if (calls) *calls = kv.second.calls;
+        if (ms) *ms = kv.second.ms;
+        if (bytes) *bytes = kv.second.bytes;
+        if (flops) *flops = kv.second.flops;
+        return BKS_OK;
+    }
+    return BKS_ENOTFOUND;
 }
 
 int bks_ttmc(bks_ctx ctx, bks_tensor t, int op, const void *B1, int64_t ld1, int p1,

@@ -79,6 +79,13 @@ struct Schedule {
 
 struct Tensor;
 
+// Event-timed launches of one kernel class (profiling).
+struct ProfClass {
+    int64_t calls = 0;
+    double ms = 0.0, bytes = 0.0, flops = 0.0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+};
+
 struct Ctx {
     int device = 0;
     size_t budget = 0;
@@ -88,6 +95,15 @@ struct Ctx {
     DevBuf ws_partial;              // TTMc partial rows
     DevBuf ws_pack1, ws_pack2;      // packed factor copies
     std::mutex mu;
+    std::mutex tensors_mu;
+    std::vector<Tensor *> tensors;  // live tensors uploaded through this ctx
+    bool prof = false;
+    std::mutex prof_mu;
+    std::map<std::string, ProfClass> prof_stats;
+    // Record a launch of class `name` bracketed by (a, b) on its stream.
+    void prof_record(const std::string &name, hipEvent_t a, hipEvent_t b, double bytes,
+                     double flops);
+    void prof_flush();
 };
 
 struct Tensor {
@@ -103,6 +119,7 @@ struct Tensor {
     std::mutex sched_mu;
     std::map<std::pair<int, int>, std::unique_ptr<Schedule>> sched;  // (order, E) -> schedule
     const Schedule &schedule(int order, int E);
+    void release_device();  // free every device buffer (ctx teardown)
 };
 
 // Build formats from host COO (validated, canonicalised).  Throws Error.

@@ -74,6 +74,36 @@ __global__ void reduce_splits(const double *__restrict__ part, int nsplit, int k
     out[(int64_t)kk * ldo + qq] = s;
 }
 
+// Many splits: one 256-thread block per output, strided partial sums and a
+// fixed-order tree in LDS (deterministic).
+__global__ __launch_bounds__(256) void reduce_splits_wide(const double *__restrict__ part,
+                                                          int nsplit, int k, int q,
+                                                          double *__restrict__ out, int64_t ldo) {
+    __shared__ double red[256];
+    const int64_t o = blockIdx.x;
+    const int kk = (int)(o / q), qq = (int)(o % q);
+    double s = 0.0;
+    for (int x = threadIdx.x; x < nsplit; x += 256) s += part[((int64_t)x * k + kk) * q + qq];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[(int64_t)kk * ldo + qq] = red[0];
+}
+
+void launch_reduce(const double *part, int nsplit, int k, int q, double *out, int64_t ldo,
+                   hipStream_t s) {
+    const int64_t n = (int64_t)k * q;
+    if (nsplit > 32 && n <= 65536)
+        hipLaunchKernelGGL(reduce_splits_wide, dim3((unsigned)n), dim3(256), 0, s, part, nsplit, k,
+                           q, out, ldo);
+    else
+        hipLaunchKernelGGL(reduce_splits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part,
+                           nsplit, k, q, out, ldo);
+}
+
 template <typename TB>
 void gemm_tn_impl(const double *A, int64_t lda, const TB *B, int64_t ldb, int64_t rows, int k,
                   int q, double *out, int64_t ldo, Ctx &c, hipStream_t s) {
@@ -96,9 +126,7 @@ void gemm_tn_impl(const double *A, int64_t lda, const TB *B, int64_t ldb, int64_
         hipLaunchKernelGGL(gemm_tn_kernel<TB>, dim3(tiles, (unsigned)nsplit), dim3(256), 0, s, A,
                            lda, B, ldb, rows, k, q, rps, part, ntk, ntq);
     }
-    const int64_t n = (int64_t)k * q;
-    hipLaunchKernelGGL(reduce_splits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part,
-                       (int)nsplit, k, q, out, ldo);
+    launch_reduce(part, (int)nsplit, k, q, out, ldo, s);
     HIPCHECK(hipGetLastError());
 }
 
@@ -212,14 +240,33 @@ __global__ __launch_bounds__(256) void gram_dd_kernel(const double *__restrict__
     }
 }
 
-__global__ void gram_dd_reduce(const double *__restrict__ phi, const double *__restrict__ plo,
-                               int nblk, int q, double *__restrict__ Ghi,
-                               double *__restrict__ Glo) {
+// One 64-thread block per pair: strided double-double partial sums, then a
+// fixed-order double-double tree in LDS.
+__global__ __launch_bounds__(64) void gram_dd_reduce(const double *__restrict__ phi,
+                                                     const double *__restrict__ plo, int nblk,
+                                                     int q, double *__restrict__ Ghi,
+                                                     double *__restrict__ Glo) {
+    __shared__ double rh[64], rl[64];
     const int npair = q * (q + 1) / 2;
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= npair) return;
+    const int p = blockIdx.x;
     double hi = 0.0, lo = 0.0;
-    for (int x = 0; x < nblk; ++x) dd_add(hi, lo, phi[(int64_t)x * npair + p], plo[(int64_t)x * npair + p]);
+    for (int x = threadIdx.x; x < nblk; x += 64)
+        dd_add(hi, lo, phi[(int64_t)x * npair + p], plo[(int64_t)x * npair + p]);
+    rh[threadIdx.x] = hi;
+    rl[threadIdx.x] = lo;
+    __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            double h2 = rh[threadIdx.x], l2 = rl[threadIdx.x];
+            dd_add(h2, l2, rh[threadIdx.x + w], rl[threadIdx.x + w]);
+            rh[threadIdx.x] = h2;
+            rl[threadIdx.x] = l2;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    hi = rh[0];
+    lo = rl[0];
     int d = 0;
     while ((d + 1) * (d + 2) / 2 <= p) ++d;
     const int c = p - d * (d + 1) / 2;
@@ -295,23 +342,22 @@ void gram_dd(const double *B, int64_t ldb, int64_t rows, int q, double *Ghi, dou
     double *plo = phi + nblk * npair;
     hipLaunchKernelGGL(gram_dd_kernel, dim3((unsigned)nblk), dim3(256), 0, s, B, ldb, rows, q, rpb,
                        phi, plo);
-    hipLaunchKernelGGL(gram_dd_reduce, dim3((npair + 127) / 128), dim3(128), 0, s, phi, plo,
-                       (int)nblk, q, Ghi, Glo);
+    hipLaunchKernelGGL(gram_dd_reduce, dim3(npair), dim3(64), 0, s, phi, plo, (int)nblk, q, Ghi,
+                       Glo);
     HIPCHECK(hipGetLastError());
 }
 
 void colnorm2(const double *B, int64_t ldb, int64_t rows, int q, double *out, Ctx &c,
               hipStream_t s) {
     if (q <= 0) return;
-    int64_t nblk = std::min<int64_t>(512, std::max<int64_t>(1, (rows + 1023) / 1024));
+    int64_t nblk = std::min<int64_t>(2048, std::max<int64_t>(1, (rows + 63) / 64));
     int64_t rpb = std::max<int64_t>(1, (rows + nblk - 1) / nblk);
     nblk = std::max<int64_t>(1, (rows + rpb - 1) / rpb);
     c.ws_pack1.ensure((size_t)nblk * q * sizeof(double));
     double *part = c.ws_pack1.as<double>();
     hipLaunchKernelGGL(colnorm2_kernel, dim3((unsigned)nblk), dim3(256), 0, s, B, ldb, rows, q, rpb,
                        part);
-    hipLaunchKernelGGL(reduce_splits, dim3((q + 255) / 256), dim3(256), 0, s, part, (int)nblk, 1,
-                       q, out, (int64_t)q);
+    launch_reduce(part, (int)nblk, 1, q, out, (int64_t)q, s);
     HIPCHECK(hipGetLastError());
 }
 

@@ -326,6 +326,21 @@ void build_schedule(const std::vector<int64_t> &segptr, int E, std::vector<Item>
     }
 }
 
+void Tensor::release_device() {
+    std::lock_guard<std::mutex> g(sched_mu);
+    for (Segmented *o : {&o3, &o1, &op}) {
+        o->segptr.release();
+        o->c1.release();
+        o->c2.release();
+        o->v32.release();
+        o->v64.release();
+        o->nseg = 0;
+        o->nent = 0;
+    }
+    sched.clear();
+    dev_bytes = 0;
+}
+
 const Schedule &Tensor::schedule(int order, int E) {
     std::lock_guard<std::mutex> g(sched_mu);
     auto key = std::make_pair(order, E);

@@ -1,0 +1,458 @@
+// Inner solve of Algorithm 5 step (i) on the host in FP64.
+//
+// g(P, S) = ||C.(P, P, S)||^2 on Gr(k1, r) x Gr(k3, r3).  Start: truncated
+// HOSVD of C and `hooi_warm` symmetric HOOI iterations (Section 5.2), then
+// Newton-Grassmann.  The paper cites Newton-Grassmann without giving it; the
+// step used here comes from the second-order expansion of g in the local
+// coordinates of Appendix A.  With [P P_perp], [S S_perp] orthogonal and
+// B = C.([P P_perp], [P P_perp], [S S_perp]) split into blocks (0 = first r or
+// r3 coordinates, 1 = the rest), F = B000 and, along P(D) = [I; D] M,
+// S(T) = [I; T] N with M, N the normalisations,
+//   g = ||F||^2 + 4<Gamma1, D> + 2<Gamma3, T> + d^T A d + O(|d|^3)
+//   Gamma1 = <B100, F>_{-1},  Gamma3 = <B001, F>_{-3}
+//   d^T A d = ||G1||^2 + 2<F, G2> - 2 tr(D S1 D^T) - tr(T S3 T^T)
+// where G1, G2 are the first and second order parts of B.([I;D],[I;D],[I;T])
+// and S1 = <F, F>_{-1}, S3 = <F, F>_{-3}.  The blocks of A are formed in
+// closed form from B100, B001, B110, B101 and F; the Newton step solves
+// (-2A) d = (4 Gamma1, 2 Gamma3) by Cholesky and retracts with a thin QR.
+// If -2A is not positive definite a HOOI iteration is taken instead.
+#include "inner.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "linalg.h"
+
+namespace bks {
+
+namespace {
+
+struct View {
+    const double *C;
+    int k1, k3;
+    double at(int a, int b, int c) const { return C[a + (size_t)k1 * (b + (size_t)k1 * c)]; }
+};
+
+// CS(a, b, l) = sum_c C(a, b, c) Sv(c, l) for the columns [l0, l0+nl) of Sv
+// (k3 x ldS row-major).  Output layout: a + k1*(b + k1*l).
+void mode3_product(const View &V, const double *Sv, int ldS, int l0, int nl,
+                   std::vector<double> &out) {
+    const int k1 = V.k1, k3 = V.k3;
+    const size_t sl = (size_t)k1 * k1;
+    out.assign(sl * nl, 0.0);
+    for (int c = 0; c < k3; ++c) {
+        const double *slice = V.C + sl * c;
+        for (int l = 0; l < nl; ++l) {
+            const double w = Sv[(size_t)c * ldS + l0 + l];
+            if (w == 0.0) continue;
+            double *o = &out[sl * l];
+            for (size_t x = 0; x < sl; ++x) o[x] += w * slice[x];
+        }
+    }
+}
+
+void hosvd(const View &V, int r, int r3, std::vector<double> &P, std::vector<double> &S) {
+    const int k1 = V.k1, k3 = V.k3;
+    const size_t sl = (size_t)k1 * k1;
+    // G1 = C_(1) C_(1)^T over the columns (b, c)
+    std::vector<double> G1((size_t)k1 * k1, 0.0);
+    const size_t ncol = (size_t)k1 * k3;
+    for (size_t col = 0; col < ncol; ++col) {
+        const double *v = V.C + (size_t)k1 * col;
+        for (int a = 0; a < k1; ++a) {
+            const double va = v[a];
+            if (va == 0.0) continue;
+            double *g = &G1[(size_t)a * k1];
+            for (int b = 0; b <= a; ++b) g[b] += va * v[b];
+        }
+    }
+    for (int a = 0; a < k1; ++a)
+        for (int b = 0; b < a; ++b) G1[(size_t)b * k1 + a] = G1[(size_t)a * k1 + b];
+    std::vector<double> G3((size_t)k3 * k3, 0.0);
+    for (int c = 0; c < k3; ++c)
+        for (int d = 0; d <= c; ++d) {
+            const double *x = V.C + sl * c, *y = V.C + sl * d;
+            double s = 0.0;
+            for (size_t t = 0; t < sl; ++t) s += x[t] * y[t];
+            G3[(size_t)c * k3 + d] = G3[(size_t)d * k3 + c] = s;
+        }
+    P.assign((size_t)k1 * r, 0.0);
+    S.assign((size_t)k3 * r3, 0.0);
+    la::top_eigvecs(k1, G1.data(), r, P.data());
+    la::top_eigvecs(k3, G3.data(), r3, S.data());
+}
+
+// One symmetric HOOI iteration on the core (Section 5.1).
+void hooi_step(const View &V, int r, int r3, std::vector<double> &P, std::vector<double> &S) {
+    const int k1 = V.k1, k3 = V.k3;
+    std::vector<double> CS;
+    mode3_product(V, S.data(), r3, 0, r3, CS);  // k1 x k1 x r3
+    // M1(a, j + r*l) = sum_b CS(a, b, l) P(b, j)
+    const int w1 = r * r3;
+    std::vector<double> M1((size_t)k1 * w1, 0.0);
+    for (int l = 0; l < r3; ++l)
+        for (int b = 0; b < k1; ++b)
+            for (int a = 0; a < k1; ++a) {
+                const double cv = CS[a + (size_t)k1 * (b + (size_t)k1 * l)];
+                if (cv == 0.0) continue;
+                for (int j = 0; j < r; ++j) M1[(size_t)a * w1 + j + r * l] += cv * P[(size_t)b * r + j];
+            }
+    std::vector<double> G((size_t)k1 * k1, 0.0);
+    la::gemm(k1, k1, w1, M1.data(), [&] {
+        std::vector<double> T((size_t)w1 * k1);
+        for (int a = 0; a < k1; ++a)
+            for (int x = 0; x < w1; ++x) T[(size_t)x * k1 + a] = M1[(size_t)a * w1 + x];
+        return T;
+    }().data(), G.data());
+    la::top_eigvecs(k1, G.data(), r, P.data());
+    // M3(c, i + r*j) = sum_{a,b} C(a,b,c) P(a,i) P(b,j)
+    const int w3 = r * r;
+    std::vector<double> M3((size_t)k3 * w3, 0.0);
+    std::vector<double> CP((size_t)r * k1);
+    for (int c = 0; c < k3; ++c) {
+        std::fill(CP.begin(), CP.end(), 0.0);
+        for (int b = 0; b < k1; ++b)
+            for (int a = 0; a < k1; ++a) {
+                const double cv = V.at(a, b, c);
+                if (cv == 0.0) continue;
+                for (int i = 0; i < r; ++i) CP[(size_t)i * k1 + b] += cv * P[(size_t)a * r + i];
+            }
+        for (int i = 0; i < r; ++i)
+            for (int j = 0; j < r; ++j) {
+                double s = 0.0;
+                for (int b = 0; b < k1; ++b) s += CP[(size_t)i * k1 + b] * P[(size_t)b * r + j];
+                M3[(size_t)c * w3 + i + r * j] = s;
+            }
+    }
+    std::vector<double> G3((size_t)k3 * k3, 0.0);
+    for (int c = 0; c < k3; ++c)
+        for (int d = 0; d <= c; ++d) {
+            double s = 0.0;
+            for (int x = 0; x < w3; ++x) s += M3[(size_t)c * w3 + x] * M3[(size_t)d * w3 + x];
+            G3[(size_t)c * k3 + d] = G3[(size_t)d * k3 + c] = s;
+        }
+    la::top_eigvecs(k3, G3.data(), r3, S.data());
+}
+
+struct Blocks {
+    int r, r3, A1, C1;
+    std::vector<double> Qp, Qs;   // k1 x k1, k3 x k3 (row-major), first columns span P, S
+    std::vector<double> F;        // r x r x r3     F(a,b,c)   at a + r*(b + r*c)
+    std::vector<double> B100;     // A1 x r x r3    (x,b,c)    at x + A1*(b + r*c)
+    std::vector<double> B110;     // A1 x A1 x r3   (x,y,c)    at x + A1*(y + A1*c)
+    std::vector<double> B001;     // r x r x C1     (a,b,z)    at a + r*(b + r*z)
+    std::vector<double> B101;     // A1 x r x C1    (x,b,z)    at x + A1*(b + r*z)
+};
+
+void rotate(const View &V, const std::vector<double> &P, const std::vector<double> &S, int r,
+            int r3, Blocks &B) {
+    const int k1 = V.k1, k3 = V.k3;
+    B.r = r;
+    B.r3 = r3;
+    B.A1 = k1 - r;
+    B.C1 = k3 - r3;
+    B.Qp.resize((size_t)k1 * k1);
+    B.Qs.resize((size_t)k3 * k3);
+    la::qr_full(k1, r, P.data(), B.Qp.data());
+    la::qr_full(k3, r3, S.data(), B.Qs.data());
+    const int A1 = B.A1, C1 = B.C1;
+    // R0 = C.(Qp, Qp, S)  (all of modes 1-2, the first r3 of mode 3)
+    std::vector<double> CS;
+    mode3_product(V, B.Qs.data(), k3, 0, r3, CS);
+    std::vector<double> tmp((size_t)k1 * k1), Y((size_t)k1 * k1);
+    B.F.assign((size_t)r * r * r3, 0.0);
+    B.B100.assign((size_t)A1 * r * r3, 0.0);
+    B.B110.assign((size_t)A1 * A1 * r3, 0.0);
+    for (int l = 0; l < r3; ++l) {
+        // Xl(a, b) = CS(a, b, l) at a + k1*b (symmetric);  Y = Qp^T Xl Qp
+        const double *Xl = &CS[(size_t)k1 * k1 * l];
+        // tmp(a, y) = sum_b Xl(a, b) Qp(b, y)
+        std::fill(tmp.begin(), tmp.end(), 0.0);
+        for (int a = 0; a < k1; ++a)
+            for (int b = 0; b < k1; ++b) {
+                const double xv = Xl[a + (size_t)k1 * b];
+                if (xv == 0.0) continue;
+                const double *qb = &B.Qp[(size_t)b * k1];
+                double *t = &tmp[(size_t)a * k1];
+                for (int y = 0; y < k1; ++y) t[y] += xv * qb[y];
+            }
+        la::gemm_tn(k1, k1, k1, B.Qp.data(), tmp.data(), Y.data());  // Y(x, y)
+        for (int x = 0; x < k1; ++x)
+            for (int y = 0; y < k1; ++y) {
+                const double v = Y[(size_t)x * k1 + y];
+                if (x < r && y < r) B.F[x + r * (y + (size_t)r * l)] = v;
+                else if (x >= r && y < r) B.B100[(x - r) + (size_t)A1 * (y + (size_t)r * l)] = v;
+                else if (x >= r && y >= r)
+                    B.B110[(x - r) + (size_t)A1 * ((y - r) + (size_t)A1 * l)] = v;
+            }
+    }
+    // R1 = C.(Qp, P, S_perp)
+    B.B001.assign((size_t)r * r * C1, 0.0);
+    B.B101.assign((size_t)A1 * r * C1, 0.0);
+    if (C1 > 0) {
+        std::vector<double> CSp;
+        mode3_product(V, B.Qs.data(), k3, r3, C1, CSp);
+        std::vector<double> t2((size_t)k1 * r), Y2((size_t)k1 * r);
+        for (int z = 0; z < C1; ++z) {
+            const double *Xz = &CSp[(size_t)k1 * k1 * z];
+            std::fill(t2.begin(), t2.end(), 0.0);
+            for (int a = 0; a < k1; ++a)
+                for (int b = 0; b < k1; ++b) {
+                    const double xv = Xz[a + (size_t)k1 * b];
+                    if (xv == 0.0) continue;
+                    const double *qb = &B.Qp[(size_t)b * k1];
+                    double *t = &t2[(size_t)a * r];
+                    for (int j = 0; j < r; ++j) t[j] += xv * qb[j];
+                }
+            la::gemm_tn(k1, r, k1, B.Qp.data(), t2.data(), Y2.data());  // (x, j)
+            for (int x = 0; x < k1; ++x)
+                for (int j = 0; j < r; ++j) {
+                    const double v = Y2[(size_t)x * r + j];
+                    if (x < r) B.B001[x + r * (j + (size_t)r * z)] = v;
+                    else B.B101[(x - r) + (size_t)A1 * (j + (size_t)r * z)] = v;
+                }
+        }
+    }
+}
+
+double local_gradient(const Blocks &B, std::vector<double> &G1, std::vector<double> &G3,
+                      double &normF) {
+    const int r = B.r, r3 = B.r3, A1 = B.A1, C1 = B.C1;
+    G1.assign((size_t)A1 * r, 0.0);
+    G3.assign((size_t)C1 * r3, 0.0);
+    for (int x = 0; x < A1; ++x)
+        for (int a = 0; a < r; ++a) {
+            double s = 0.0;
+            for (int c = 0; c < r3; ++c)
+                for (int b = 0; b < r; ++b)
+                    s += B.B100[x + (size_t)A1 * (b + (size_t)r * c)] * B.F[a + r * (b + (size_t)r * c)];
+            G1[(size_t)x * r + a] = s;
+        }
+    for (int z = 0; z < C1; ++z)
+        for (int c = 0; c < r3; ++c) {
+            double s = 0.0;
+            for (int b = 0; b < r; ++b)
+                for (int a = 0; a < r; ++a)
+                    s += B.B001[a + r * (b + (size_t)r * z)] * B.F[a + r * (b + (size_t)r * c)];
+            G3[(size_t)z * r3 + c] = s;
+        }
+    double f2 = 0.0, g1 = 0.0, g3 = 0.0;
+    for (double v : B.F) f2 += v * v;
+    for (double v : G1) g1 += v * v;
+    for (double v : G3) g3 += v * v;
+    normF = std::sqrt(f2);
+    return normF > 0 ? std::sqrt(2.0 * g1 + g3) / normF : INFINITY;
+}
+
+// Negative Hessian H = -2A (N x N row-major) of the second-order model.
+void newton_matrix(const Blocks &B, std::vector<double> &H) {
+    const int r = B.r, r3 = B.r3, A1 = B.A1, C1 = B.C1;
+    const int nd = A1 * r, nt = C1 * r3, N = nd + nt;
+    H.assign((size_t)N * N, 0.0);
+    auto Fv = [&](int a, int b, int c) { return B.F[a + r * (b + (size_t)r * c)]; };
+    auto M = [&](int x, int b, int c) { return B.B100[x + (size_t)A1 * (b + (size_t)r * c)]; };
+    auto B110 = [&](int x, int y, int c) { return B.B110[x + (size_t)A1 * (y + (size_t)A1 * c)]; };
+    auto B001 = [&](int a, int b, int z) { return B.B001[a + r * (b + (size_t)r * z)]; };
+    auto B101 = [&](int x, int b, int z) { return B.B101[x + (size_t)A1 * (b + (size_t)r * z)]; };
+    std::vector<double> S1((size_t)r * r, 0.0), S3((size_t)r3 * r3, 0.0);
+    for (int a = 0; a < r; ++a)
+        for (int b = 0; b < r; ++b) {
+            double s = 0.0;
+            for (int c = 0; c < r3; ++c)
+                for (int y = 0; y < r; ++y) s += Fv(a, y, c) * Fv(b, y, c);
+            S1[(size_t)a * r + b] = s;
+        }
+    for (int c = 0; c < r3; ++c)
+        for (int d = 0; d < r3; ++d) {
+            double s = 0.0;
+            for (int a = 0; a < r; ++a)
+                for (int b = 0; b < r; ++b) s += Fv(a, b, c) * Fv(a, b, d);
+            S3[(size_t)c * r3 + d] = s;
+        }
+    // <M_x, M_y>
+    std::vector<double> MM((size_t)A1 * A1, 0.0);
+    for (int x = 0; x < A1; ++x)
+        for (int y = 0; y <= x; ++y) {
+            double s = 0.0;
+            for (int c = 0; c < r3; ++c)
+                for (int b = 0; b < r; ++b) s += M(x, b, c) * M(y, b, c);
+            MM[(size_t)x * A1 + y] = MM[(size_t)y * A1 + x] = s;
+        }
+    std::vector<double> A((size_t)N * N, 0.0);
+    // Delta-Delta block
+    for (int x = 0; x < A1; ++x)
+        for (int a = 0; a < r; ++a) {
+            const int row = x * r + a;
+            for (int y = 0; y < A1; ++y)
+                for (int b = 0; b < r; ++b) {
+                    const int col = y * r + b;
+                    double v = 0.0;
+                    if (a == b) v += 2.0 * MM[(size_t)x * A1 + y];
+                    double cross = 0.0, kf = 0.0;
+                    for (int c = 0; c < r3; ++c) {
+                        cross += M(x, b, c) * M(y, a, c);
+                        kf += Fv(a, b, c) * B110(x, y, c);
+                    }
+                    v += 2.0 * cross + 2.0 * kf;
+                    if (x == y) v -= 2.0 * S1[(size_t)a * r + b];
+                    A[(size_t)row * N + col] = v;
+                }
+        }
+    // Delta-Theta blocks
+    for (int x = 0; x < A1; ++x)
+        for (int a = 0; a < r; ++a) {
+            const int row = x * r + a;
+            for (int z = 0; z < C1; ++z)
+                for (int c = 0; c < r3; ++c) {
+                    const int col = nd + z * r3 + c;
+                    double s = 0.0;
+                    for (int b = 0; b < r; ++b)
+                        s += M(x, b, c) * B001(a, b, z) + Fv(a, b, c) * B101(x, b, z);
+                    A[(size_t)row * N + col] = 2.0 * s;
+                    A[(size_t)col * N + row] = 2.0 * s;
+                }
+        }
+    // Theta-Theta block
+    for (int z = 0; z < C1; ++z)
+        for (int w = 0; w <= z; ++w) {
+            double s = 0.0;
+            for (int b = 0; b < r; ++b)
+                for (int a = 0; a < r; ++a) s += B001(a, b, z) * B001(a, b, w);
+            for (int c = 0; c < r3; ++c) {
+                const int i1 = nd + z * r3 + c, j1 = nd + w * r3 + c;
+                A[(size_t)i1 * N + j1] += s;
+                if (w != z) A[(size_t)j1 * N + i1] += s;
+            }
+        }
+    for (int z = 0; z < C1; ++z)
+        for (int c = 0; c < r3; ++c)
+            for (int d = 0; d < r3; ++d)
+                A[(size_t)(nd + z * r3 + c) * N + nd + z * r3 + d] -= S3[(size_t)c * r3 + d];
+    for (size_t i = 0; i < (size_t)N * N; ++i) H[i] = -2.0 * A[i];
+    // exact symmetry
+    for (int i = 0; i < N; ++i)
+        for (int j = i + 1; j < N; ++j) {
+            const double s = 0.5 * (H[(size_t)i * N + j] + H[(size_t)j * N + i]);
+            H[(size_t)i * N + j] = H[(size_t)j * N + i] = s;
+        }
+}
+
+// g(P, S) = ||C.(P, P, S)||^2
+double objective(const View &V, const std::vector<double> &P, const std::vector<double> &S, int r,
+                 int r3) {
+    const int k1 = V.k1;
+    std::vector<double> CS;
+    mode3_product(V, S.data(), r3, 0, r3, CS);
+    std::vector<double> t((size_t)k1 * r);
+    double g = 0.0;
+    for (int l = 0; l < r3; ++l) {
+        const double *Xl = &CS[(size_t)k1 * k1 * l];
+        std::fill(t.begin(), t.end(), 0.0);
+        for (int b = 0; b < k1; ++b)
+            for (int a = 0; a < k1; ++a) {
+                const double xv = Xl[a + (size_t)k1 * b];
+                if (xv == 0.0) continue;
+                for (int j = 0; j < r; ++j) t[(size_t)a * r + j] += xv * P[(size_t)b * r + j];
+            }
+        for (int i = 0; i < r; ++i)
+            for (int j = 0; j < r; ++j) {
+                double s = 0.0;
+                for (int a = 0; a < k1; ++a) s += P[(size_t)a * r + i] * t[(size_t)a * r + j];
+                g += s * s;
+            }
+    }
+    return g;
+}
+
+// orth(Q(:, :r) + Q(:, r:) D), Q k x k row-major, D (k-r) x r row-major
+void retract(int k, int r, const std::vector<double> &Q, const double *D, std::vector<double> &out) {
+    out.assign((size_t)k * r, 0.0);
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < r; ++j) {
+            double s = Q[(size_t)i * k + j];
+            for (int x = 0; x < k - r; ++x) s += Q[(size_t)i * k + r + x] * D[(size_t)x * r + j];
+            out[(size_t)i * r + j] = s;
+        }
+    la::orthonormalize(k, r, out.data());
+}
+
+}  // namespace
+
+void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, double tol,
+                 int hooi_warm, int ng_max, bool warm, std::vector<double> &P,
+                 std::vector<double> &S, InnerInfo &info) {
+    View V{C.data(), k1, k3};
+    info = InnerInfo{};
+    auto clk = [] {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+            .count();
+    };
+    double t0 = clk();
+    if (!warm) {
+        hosvd(V, r, r3, P, S);
+        for (int it = 0; it < hooi_warm; ++it) hooi_step(V, r, r3, P, S);
+    }
+    info.t_start = clk() - t0;
+    Blocks B;
+    std::vector<double> G1, G3, H, Hs, d, Pn, Sn;
+    double mu = 0.0;
+    while (true) {
+        t0 = clk();
+        rotate(V, P, S, r, r3, B);
+        double nf;
+        info.rel = local_gradient(B, G1, G3, nf);
+        info.t_rotate += clk() - t0;
+        if (info.rel <= tol || info.iters >= ng_max) break;
+        if (B.A1 * r + B.C1 * r3 == 0) break;
+        t0 = clk();
+        newton_matrix(B, H);
+        info.t_hess += clk() - t0;
+        const int nd = B.A1 * r, N = nd + B.C1 * r3;
+        // Safeguarded Newton step (a reading: the paper cites the method
+        // only): solve (-2A + mu I) d = b with the smallest tried shift that
+        // makes the matrix positive definite and the step increase g; mu = 0
+        // near a maximum gives the plain Newton step.
+        double hmax = 0.0;
+        for (int i = 0; i < N; ++i) hmax = std::max(hmax, std::fabs(H[(size_t)i * N + i]));
+        const double mu0 = 1e-8 * std::max(hmax, 1e-300);
+        const double g0 = nf * nf;
+        bool accepted = false;
+        for (int attempt = 0; attempt < 40 && !accepted; ++attempt) {
+            Hs = H;
+            for (int i = 0; i < N; ++i) Hs[(size_t)i * N + i] += mu;
+            t0 = clk();
+            double piv = 0.0;
+            const bool pd = la::cholesky(N, Hs.data(), &piv);
+            info.t_chol += clk() - t0;
+            if (!pd) {
+                // the failed pivot bounds how far the spectrum reaches below 0
+                mu = std::max({4.0 * mu, mu0, mu + 2.0 * std::fabs(piv)});
+                continue;
+            }
+            d.assign(N, 0.0);
+            for (int i = 0; i < nd; ++i) d[i] = 4.0 * G1[i];
+            for (int i = 0; i < N - nd; ++i) d[nd + i] = 2.0 * G3[i];
+            la::chol_solve(N, Hs.data(), d.data());
+            retract(k1, r, B.Qp, d.data(), Pn);
+            retract(k3, r3, B.Qs, d.data() + nd, Sn);
+            const double g1 = objective(V, Pn, Sn, r, r3);
+            if (g1 >= g0 * (1.0 - 4e-16)) {
+                accepted = true;
+                P.swap(Pn);
+                S.swap(Sn);
+                mu = mu > mu0 ? mu / 4.0 : 0.0;
+            } else {
+                mu = std::max(4.0 * mu, mu0);
+            }
+        }
+        ++info.iters;
+        if (accepted) {
+            ++info.newton;
+        } else {
+            hooi_step(V, r, r3, P, S);
+        }
+    }
+}
+
+}  // namespace bks

@@ -1,0 +1,41 @@
+// Small dense FP64 linear algebra on the host for the projected problem
+// (Algorithm 5 step (i)) and the small factors of the block
+// orthogonalisation.  Matrices are row-major unless stated.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace bks {
+namespace la {
+
+using Mat = std::vector<double>;
+
+// Symmetric eigendecomposition A = V diag(w) V^T (A n x n row-major, only
+// read).  Eigenvalues in descending order; V(:, i) is column i of the
+// row-major V.  Householder tridiagonalisation + implicit QL.
+void sym_eig(int n, const double *A, double *w, double *V);
+
+// Leading r eigenvectors (descending eigenvalues) as an n x r row-major matrix.
+void top_eigvecs(int n, const double *A, int r, double *Vr, double *wr = nullptr);
+
+// Cholesky A = L L^T in place (lower triangle, row-major).  false if A is
+// not numerically positive definite (then *fail_pivot, if given, is the
+// offending Schur-complement diagonal).
+bool cholesky(int n, double *A, double *fail_pivot = nullptr);
+// Solve L L^T x = b in place.
+void chol_solve(int n, const double *L, double *b);
+
+// Householder QR of an m x n (m >= n) row-major matrix: returns the full
+// m x m orthogonal Q (row-major) whose first n columns span the columns.
+void qr_full(int m, int n, const double *A, double *Q);
+// Thin orthonormalisation (first n columns of qr_full).
+void orthonormalize(int m, int n, double *A);
+
+// C (m x n) = A (m x k) * B (k x n), all row-major.
+void gemm(int m, int n, int k, const double *A, const double *B, double *C);
+// C (m x n) = A^T (A: k x m) * B (k x n)
+void gemm_tn(int m, int n, int k, const double *A, const double *B, double *C);
+
+}  // namespace la
+}  // namespace bks

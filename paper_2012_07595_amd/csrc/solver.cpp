@@ -1,13 +1,999 @@
-// placeholder, replaced by the solver implementation
+// Block Krylov-Schur (Algorithm 5, symmetric case U = V) and symmetric HOOI
+// (Section 5.1) driven from the host; every product with the large tensor
+// and every tall-skinny operation runs on the device, the small projected
+// problems on the host in FP64.
+//
+// Precision modes
+//   FP64:  every tensor product in FP64.
+//   MIXED: block-Krylov expansion products and the core product A.(X, X)_{1,2}
+//          in FP32; the step-(iii) products T1 = A.(U0, W0)_{2,3} and
+//          T3 = A.(U0, U0)_{1,2} with FP32 values, FP64 factors and FP64
+//          accumulation.  By Proposition 3.2 and Lemma 3.1 the G-gradient
+//          of the projected problem at the restart point depends only on the
+//          slices C(:, U0, W0) = X^T T1 and C(U0, U0, :) = Z^T T3, so those
+//          slices of the FP32-formed core are overwritten with FP64-accurate
+//          ones: a stationary point of the full problem is then an exact
+//          fixed point of the mixed iteration.  The basis itself is always
+//          kept and orthogonalised in FP64 (with an FP32 shadow copy feeding
+//          the FP32 products).
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <random>
+#include <set>
+
 #include "bks_internal.h"
-extern "C" {
-int bks_solve(bks_ctx, bks_tensor, const bks_params *, double *, double *, double *, bks_info *) { return BKS_EINVAL; }
-int hooi_solve(bks_ctx, bks_tensor, const hooi_params *, double *, double *, double *, bks_info *) { return BKS_EINVAL; }
-int bks_server_create(bks_ctx, const bks_server_params *, bks_server *) { return BKS_EINVAL; }
-int bks_server_submit(bks_server, bks_tensor, const bks_params *, double *, double *, double *, uint64_t *) { return BKS_EINVAL; }
-int bks_server_submit_coo(bks_server, int64_t, int64_t, int64_t, const int32_t *, const int32_t *, const int32_t *, const float *, const bks_params *, double *, double *, double *, uint64_t *) { return BKS_EINVAL; }
-int bks_server_poll(bks_server, uint64_t, bks_result *) { return BKS_EINVAL; }
-int bks_server_wait(bks_server, uint64_t, bks_result *) { return BKS_EINVAL; }
-double bks_server_now(bks_server) { return 0.0; }
-void bks_server_destroy(bks_server) {}
+#include "inner.h"
+#include "linalg.h"
+
+namespace bks {
+
+namespace {
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
+
+// ------------------------------------------------------------ double-double
+struct dd {
+    double hi, lo;
+};
+inline dd dd_from(double a) { return {a, 0.0}; }
+inline dd two_sum(double a, double b) {
+    double s = a + b, bb = s - a;
+    return {s, (a - (s - bb)) + (b - bb)};
+}
+inline dd dd_norm(double s, double e) {
+    double h = s + e;
+    return {h, e - (h - s)};
+}
+inline dd add(dd a, dd b) {
+    dd s = two_sum(a.hi, b.hi);
+    dd t = two_sum(a.lo, b.lo);
+    s.lo += t.hi;
+    s = dd_norm(s.hi, s.lo);
+    s.lo += t.lo;
+    return dd_norm(s.hi, s.lo);
+}
+inline dd neg(dd a) { return {-a.hi, -a.lo}; }
+inline dd sub(dd a, dd b) { return add(a, neg(b)); }
+inline dd mul(dd a, dd b) {
+    double p = a.hi * b.hi;
+    double e = std::fma(a.hi, b.hi, -p);
+    e += a.hi * b.lo + a.lo * b.hi;
+    return dd_norm(p, e);
+}
+inline dd divd(dd a, dd b) {
+    double q1 = a.hi / b.hi;
+    dd r = sub(a, mul(b, dd_from(q1)));
+    double q2 = r.hi / b.hi;
+    r = sub(r, mul(b, dd_from(q2)));
+    double q3 = r.hi / b.hi;
+    return add(dd_norm(q1, q2), dd_from(q3));
+}
+inline dd sqrtd(dd a) {
+    if (a.hi <= 0) return {0, 0};
+    double x = std::sqrt(a.hi);
+    dd xx = mul(dd_from(x), dd_from(x));
+    dd r = sub(a, xx);
+    return add(dd_from(x), dd_from(r.hi / (2.0 * x)));
+}
+
+// Ordered Cholesky of a DD Gram matrix G (q x q, row-major hi/lo) with
+// column dropping; returns kept columns and T (q x q', row-major) with
+// Q = B T having orthonormal columns spanning the kept part.
+//   drop column c if its residual^2 <= (tau * before_c)^2, or once the basis
+//   is full (room columns already kept).
+void chol_drop(int q, const std::vector<double> &Ghi, const std::vector<double> &Glo,
+               const std::vector<double> &before2, double tau, int room, std::vector<int> &kept,
+               std::vector<double> &T) {
+    std::vector<dd> G((size_t)q * q);
+    for (size_t i = 0; i < G.size(); ++i) G[i] = {Ghi[i], Glo[i]};
+    std::vector<dd> R((size_t)q * q, dd{0, 0});
+    kept.clear();
+    for (int c = 0; c < q; ++c) {
+        if ((int)kept.size() >= room) break;
+        dd d = G[(size_t)c * q + c];
+        for (int e : kept) d = sub(d, mul(R[(size_t)e * q + c], R[(size_t)e * q + c]));
+        const double thr = tau * tau * before2[c];
+        if (!(d.hi > thr) || d.hi <= 0.0) continue;
+        dd rcc = sqrtd(d);
+        R[(size_t)c * q + c] = rcc;
+        for (int x = c + 1; x < q; ++x) {
+            dd s = G[(size_t)c * q + x];
+            for (int e : kept) s = sub(s, mul(R[(size_t)e * q + c], R[(size_t)e * q + x]));
+            R[(size_t)c * q + x] = divd(s, rcc);
+        }
+        kept.push_back(c);
+    }
+    const int k = (int)kept.size();
+    // Rk = R(kept, kept) upper triangular; T = Rk^{-1} (DD back substitution)
+    std::vector<dd> Ti((size_t)k * k, dd{0, 0});
+    for (int j = 0; j < k; ++j) {
+        // solve Rk t = e_j
+        for (int i = j; i >= 0; --i) {
+            dd s = (i == j) ? dd_from(1.0) : dd{0, 0};
+            for (int l = i + 1; l <= j; ++l)
+                s = sub(s, mul(R[(size_t)kept[i] * q + kept[l]], Ti[(size_t)l * k + j]));
+            Ti[(size_t)i * k + j] = divd(s, R[(size_t)kept[i] * q + kept[i]]);
+        }
+    }
+    T.assign((size_t)q * k, 0.0);
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) T[(size_t)kept[i] * k + j] = Ti[(size_t)i * k + j].hi + Ti[(size_t)i * k + j].lo;
+}
+
+int sym_idx(int a, int b) { return b * (b + 1) / 2 + a; }  // a <= b
+
+struct Solver {
+    Ctx &c;
+    Tensor &t;
+    hipStream_t s;
+    int64_t m, n;
+    int r, r3, p, stages, variant;
+    bool mixed;
+    double tau64 = 1e-14, tau32 = 1e-5;
+
+    int k1cap = 0, k3cap = 0, qcap = 0;
+    DevBuf X64, X32, Z64, Z32;
+    int k1 = 0, k3 = 0;
+    std::vector<int> uoff, uw, woff, ww;
+    std::set<std::pair<int, int>> used_u, used_w;
+
+    DevBuf P32, P64, W64a, W64b;  // product / work buffers (rows x qcap)
+    DevBuf T1, T3h;               // FP64 step-(iii) products
+    DevBuf T3core, Cdev;          // core product and Z^T T3core
+    DevBuf Hd, Hd2, Gd;           // small device scratch
+    std::vector<double> hbuf;
+
+    Solver(Ctx &c_, Tensor &t_, hipStream_t s_, int r_, int r3_, int p_, int st, int var, bool mx)
+        : c(c_), t(t_), s(s_), m(t_.m), n(t_.n), r(r_), r3(r3_), p(p_), stages(st),
+          variant(var), mixed(mx) {}
+
+    void sync() { HIPCHECK(hipStreamSynchronize(s)); }
+
+    template <class T_>
+    void d2h(T_ *h, const void *d, size_t count) {
+        HIPCHECK(hipMemcpyAsync(h, d, count * sizeof(T_), hipMemcpyDeviceToHost, s));
+        sync();
+    }
+    template <class T_>
+    void h2d(void *d, const T_ *h, size_t count) {
+        HIPCHECK(hipMemcpyAsync(d, h, count * sizeof(T_), hipMemcpyHostToDevice, s));
+        sync();
+    }
+
+    // -------------------------------------------------------- capacities
+    int ubar_w(int a) const {
+        if (a == 0 || variant == BKS_VARIANT_MAX) return uw[a];
+        return std::min(p, uw[a]);
+    }
+    int wbar_w(int b) const {
+        if (b == 0 || variant == BKS_VARIANT_MAX) return ww[b];
+        return std::min(p, ww[b]);
+    }
+
+    std::vector<std::array<int, 3>> stage_products(int stage) const {
+        std::vector<std::array<int, 3>> out;  // {kind 0=U 1=W, a, b}
+        if (stage == 1) return {{0, 0, 0}, {1, 0, 0}};
+        const int nu = (int)uw.size(), nw = (int)ww.size();
+        if (variant == BKS_VARIANT_MIN) {
+            int q = stage - 1;
+            if (q < nu && q < nw) out.push_back({0, q, q});
+            if (q < nu) out.push_back({1, q, q});
+            return out;
+        }
+        if (variant == BKS_VARIANT_BK) {
+            int q = stage - 1;
+            for (int a = 0; a < q; ++a) {
+                if (a < nu && q < nw) out.push_back({0, a, q});
+                if (q < nu && a < nw) out.push_back({0, q, a});
+            }
+            for (int a = 0; a < q; ++a)
+                if (q < nu) out.push_back({1, a, q});
+            return out;
+        }
+        for (int s_ = 1; s_ < std::max(nu, nw); ++s_) {
+            for (int a = 0; a < s_; ++a) {
+                if (a < nu && s_ < nw && !used_u.count({a, s_})) out.push_back({0, a, s_});
+                if (s_ < nu && a < nw && !used_u.count({s_, a})) out.push_back({0, s_, a});
+            }
+            if (s_ < nu && s_ < nw && !used_u.count({s_, s_})) out.push_back({0, s_, s_});
+        }
+        for (int s_ = 0; s_ < nu; ++s_)
+            for (int a = 0; a <= s_; ++a)
+                if (!used_w.count({a, s_})) out.push_back({1, a, s_});
+        return out;
+    }
+
+    // Simulate the schedule without deflation to size the device buffers.
+    void plan() {
+        uw = {r};
+        ww = {r3};
+        used_u.clear();
+        used_w.clear();
+        int qmax = std::max(r * r3, r * (r + 1) / 2);
+        int64_t K1 = r, K3 = r3;
+        for (int st = 1; st <= stages; ++st) {
+            auto prods = stage_products(st);
+            std::vector<int> nu, nw;
+            for (auto &pr : prods) {
+                if (pr[0] == 0) {
+                    used_u.insert({pr[1], pr[2]});
+                    int q = ubar_w(pr[1]) * wbar_w(pr[2]);
+                    qmax = std::max(qmax, q);
+                    nu.push_back(q);
+                } else {
+                    used_w.insert({pr[1], pr[2]});
+                    int pa = ubar_w(pr[1]), pb = ubar_w(pr[2]);
+                    int q = pr[1] == pr[2] ? pa * (pa + 1) / 2 : pa * pb;
+                    qmax = std::max(qmax, q);
+                    nw.push_back(q);
+                }
+            }
+            for (int q : nu) {
+                int w = (int)std::min<int64_t>(q, m - K1);
+                uw.push_back(w);
+                K1 += w;
+            }
+            for (int q : nw) {
+                int w = (int)std::min<int64_t>(q, n - K3);
+                ww.push_back(w);
+                K3 += w;
+            }
+        }
+        k1cap = (int)std::min<int64_t>(m, K1);
+        k3cap = (int)std::min<int64_t>(n, K3);
+        qcap = qmax;
+        if (k1cap > 4096 || k3cap > 4096) fail(BKS_EINVAL, "basis would exceed 4096 columns");
+    }
+
+    void allocate() {
+        X64.alloc((size_t)m * k1cap * 8);
+        Z64.alloc((size_t)n * k3cap * 8);
+        if (mixed) {
+            X32.alloc((size_t)m * k1cap * 4);
+            Z32.alloc((size_t)n * k3cap * 4);
+        }
+        const int64_t rows = std::max(m, n);
+        P64.alloc((size_t)rows * qcap * 8);
+        if (mixed) P32.alloc((size_t)rows * qcap * 4);
+        W64a.alloc((size_t)rows * std::max(qcap, std::max(r, r3)) * 8);
+        W64b.alloc((size_t)rows * std::max(qcap, std::max(r, r3)) * 8);
+        T1.alloc((size_t)m * r * r3 * 8);
+        T3h.alloc((size_t)n * (r * (r + 1) / 2) * 8);
+        const size_t Q = (size_t)k1cap * (k1cap + 1) / 2;
+        T3core.alloc((size_t)n * Q * (mixed ? 4 : 8));
+        Cdev.alloc((size_t)k3cap * Q * 8);
+        const size_t small = (size_t)std::max(k1cap, k3cap) * std::max(qcap, 64) * 8 + 4096;
+        Hd.alloc(small);
+        Hd2.alloc(small);
+        Gd.alloc((size_t)64 * 64 * 8 * 2 + 64 * 8);
+    }
+
+    double *Xcol(int col) { return X64.as<double>() + col; }
+    double *Zcol(int col) { return Z64.as<double>() + col; }
+
+    // Orthonormalise B (rows x q, ld) against the basis and append the kept
+    // columns; B is left projected off the old basis.  Returns kept count.
+    int orth_append(bool isU, double *B, int64_t ldb, int q, double tau) {
+        const int64_t rows = isU ? m : n;
+        int &k = isU ? k1 : k3;
+        const int cap = isU ? k1cap : k3cap;
+        DevBuf &Bas = isU ? X64 : Z64;
+        const int64_t ldbas = isU ? k1cap : k3cap;
+        int total = 0;
+        for (int c0 = 0; c0 < q; c0 += 64) {
+            const int qc = std::min(64, q - c0);
+            double *Bc = B + c0;
+            const int room = cap - k;
+            if (room <= 0) break;
+            std::vector<double> before2(qc);
+            colnorm2(Bc, ldb, rows, qc, Gd.as<double>(), c, s);
+            d2h(before2.data(), Gd.ptr, qc);
+            double *H = Hd.as<double>();
+            for (int pass = 0; pass < 2 && k > 0; ++pass) {
+                gemm_tn_f64(Bas.as<double>(), ldbas, Bc, ldb, rows, k, qc, H, qc, c, s);
+                gemm_nn_f64(Bas.as<double>(), ldbas, H, qc, rows, k, qc, -1.0, 1.0, Bc, ldb, s);
+            }
+            std::vector<double> Ghi((size_t)qc * qc), Glo((size_t)qc * qc);
+            gram_dd(Bc, ldb, rows, qc, Gd.as<double>(), Gd.as<double>() + 64 * 64, c, s);
+            d2h(Ghi.data(), Gd.ptr, (size_t)qc * qc);
+            d2h(Glo.data(), Gd.as<double>() + 64 * 64, (size_t)qc * qc);
+            std::vector<int> kept;
+            std::vector<double> T;
+            chol_drop(qc, Ghi, Glo, before2, tau, room, kept, T);
+            const int qk = (int)kept.size();
+            if (qk == 0) continue;
+            // Q1 = B T into W64a (rows x qk)
+            double *Q1 = W64a.as<double>();
+            h2d(H, T.data(), T.size());
+            gemm_nn_f64(Bc, ldb, H, qk, rows, qc, qk, 1.0, 0.0, Q1, qk, s);
+            // second pass: off the old basis, then CholQR on the block
+            if (k > 0) {
+                gemm_tn_f64(Bas.as<double>(), ldbas, Q1, qk, rows, k, qk, H, qk, c, s);
+                gemm_nn_f64(Bas.as<double>(), ldbas, H, qk, rows, k, qk, -1.0, 1.0, Q1, qk, s);
+            }
+            std::vector<double> G2h((size_t)qk * qk), G2l((size_t)qk * qk);
+            gram_dd(Q1, qk, rows, qk, Gd.as<double>(), Gd.as<double>() + 64 * 64, c, s);
+            d2h(G2h.data(), Gd.ptr, (size_t)qk * qk);
+            d2h(G2l.data(), Gd.as<double>() + 64 * 64, (size_t)qk * qk);
+            std::vector<double> ones(qk, 1.0);
+            std::vector<int> kept2;
+            std::vector<double> T2;
+            chol_drop(qk, G2h, G2l, ones, 0.0, qk, kept2, T2);
+            if ((int)kept2.size() != qk) fail(BKS_EDEVICE, "orthogonalisation lost rank");
+            h2d(H, T2.data(), T2.size());
+            gemm_nn_f64(Q1, qk, H, qk, rows, qk, qk, 1.0, 0.0, Bas.as<double>() + k, ldbas, s);
+            if (mixed) {
+                DevBuf &B32 = isU ? X32 : Z32;
+                convert_f64_f32(Bas.as<double>() + k, ldbas, B32.as<float>() + k, ldbas, rows, qk, s);
+            }
+            k += qk;
+            total += qk;
+        }
+        return total;
+    }
+
+    // Append a new block of `w` columns starting at `off`.
+    void add_block(bool isU, int off, int w) {
+        if (isU) {
+            uoff.push_back(off);
+            uw.push_back(w);
+        } else {
+            woff.push_back(off);
+            ww.push_back(w);
+        }
+    }
+
+    // A block's bars: first columns of block a (U) or b (W).
+    // product (kind U: FREE1(Ubar_a, Wbar_b); kind W: FREE3(Ubar_a, Ubar_b))
+    // into P64 (rows x q).  prec: BKS_F32 / BKS_F64 / BKS_F32IN_F64ACC.
+    int product(int kind, int a, int b, int prec, double *dst, int64_t ldd) {
+        if (kind == 0) {
+            const int py = ubar_w(a), pz = wbar_w(b);
+            if (py == 0 || pz == 0) return 0;
+            const int q = py * pz;
+            if (prec == BKS_F32) {
+                ttmc(c, t, BKS_FREE1, X32.as<float>() + uoff[a], k1cap, py, Z32.as<float>() + woff[b],
+                     k3cap, pz, false, BKS_F32, P32.ptr, q, s);
+                convert_f32_f64(P32.as<float>(), q, dst, ldd, m, q, s);
+            } else {
+                ttmc(c, t, BKS_FREE1, Xcol(uoff[a]), k1cap, py, Zcol(woff[b]), k3cap, pz, false, prec,
+                     dst, ldd, s);
+            }
+            return q;
+        }
+        const int pa = ubar_w(a), pb = ubar_w(b);
+        if (pa == 0 || pb == 0) return 0;
+        const bool sym = (a == b);
+        const int q = sym ? pa * (pa + 1) / 2 : pa * pb;
+        if (prec == BKS_F32) {
+            ttmc(c, t, BKS_FREE3, X32.as<float>() + uoff[a], k1cap, pa,
+                 sym ? nullptr : (const void *)(X32.as<float>() + uoff[b]), k1cap, pb, sym, BKS_F32,
+                 P32.ptr, q, s);
+            convert_f32_f64(P32.as<float>(), q, dst, ldd, n, q, s);
+        } else {
+            ttmc(c, t, BKS_FREE3, Xcol(uoff[a]), k1cap, pa,
+                 sym ? nullptr : (const void *)Xcol(uoff[b]), k1cap, pb, sym, prec, dst, ldd, s);
+        }
+        return q;
+    }
+
+    // Load a host column-major start (rows x w) into the basis and orthonormalise.
+    void load_start(bool isU, const double *h, int w) {
+        const int64_t rows = isU ? m : n;
+        const int64_t ld = isU ? k1cap : k3cap;
+        std::vector<double> rm((size_t)rows * ld, 0.0);
+        for (int64_t i = 0; i < rows; ++i)
+            for (int j = 0; j < w; ++j) rm[(size_t)i * ld + j] = h[(size_t)j * rows + i];
+        DevBuf &Bas = isU ? X64 : Z64;
+        h2d(Bas.ptr, rm.data(), rm.size());
+        reset_basis(isU, w);
+    }
+
+    // Orthonormalise columns [0, w) of the basis in place (CholQR twice) and
+    // make them the only block.
+    void reset_basis(bool isU, int w) {
+        const int64_t rows = isU ? m : n;
+        const int64_t ld = isU ? k1cap : k3cap;
+        DevBuf &Bas = isU ? X64 : Z64;
+        double *W = W64b.as<double>();
+        for (int pass = 0; pass < 2; ++pass) {
+            copy2d_f64(Bas.as<double>(), ld, W, w, rows, w, s);
+            std::vector<double> Gh((size_t)w * w), Gl((size_t)w * w);
+            gram_dd(W, w, rows, w, Gd.as<double>(), Gd.as<double>() + 64 * 64, c, s);
+            d2h(Gh.data(), Gd.ptr, (size_t)w * w);
+            d2h(Gl.data(), Gd.as<double>() + 64 * 64, (size_t)w * w);
+            std::vector<double> ones(w, 1.0), T;
+            std::vector<int> kept;
+            chol_drop(w, Gh, Gl, ones, 0.0, w, kept, T);
+            if ((int)kept.size() != w) fail(BKS_EINVAL, "start matrix is rank deficient");
+            h2d(Hd.ptr, T.data(), T.size());
+            gemm_nn_f64(W, w, Hd.as<double>(), w, rows, w, w, 1.0, 0.0, Bas.as<double>(), ld, s);
+        }
+        if (mixed) {
+            DevBuf &B32 = isU ? X32 : Z32;
+            convert_f64_f32(Bas.as<double>(), ld, B32.as<float>(), ld, rows, w, s);
+        }
+        if (isU) {
+            k1 = w;
+            uoff = {0};
+            uw = {w};
+            used_u.clear();
+        } else {
+            k3 = w;
+            woff = {0};
+            ww = {w};
+            used_w.clear();
+        }
+    }
+
+    // ------------------------------------------------------ step (iii)/(iv)
+    struct StepOut {
+        double rel, normF;
+        std::vector<double> F1;   // r x r*r3 (row-major)
+        std::vector<double> s1, s3;
+    };
+
+    StepOut bk_step() {
+        // FP64 accumulation over the tensor's own values (FP32 values are exact in FP64)
+        const int prec = BKS_F64;
+        const int q1 = r * r3, q3 = r * (r + 1) / 2;
+        StepOut o;
+        // T1 = A.(U0, W0)_{2,3};  T3 = A.(U0, U0)_{1,2} (sym-half)
+        ttmc(c, t, BKS_FREE1, Xcol(0), k1cap, r, Zcol(0), k3cap, r3, false, prec, T1.ptr, q1, s);
+        ttmc(c, t, BKS_FREE3, Xcol(0), k1cap, r, nullptr, 0, 0, true, prec, T3h.ptr, q3, s);
+        // F_(1) = U0^T T1
+        o.F1.assign((size_t)r * q1, 0.0);
+        gemm_tn_f64(Xcol(0), k1cap, T1.as<double>(), q1, m, r, q1, Hd.as<double>(), q1, c, s);
+        d2h(o.F1.data(), Hd.ptr, o.F1.size());
+        // U1, W1 and the R factors
+        // R1 = U1^T (I - U0 U0^T) T1 = U1^T T1 and R3 = W1^T T3 since U1 is
+        // orthogonal to U0 and W1 to W0.
+        double *B = P64.as<double>();
+        copy2d_f64(T1.as<double>(), q1, B, q1, m, q1, s);
+        const int kU = orth_append(true, B, q1, q1, tau64);
+        add_block(true, r, kU);
+        std::vector<double> R1((size_t)kU * q1, 0.0);
+        if (kU > 0) {
+            gemm_tn_f64(Xcol(r), k1cap, T1.as<double>(), q1, m, kU, q1, Hd.as<double>(), q1, c, s);
+            d2h(R1.data(), Hd.ptr, R1.size());
+        }
+        copy2d_f64(T3h.as<double>(), q3, B, q3, n, q3, s);
+        const int kW = orth_append(false, B, q3, q3, tau64);
+        add_block(false, r3, kW);
+        std::vector<double> R3h((size_t)kW * q3, 0.0);
+        if (kW > 0) {
+            gemm_tn_f64(Zcol(r3), k3cap, T3h.as<double>(), q3, n, kW, q3, Hd.as<double>(), q3, c, s);
+            d2h(R3h.data(), Hd.ptr, R3h.size());
+        }
+        used_u.insert({0, 0});
+        used_w.insert({0, 0});
+        // F(a,b,c) = F1[a][b + r c];  F_(3)[c][a + r b]
+        std::vector<double> F3((size_t)r3 * r * r);
+        double f2 = 0.0;
+        for (int a = 0; a < r; ++a)
+            for (int b = 0; b < r; ++b)
+                for (int cc = 0; cc < r3; ++cc) {
+                    const double v = o.F1[(size_t)a * q1 + b + r * cc];
+                    F3[(size_t)cc * r * r + a + r * b] = v;
+                    f2 += v * v;
+                }
+        // <H0, H1^1>_{-1} = R1 F_(1)^T ; <H0, H1^3>_{-3} = R3full F_(3)^T
+        double g1 = 0.0, g3 = 0.0;
+        for (int i = 0; i < kU; ++i)
+            for (int a = 0; a < r; ++a) {
+                double sacc = 0.0;
+                for (int x = 0; x < q1; ++x) sacc += R1[(size_t)i * q1 + x] * o.F1[(size_t)a * q1 + x];
+                g1 += sacc * sacc;
+            }
+        std::vector<double> R3f((size_t)kW * r * r, 0.0);
+        for (int i = 0; i < kW; ++i)
+            for (int b = 0; b < r; ++b)
+                for (int a = 0; a <= b; ++a) {
+                    const double v = R3h[(size_t)i * q3 + sym_idx(a, b)];
+                    R3f[(size_t)i * r * r + a + r * b] = v;
+                    R3f[(size_t)i * r * r + b + r * a] = v;
+                }
+        for (int i = 0; i < kW; ++i)
+            for (int cc = 0; cc < r3; ++cc) {
+                double sacc = 0.0;
+                for (int x = 0; x < r * r; ++x) sacc += R3f[(size_t)i * r * r + x] * F3[(size_t)cc * r * r + x];
+                g3 += sacc * sacc;
+            }
+        o.normF = std::sqrt(f2);
+        o.rel = o.normF > 0 ? std::sqrt(2.0 * g1 + g3) / o.normF : INFINITY;
+        // S-values (Section 2.6)
+        auto svals = [](int rows_, int cols, const std::vector<double> &M, int nv) {
+            // singular values of M (rows_ x cols) via eig of M M^T
+            std::vector<double> G((size_t)rows_ * rows_, 0.0), w(rows_), V((size_t)rows_ * rows_);
+            for (int i = 0; i < rows_; ++i)
+                for (int j = 0; j < rows_; ++j) {
+                    double sacc = 0.0;
+                    for (int x = 0; x < cols; ++x) sacc += M[(size_t)i * cols + x] * M[(size_t)j * cols + x];
+                    G[(size_t)i * rows_ + j] = sacc;
+                }
+            if (rows_ > 0) la::sym_eig(rows_, G.data(), w.data(), V.data());
+            std::vector<double> out;
+            for (int i = 0; i < std::min(nv, rows_); ++i) out.push_back(std::sqrt(std::max(w[i], 0.0)));
+            return out;
+        };
+        o.s1 = svals(r, q1, o.F1, r);
+        auto t1 = svals(kU, q1, R1, 1);
+        o.s1.push_back(t1.empty() ? 0.0 : t1[0]);
+        o.s3 = svals(r3, r * r, F3, r3);
+        auto t3 = svals(kW, r * r, R3f, 1);
+        o.s3.push_back(t3.empty() ? 0.0 : t3[0]);
+        return o;
+    }
+
+    void expand(int from_stage) {
+        for (int st = from_stage; st <= stages; ++st) {
+            auto prods = stage_products(st);
+            // bars are taken from blocks existing at the start of the stage
+            struct P_ {
+                int kind, a, b;
+            };
+            std::vector<P_> us, ws;
+            for (auto &pr : prods) {
+                if (pr[0] == 0) {
+                    used_u.insert({pr[1], pr[2]});
+                    us.push_back({0, pr[1], pr[2]});
+                } else {
+                    used_w.insert({pr[1], pr[2]});
+                    ws.push_back({1, pr[1], pr[2]});
+                }
+            }
+            const int prec = mixed ? BKS_F32 : BKS_F64;
+            const double tau = mixed ? tau32 : tau64;
+            double *B = P64.as<double>();
+            for (auto &pr : us) {
+                int q = 0;
+                const int off = k1;
+                if (k1 < k1cap) q = product(0, pr.a, pr.b, prec, B, qcap);
+                const int got = q > 0 ? orth_append(true, B, qcap, q, tau) : 0;
+                add_block(true, off, got);
+            }
+            for (auto &pr : ws) {
+                int q = 0;
+                const int off = k3;
+                if (k3 < k3cap) q = product(1, pr.a, pr.b, prec, B, qcap);
+                const int got = q > 0 ? orth_append(false, B, qcap, q, tau) : 0;
+                add_block(false, off, got);
+            }
+        }
+    }
+
+    // C = A.(X, X, Z) as a k1 x k1 x k3 column-major host array.
+    void form_core(std::vector<double> &C) {
+        const int Q = k1 * (k1 + 1) / 2;
+        if (mixed) {
+            ttmc(c, t, BKS_FREE3, X32.ptr, k1cap, k1, nullptr, 0, 0, true, BKS_F32, T3core.ptr, Q, s);
+            gemm_tn_f32f64(Zcol(0), k3cap, T3core.as<float>(), Q, n, k3, Q, Cdev.as<double>(), Q, c, s);
+        } else {
+            ttmc(c, t, BKS_FREE3, X64.ptr, k1cap, k1, nullptr, 0, 0, true, BKS_F64, T3core.ptr, Q, s);
+            gemm_tn_f64(Zcol(0), k3cap, T3core.as<double>(), Q, n, k3, Q, Cdev.as<double>(), Q, c, s);
+        }
+        std::vector<double> Ch((size_t)k3 * Q);
+        d2h(Ch.data(), Cdev.ptr, Ch.size());
+        C.assign((size_t)k1 * k1 * k3, 0.0);
+        for (int cc = 0; cc < k3; ++cc)
+            for (int b = 0; b < k1; ++b)
+                for (int a = 0; a <= b; ++a) {
+                    const double v = Ch[(size_t)cc * Q + sym_idx(a, b)];
+                    C[a + (size_t)k1 * (b + (size_t)k1 * cc)] = v;
+                    C[b + (size_t)k1 * (a + (size_t)k1 * cc)] = v;
+                }
+        if (mixed) {
+            // FP64-accurate gradient-defining slices from the step-(iii) products
+            const int q1 = r * r3, q3 = r * (r + 1) / 2;
+            std::vector<double> XT1((size_t)k1 * q1), ZT3((size_t)k3 * q3);
+            gemm_tn_f64(Xcol(0), k1cap, T1.as<double>(), q1, m, k1, q1, Hd.as<double>(), q1, c, s);
+            d2h(XT1.data(), Hd.ptr, XT1.size());
+            gemm_tn_f64(Zcol(0), k3cap, T3h.as<double>(), q3, n, k3, q3, Hd.as<double>(), q3, c, s);
+            d2h(ZT3.data(), Hd.ptr, ZT3.size());
+            for (int a = 0; a < k1; ++a)
+                for (int b = 0; b < r; ++b)
+                    for (int cc = 0; cc < r3; ++cc) {
+                        const double v = XT1[(size_t)a * q1 + b + r * cc];
+                        C[a + (size_t)k1 * (b + (size_t)k1 * cc)] = v;
+                        C[b + (size_t)k1 * (a + (size_t)k1 * cc)] = v;
+                    }
+            for (int cc = 0; cc < k3; ++cc)
+                for (int b = 0; b < r; ++b)
+                    for (int a = 0; a <= b; ++a) {
+                        const double v = ZT3[(size_t)cc * q3 + sym_idx(a, b)];
+                        C[a + (size_t)k1 * (b + (size_t)k1 * cc)] = v;
+                        C[b + (size_t)k1 * (a + (size_t)k1 * cc)] = v;
+                    }
+        }
+    }
+
+    // U0 = X P, W0 = Z S (eq. tks1), orthonormalised, as the new single blocks.
+    void restart(const std::vector<double> &P, const std::vector<double> &S) {
+        double *W = W64a.as<double>();
+        h2d(Hd.ptr, P.data(), P.size());
+        gemm_nn_f64(Xcol(0), k1cap, Hd.as<double>(), r, m, k1, r, 1.0, 0.0, W, r, s);
+        copy2d_f64(W, r, Xcol(0), k1cap, m, r, s);
+        reset_basis(true, r);
+        h2d(Hd.ptr, S.data(), S.size());
+        gemm_nn_f64(Zcol(0), k3cap, Hd.as<double>(), r3, n, k3, r3, 1.0, 0.0, W, r3, s);
+        copy2d_f64(W, r3, Zcol(0), k3cap, n, r3, s);
+        reset_basis(false, r3);
+    }
+
+    void outputs(double *U, double *W, double *F, const std::vector<double> &F1) {
+        std::vector<double> h((size_t)m * k1cap);
+        if (U) {
+            d2h(h.data(), X64.ptr, (size_t)m * k1cap);
+            for (int64_t i = 0; i < m; ++i)
+                for (int j = 0; j < r; ++j) U[(size_t)j * m + i] = h[(size_t)i * k1cap + j];
+        }
+        if (W) {
+            std::vector<double> hz((size_t)n * k3cap);
+            d2h(hz.data(), Z64.ptr, hz.size());
+            for (int64_t i = 0; i < n; ++i)
+                for (int j = 0; j < r3; ++j) W[(size_t)j * n + i] = hz[(size_t)i * k3cap + j];
+        }
+        if (F)
+            for (int a = 0; a < r; ++a)
+                for (int b = 0; b < r; ++b)
+                    for (int cc = 0; cc < r3; ++cc)
+                        F[a + (size_t)r * (b + (size_t)r * cc)] = F1[(size_t)a * r * r3 + b + r * cc];
+    }
+};
+
+void draw_start(uint64_t seed, int64_t rows, int w, std::vector<double> &out) {
+    std::mt19937_64 g(seed);
+    std::normal_distribution<double> N(0.0, 1.0);
+    out.resize((size_t)rows * w);
+    for (auto &v : out) v = N(g);
+}
+
+void fill_info(bks_info *info, const Solver::StepOut &o, int iters, bool conv, int k1, int k3,
+               double normA) {
+    if (!info) return;
+    info->outer_iters = iters;
+    info->converged = conv ? 1 : 0;
+    info->k1 = k1;
+    info->k3 = k3;
+    info->rel_grad = o.rel;
+    info->normF = o.normF;
+    info->normA = normA;
+    for (int i = 0; i < 65; ++i) {
+        info->svals1[i] = i < (int)o.s1.size() ? o.s1[i] : 0.0;
+        info->svals3[i] = i < (int)o.s3.size() ? o.s3[i] : 0.0;
+    }
+}
+
+}  // namespace
+
+int run_bks(Ctx &c, Tensor &t, const bks_params &prm, double *U, double *W, double *F,
+            bks_info *info, hipStream_t s) {
+    const double t0 = now_s();
+    const int r = prm.r, r3 = prm.r3;
+    if (r < 1 || r3 < 1 || r > t.m || r3 > t.n || r3 > r * (r + 1) / 2)
+        fail(BKS_EINVAL, "need 1 <= r <= m, 1 <= r3 <= min(n, r(r+1)/2)");
+    if (r > 64 || r3 > 64) fail(BKS_EINVAL, "r and r3 are limited to 64");
+    const int st = prm.s > 0 ? prm.s : 2;
+    const int p = prm.p > 0 ? prm.p : 4;
+    if (prm.variant < 0 || prm.variant > 2) fail(BKS_EINVAL, "variant");
+    if (prm.precision != BKS_PREC_FP64 && prm.precision != BKS_PREC_MIXED) fail(BKS_EINVAL, "precision");
+    const bool mixed = prm.precision == BKS_PREC_MIXED;
+    const double tol = prm.tol > 0 ? prm.tol : (mixed ? 1e-11 : 1e-13);
+    const double itol = prm.inner_tol > 0 ? prm.inner_tol : 1e-13;
+    const int max_outer = prm.max_outer > 0 ? prm.max_outer : 200;
+    const int hooi_warm = prm.hooi_warm >= 0 ? prm.hooi_warm : 5;
+    const int ng_max = prm.ng_max > 0 ? prm.ng_max : 50;
+
+    Solver S(c, t, s, r, r3, p, st, prm.variant, mixed);
+    S.plan();
+    S.allocate();
+    std::vector<double> h0;
+    if (prm.U0) {
+        S.load_start(true, prm.U0, r);
+    } else {
+        draw_start(prm.seed * 2 + 1, t.m, r, h0);
+        S.load_start(true, h0.data(), r);
+    }
+    if (prm.W0) {
+        S.load_start(false, prm.W0, r3);
+    } else {
+        draw_start(prm.seed * 2 + 2, t.n, r3, h0);
+        S.load_start(false, h0.data(), r3);
+    }
+    double te = 0, tc = 0, ti = 0, ts = 0;
+    double a = now_s();
+    Solver::StepOut o = S.bk_step();  // stage 1 of the initial expansion
+    ts += now_s() - a;
+    a = now_s();
+    S.expand(2);
+    te += now_s() - a;
+    int it = 0;
+    bool conv = false;
+    std::vector<double> C, P, Sm;
+    std::vector<double> rel_hist, f_hist;
+    long inner_newton = 0;
+    int last_k1 = S.k1, last_k3 = S.k3;
+    while (true) {
+        last_k1 = S.k1;
+        last_k3 = S.k3;
+        a = now_s();
+        S.form_core(C);
+        tc += now_s() - a;
+        a = now_s();
+        InnerInfo ii;
+        const bool warm = prm.inner_start == 1;
+        if (warm) {
+            // the restart point U0, W0 is the leading block of X, Z
+            P.assign((size_t)S.k1 * r, 0.0);
+            Sm.assign((size_t)S.k3 * r3, 0.0);
+            for (int j = 0; j < r; ++j) P[(size_t)j * r + j] = 1.0;
+            for (int j = 0; j < r3; ++j) Sm[(size_t)j * r3 + j] = 1.0;
+        }
+        inner_solve(C, S.k1, S.k3, r, r3, itol, hooi_warm, ng_max, warm, P, Sm, ii);
+        inner_newton += ii.newton;
+        ti += now_s() - a;
+        a = now_s();
+        S.restart(P, Sm);
+        o = S.bk_step();
+        ts += now_s() - a;
+        ++it;
+        rel_hist.push_back(o.rel);
+        f_hist.push_back(o.normF);
+        if (o.rel <= tol) {
+            conv = true;
+            break;
+        }
+        if (it >= max_outer) break;
+        a = now_s();
+        S.expand(2);
+        te += now_s() - a;
+    }
+    S.outputs(U, W, F, o.F1);
+    fill_info(info, o, it, conv, last_k1, last_k3, std::sqrt(t.frob2));
+    if (info) {
+        info->t_expand = te;
+        info->t_core = tc;
+        info->t_inner = ti;
+        info->t_step = ts;
+        info->t_total = now_s() - t0;
+        info->n_hist = (int)std::min<size_t>(512, rel_hist.size());
+        for (int i = 0; i < info->n_hist; ++i) {
+            info->rel_hist[i] = rel_hist[i];
+            info->normF_hist[i] = f_hist[i];
+        }
+    }
+    return conv ? BKS_OK : BKS_ENOTCONV;
+}
+
+// Symmetric HOOI (Section 5.1): U from the r leading left singular vectors
+// of T1 = A.(U, W)_{2,3}, then W from A.(U, U)_{1,2} with the new U (its
+// sym-half unfolding with off-diagonal columns weighted by sqrt(2) has the
+// Gram matrix of the full unfolding).  Singular vectors come from the small
+// Gram matrix: U = T1 V_r diag(sigma)^{-1}, then re-orthonormalised in FP64.
+// The G-gradient (global coordinates, Section 2.5) is evaluated every
+// `grad_every` iterations with FP64-accurate products.  In mixed precision
+// the iteration products are FP32 until the measured relative gradient is
+// below 1e-4, then FP64-accurate.
+int run_hooi(Ctx &c, Tensor &t, const hooi_params &prm, double *U, double *W, double *F,
+             bks_info *info, hipStream_t s) {
+    const double t0 = now_s();
+    const int r = prm.r, r3 = prm.r3;
+    if (r < 1 || r3 < 1 || r > t.m || r3 > t.n || r3 > r * (r + 1) / 2)
+        fail(BKS_EINVAL, "need 1 <= r <= m, 1 <= r3 <= min(n, r(r+1)/2)");
+    if (r > 64 || r3 > 64) fail(BKS_EINVAL, "r and r3 are limited to 64");
+    const bool mixed = prm.precision == BKS_PREC_MIXED;
+    const double tol = prm.tol > 0 ? prm.tol : 1e-13;
+    const int max_iter = prm.max_iter > 0 ? prm.max_iter : 2000;
+    const int every = prm.grad_every > 0 ? prm.grad_every : 10;
+    // the basis buffers of a Solver hold U (k1cap = r) and W (k3cap = r3)
+    Solver S(c, t, s, r, r3, 1, 1, BKS_VARIANT_BK, mixed);
+    S.k1cap = r;
+    S.k3cap = r3;
+    S.qcap = std::max(r * r3, r * (r + 1) / 2);
+    S.X64.alloc((size_t)t.m * r * 8);
+    S.Z64.alloc((size_t)t.n * r3 * 8);
+    if (mixed) {
+        S.X32.alloc((size_t)t.m * r * 4);
+        S.Z32.alloc((size_t)t.n * r3 * 4);
+        S.P32.alloc((size_t)std::max(t.m, t.n) * S.qcap * 4);
+    }
+    S.P64.alloc((size_t)std::max(t.m, t.n) * S.qcap * 8);
+    S.W64a.alloc((size_t)std::max(t.m, t.n) * S.qcap * 8);
+    S.W64b.alloc((size_t)std::max(t.m, t.n) * S.qcap * 8);
+    S.T1.alloc((size_t)t.m * r * r3 * 8);
+    S.T3h.alloc((size_t)t.n * (r * (r + 1) / 2) * 8);
+    const int qa = r * r3, qb = r * (r + 1) / 2;
+    // small scratch: Gram (q x q) / right factors, then a second region at
+    // offset `hoff` for the projection coefficients of the gradient
+    const size_t hoff = (size_t)std::max(qa, qb) * std::max(qa, qb) + (size_t)qa * r + 4096;
+    S.Hd.alloc((hoff + 64 * 64) * 8);
+    S.Gd.alloc((size_t)64 * 64 * 8 * 2 + 64 * 8);
+    std::vector<double> h0;
+    if (prm.U0) S.load_start(true, prm.U0, r);
+    else {
+        draw_start(prm.seed * 2 + 1, t.m, r, h0);
+        S.load_start(true, h0.data(), r);
+    }
+    if (prm.W0) S.load_start(false, prm.W0, r3);
+    else {
+        draw_start(prm.seed * 2 + 2, t.n, r3, h0);
+        S.load_start(false, h0.data(), r3);
+    }
+    const int q1 = r * r3, q3 = r * (r + 1) / 2;
+    // top `w` left singular vectors of M (rows x q, FP64 device, ld q) into
+    // the basis columns [0, w) via the Gram matrix, weights applied to columns
+    auto left_sv = [&](bool isU, double *M, int64_t rows, int q, int w,
+                       const std::vector<double> &colw) {
+        std::vector<double> G((size_t)q * q);
+        gemm_tn_f64(M, q, M, q, rows, q, q, S.Hd.as<double>(), q, c, s);
+        S.d2h(G.data(), S.Hd.ptr, G.size());
+        for (int i = 0; i < q; ++i)
+            for (int j = 0; j < q; ++j) G[(size_t)i * q + j] *= colw[i] * colw[j];
+        std::vector<double> V((size_t)q * w), ev(w);
+        la::top_eigvecs(q, G.data(), w, V.data(), ev.data());
+        for (int i = 0; i < q; ++i)
+            for (int j = 0; j < w; ++j) {
+                const double sg = std::sqrt(std::max(ev[j], 1e-300));
+                V[(size_t)i * w + j] *= colw[i] / sg;
+            }
+        S.h2d(S.Hd.ptr, V.data(), V.size());
+        DevBuf &Bas = isU ? S.X64 : S.Z64;
+        gemm_nn_f64(M, q, S.Hd.as<double>(), w, rows, q, w, 1.0, 0.0, Bas.as<double>(), w, s);
+        S.reset_basis(isU, w);
+    };
+    std::vector<double> w1(q1, 1.0), w3(q3, 1.0);
+    for (int b = 0; b < r; ++b)
+        for (int a = 0; a < b; ++a) w3[sym_idx(a, b)] = std::sqrt(2.0);
+    // global gradient at the current (U, W); also returns F_(1)
+    auto gradient = [&](std::vector<double> &F1, double &normF) {
+        // FP64 accumulation over the tensor's own values (FP32 values are exact in FP64)
+        const int prec = BKS_F64;
+        ttmc(c, t, BKS_FREE1, S.X64.ptr, r, r, S.Z64.ptr, r3, r3, false, prec, S.T1.ptr, q1, s);
+        ttmc(c, t, BKS_FREE3, S.X64.ptr, r, r, nullptr, 0, 0, true, prec, S.T3h.ptr, q3, s);
+        F1.assign((size_t)r * q1, 0.0);
+        gemm_tn_f64(S.X64.as<double>(), r, S.T1.as<double>(), q1, t.m, r, q1, S.Hd.as<double>(), q1, c, s);
+        S.d2h(F1.data(), S.Hd.ptr, F1.size());
+        // Gamma1 = T1 F_(1)^T (m x r); Gamma3 = T3full F_(3)^T via the sym-half columns
+        std::vector<double> F1t((size_t)q1 * r), M3((size_t)q3 * r3, 0.0);
+        double f2 = 0.0;
+        for (int a = 0; a < r; ++a)
+            for (int x = 0; x < q1; ++x) {
+                F1t[(size_t)x * r + a] = F1[(size_t)a * q1 + x];
+                f2 += F1[(size_t)a * q1 + x] * F1[(size_t)a * q1 + x];
+            }
+        for (int b = 0; b < r; ++b)
+            for (int a = 0; a <= b; ++a)
+                for (int cc = 0; cc < r3; ++cc) {
+                    double v = F1[(size_t)a * q1 + b + r * cc];
+                    if (a != b) v += F1[(size_t)b * q1 + a + r * cc];
+                    M3[(size_t)sym_idx(a, b) * r3 + cc] = v;
+                }
+        normF = std::sqrt(f2);
+        double g2[2];
+        for (int mode = 0; mode < 2; ++mode) {
+            const bool isU = mode == 0;
+            const int64_t rows = isU ? t.m : t.n;
+            const int w = isU ? r : r3;
+            const int q = isU ? q1 : q3;
+            double *Gm = S.W64a.as<double>();
+            S.h2d(S.Hd.ptr, isU ? F1t.data() : M3.data(), (size_t)q * w);
+            gemm_nn_f64(isU ? S.T1.as<double>() : S.T3h.as<double>(), q, S.Hd.as<double>(), w, rows,
+                        q, w, 1.0, 0.0, Gm, w, s);
+            DevBuf &Bas = isU ? S.X64 : S.Z64;
+            double *H = S.Hd.as<double>() + hoff;
+            gemm_tn_f64(Bas.as<double>(), w, Gm, w, rows, w, w, H, w, c, s);
+            gemm_nn_f64(Bas.as<double>(), w, H, w, rows, w, w, -1.0, 1.0, Gm, w, s);
+            std::vector<double> n2(w);
+            colnorm2(Gm, w, rows, w, S.Gd.as<double>(), c, s);
+            S.d2h(n2.data(), S.Gd.ptr, w);
+            g2[mode] = 0.0;
+            for (double v : n2) g2[mode] += v;
+        }
+        return normF > 0 ? std::sqrt(2.0 * g2[0] + g2[1]) / normF : INFINITY;
+    };
+    std::vector<double> F1;
+    double normF = 0.0;
+    double rel = gradient(F1, normF);
+    int it = 0;
+    std::vector<double> rel_hist;
+    bool conv = rel <= tol;
+    while (!conv && it < max_iter) {
+        const bool fp32 = mixed && rel > 1e-4;
+        const int prec = fp32 ? BKS_F32 : BKS_F64;
+        double *T = S.P64.as<double>();
+        if (fp32) {
+            ttmc(c, t, BKS_FREE1, S.X32.ptr, r, r, S.Z32.ptr, r3, r3, false, BKS_F32, S.P32.ptr, q1, s);
+            convert_f32_f64(S.P32.as<float>(), q1, T, q1, t.m, q1, s);
+        } else {
+            ttmc(c, t, BKS_FREE1, S.X64.ptr, r, r, S.Z64.ptr, r3, r3, false, prec, T, q1, s);
+        }
+        left_sv(true, T, t.m, q1, r, w1);
+        if (fp32) {
+            ttmc(c, t, BKS_FREE3, S.X32.ptr, r, r, nullptr, 0, 0, true, BKS_F32, S.P32.ptr, q3, s);
+            convert_f32_f64(S.P32.as<float>(), q3, T, q3, t.n, q3, s);
+        } else {
+            ttmc(c, t, BKS_FREE3, S.X64.ptr, r, r, nullptr, 0, 0, true, prec, T, q3, s);
+        }
+        left_sv(false, T, t.n, q3, r3, w3);
+        ++it;
+        if (it % every == 0 || it >= max_iter) {
+            rel = gradient(F1, normF);
+            rel_hist.push_back(rel);
+            conv = rel <= tol;
+        }
+    }
+    S.outputs(U, W, nullptr, F1);
+    if (F)
+        for (int a = 0; a < r; ++a)
+            for (int b = 0; b < r; ++b)
+                for (int cc = 0; cc < r3; ++cc)
+                    F[a + (size_t)r * (b + (size_t)r * cc)] = F1[(size_t)a * q1 + b + r * cc];
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->outer_iters = it;
+        info->converged = conv ? 1 : 0;
+        info->rel_grad = rel;
+        info->normF = normF;
+        info->normA = std::sqrt(t.frob2);
+        info->t_total = now_s() - t0;
+        info->n_hist = (int)std::min<size_t>(512, rel_hist.size());
+        for (int i = 0; i < info->n_hist; ++i) info->rel_hist[i] = rel_hist[i];
+    }
+    return conv ? BKS_OK : BKS_ENOTCONV;
+}
+
+}  // namespace bks
+
+using namespace bks;
+
+namespace {
+template <class F>
+int guard_solve(bks_ctx ctx, F f) {
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    try {
+        return f();
+    } catch (const Error &e) {
+        c->last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        c->last_error = "host allocation failed";
+        return BKS_ENOMEM;
+    } catch (const std::exception &e) {
+        c->last_error = e.what();
+        return BKS_EDEVICE;
+    }
+}
+}  // namespace
+
+extern "C" {
+
+int bks_solve(bks_ctx ctx, bks_tensor t, const bks_params *prm, double *U, double *W, double *F,
+              bks_info *info) {
+    if (!ctx || !t || !prm) return BKS_EINVAL;
+    return guard_solve(ctx, [&] {
+        Ctx *c = reinterpret_cast<Ctx *>(ctx);
+        std::lock_guard<std::mutex> g(c->mu);
+        HIPCHECK(hipSetDevice(c->device));
+        if (info) std::memset(info, 0, sizeof(*info));
+        return run_bks(*c, *reinterpret_cast<Tensor *>(t), *prm, U, W, F, info, c->stream);
+    });
+}
+
+int hooi_solve(bks_ctx ctx, bks_tensor t, const hooi_params *prm, double *U, double *W, double *F,
+               bks_info *info) {
+    if (!ctx || !t || !prm) return BKS_EINVAL;
+    return guard_solve(ctx, [&] {
+        Ctx *c = reinterpret_cast<Ctx *>(ctx);
+        std::lock_guard<std::mutex> g(c->mu);
+        HIPCHECK(hipSetDevice(c->device));
+        return run_hooi(*c, *reinterpret_cast<Tensor *>(t), *prm, U, W, F, info, c->stream);
+    });
+}
+
+}  // extern "C"

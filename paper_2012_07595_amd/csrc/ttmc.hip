@@ -162,15 +162,36 @@ __global__ __launch_bounds__(64) void ttmc_wave(
     }
 }
 
+// Sum the partial rows of one split segment: 256 threads as (slot lane,
+// column); each lane sums a strided subset of the slots, then a fixed-order
+// tree over the lanes in LDS (deterministic).
 template <typename CT>
-__global__ __launch_bounds__(64) void ttmc_fixup(const Fixup *__restrict__ fix,
-                                                 const CT *__restrict__ partial, int q,
-                                                 CT *__restrict__ out, int64_t ldo) {
+__global__ __launch_bounds__(256) void ttmc_fixup(const Fixup *__restrict__ fix,
+                                                  const CT *__restrict__ partial, int q,
+                                                  CT *__restrict__ out, int64_t ldo) {
+    __shared__ CT red[256];
     const Fixup f = fix[blockIdx.x];
-    for (int col = threadIdx.x; col < q; col += 64) {
+    const int cols = q < 256 ? q : 256;
+    int lanes = 256 / cols;
+    int pw = 1;
+    while (pw * 2 <= lanes) pw *= 2;
+    lanes = pw;
+    const int tid = threadIdx.x;
+    const int col_l = tid % cols, sl = tid / cols;
+    for (int c0 = 0; c0 < q; c0 += cols) {
+        const int col = c0 + col_l;
         CT s = CT(0);
-        for (int x = 0; x < f.nslots; ++x) s += partial[(int64_t)(f.first_slot + x) * q + col];
-        out[(int64_t)f.seg * ldo + col] = s;
+        if (sl < lanes && col < q)
+            for (int x = sl; x < f.nslots; x += lanes)
+                s += partial[(int64_t)(f.first_slot + x) * q + col];
+        red[tid] = s;
+        __syncthreads();
+        for (int w = lanes / 2; w > 0; w >>= 1) {
+            if (sl < w) red[tid] += red[tid + w * cols];
+            __syncthreads();
+        }
+        if (sl == 0 && col < q) out[(int64_t)f.seg * ldo + col] = red[tid];
+        __syncthreads();
     }
 }
 
@@ -346,10 +367,85 @@ void launch_sym_wide(const Segmented &o, const VT *val, const CT *X, int64_t ldx
 }  // namespace
 
 constexpr int kWideThreshold = 24;
+constexpr int kWideThresholdPublic = kWideThreshold;
+
+static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, int p1,
+                        const void *B2, int64_t ld2, int p2, bool sym_half, int prec, void *out,
+                        int64_t ldo, hipStream_t s);
+
+// Algorithmic traffic and flops of one product: the stored tensor read once
+// (two 4-byte indices and the value per stored entry; the mode-3 product
+// reads one index), each factor read once, the output written once; 2 flops
+// per fused multiply-add.
+static void ttmc_cost(const Tensor &t, int op, int p1, int p2, bool sym, bool same, int prec,
+                      std::string &name, double &bytes, double &flops) {
+    const double eb = prec == BKS_F32 ? 4.0 : 8.0;
+    const double vb = (prec == BKS_F64 && t.has64) ? 8.0 : 4.0;
+    const double nnz = (double)t.nnz, m = (double)t.m, n = (double)t.n, P = (double)t.npairs;
+    const char *suf = prec == BKS_F32 ? "_f32" : (prec == BKS_F64 ? "_f64" : "_f32in");
+    if (op == BKS_FREE3) {
+        const double px = p1, py = sym || same ? p1 : p2;
+        const double q = sym ? px * (px + 1) / 2 : px * py;
+        bytes = nnz * (8.0 + vb) + m * (px + (sym || same ? 0.0 : py)) * eb + n * q * eb;
+        flops = sym ? 2.0 * nnz * px * px : 4.0 * nnz * px * py;
+        name = std::string(sym ? (p1 > kWideThresholdPublic ? "free3_sym_wide" : "free3_sym") : "free3") + suf;
+    } else if (op == BKS_FREE1) {
+        bytes = nnz * (8.0 + vb) + m * p1 * eb + n * p2 * eb + m * (double)p1 * p2 * eb;
+        flops = 4.0 * nnz * p1 * p2;
+        name = std::string("free1") + suf;
+    } else {
+        bytes = nnz * (4.0 + vb) + P * 8.0 + n * p2 * eb + P * p2 * eb;
+        flops = 2.0 * nnz * p2;
+        name = std::string("mode3") + suf;
+    }
+}
 
 void ttmc(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, int p1, const void *B2,
-          int64_t ld2, int p2, bool sym_half, int prec, void *out, int64_t ldo,
-          hipStream_t s) {
+          int64_t ld2, int p2, bool sym_half, int prec, void *out, int64_t ldo, hipStream_t s) {
+    if (!c.prof) {
+        ttmc_launch(c, t, op, B1, ld1, p1, B2, ld2, p2, sym_half, prec, out, ldo, s);
+        return;
+    }
+    hipEvent_t a, b;
+    HIPCHECK(hipEventCreate(&a));
+    HIPCHECK(hipEventCreate(&b));
+    HIPCHECK(hipEventRecord(a, s));
+    ttmc_launch(c, t, op, B1, ld1, p1, B2, ld2, p2, sym_half, prec, out, ldo, s);
+    HIPCHECK(hipEventRecord(b, s));
+    std::string name;
+    double bytes, flops;
+    ttmc_cost(t, op, p1, p2, sym_half, B2 == nullptr || B2 == B1, prec, name, bytes, flops);
+    c.prof_record(name, a, b, bytes, flops);
+}
+
+void Ctx::prof_record(const std::string &name, hipEvent_t a, hipEvent_t b, double bytes,
+                      double flops) {
+    std::lock_guard<std::mutex> g(prof_mu);
+    ProfClass &pc = prof_stats[name];
+    pc.calls += 1;
+    pc.bytes += bytes;
+    pc.flops += flops;
+    pc.pending.emplace_back(a, b);
+}
+
+void Ctx::prof_flush() {
+    std::lock_guard<std::mutex> g(prof_mu);
+    for (auto &kv : prof_stats) {
+        for (auto &ev : kv.second.pending) {
+            HIPCHECK(hipEventSynchronize(ev.second));
+            float ms = 0.f;
+            HIPCHECK(hipEventElapsedTime(&ms, ev.first, ev.second));
+            kv.second.ms += ms;
+            (void)hipEventDestroy(ev.first);
+            (void)hipEventDestroy(ev.second);
+        }
+        kv.second.pending.clear();
+    }
+}
+
+static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, int p1,
+                        const void *B2, int64_t ld2, int p2, bool sym_half, int prec, void *out,
+                        int64_t ldo, hipStream_t s) {
     if (prec != BKS_F32 && prec != BKS_F64 && prec != BKS_F32IN_F64ACC)
         fail(BKS_EINVAL, "unknown precision");
     const bool dbl = prec != BKS_F32;
@@ -486,11 +582,11 @@ void ttmc(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, int p1, const 
     HIPCHECK(hipGetLastError());
     if (sc.nfix > 0) {
         if (dbl)
-            hipLaunchKernelGGL(ttmc_fixup<double>, dim3((unsigned)sc.nfix), dim3(64), 0, s,
+            hipLaunchKernelGGL(ttmc_fixup<double>, dim3((unsigned)sc.nfix), dim3(256), 0, s,
                                sc.fix.as<Fixup>(), static_cast<const double *>(partial), q,
                                static_cast<double *>(out), ldo);
         else
-            hipLaunchKernelGGL(ttmc_fixup<float>, dim3((unsigned)sc.nfix), dim3(64), 0, s,
+            hipLaunchKernelGGL(ttmc_fixup<float>, dim3((unsigned)sc.nfix), dim3(256), 0, s,
                                sc.fix.as<Fixup>(), static_cast<const float *>(partial), q,
                                static_cast<float *>(out), ldo);
         HIPCHECK(hipGetLastError());

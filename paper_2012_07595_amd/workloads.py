@@ -17,7 +17,14 @@ tensor holds it at (i, j, k) and (j, i, k).
 from __future__ import annotations
 
 import dataclasses
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
+
+
+def _threads() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
 
 
 @dataclasses.dataclass
@@ -72,19 +79,49 @@ def sparse_sym(m: int, n: int, nnz: int, zipf: float = 0.0, values: str = "norma
     rng = np.random.default_rng(seed)
     perm = rng.permutation(m).astype(np.int64)
     keys = np.empty(0, dtype=np.int64)
-    want = nnz
     rounds = 0
+    yield_est = 1.0
+    piece = 4_000_000
+    cdf = None
+    if zipf != 0.0:
+        w = np.arange(1, m + 1, dtype=np.float64) ** (-zipf)
+        cdf = np.cumsum(w)
+        cdf /= cdf[-1]
+
+    def draw_piece(args):
+        rnd, idx, d = args
+        prng = np.random.default_rng([seed, rnd, idx])
+        ab = []
+        for _ in range(2):
+            if cdf is None:
+                ab.append(prng.integers(0, m, size=d, dtype=np.int64))
+            else:
+                r = np.searchsorted(cdf, prng.random(d), side="right")
+                np.minimum(r, m - 1, out=r)
+                ab.append(perm[r])
+        kk = prng.integers(0, n, size=d, dtype=np.int64)
+        a, b = ab
+        return np.unique((kk * m + np.minimum(a, b)) * m + np.maximum(a, b))
+
     while keys.shape[0] < nnz:
-        draw = int(max(1024, (want - keys.shape[0]) * 1.25 + 64))
-        a = _zipf_labels(rng, m, draw, zipf, perm)
-        b = _zipf_labels(rng, m, draw, zipf, perm)
-        kk = rng.integers(0, n, size=draw, dtype=np.int64)
-        lo = np.minimum(a, b)
-        hi = np.maximum(a, b)
-        new = (kk * m + lo) * m + hi
-        keys = np.union1d(keys, new)
+        missing = nnz - keys.shape[0]
+        # size the round by the distinct-position yield seen so far (power-law
+        # indices repeat heavy (i, j) fibres, so most draws can be repeats)
+        draw = int(min(400_000_000, max(1024, missing / max(yield_est, 0.02) * 1.2 + 64)))
+        jobs = [(rounds, x, min(piece, draw - s0)) for x, s0 in enumerate(range(0, draw, piece))]
+        with ThreadPoolExecutor(max_workers=_threads()) as ex:
+            parts = list(ex.map(draw_piece, jobs))
+        before = keys.shape[0]
+        allk = np.concatenate([keys] + parts)
+        allk.sort(kind="stable")  # merges the sorted runs
+        keep = np.empty(allk.shape[0], dtype=bool)
+        if allk.shape[0]:
+            keep[0] = True
+            np.not_equal(allk[1:], allk[:-1], out=keep[1:])
+        keys = allk[keep]
+        yield_est = max((keys.shape[0] - before) / draw, 1e-4)
         rounds += 1
-        if rounds > 200:
+        if rounds > 60:
             raise RuntimeError("could not draw enough distinct positions")
     if keys.shape[0] > nnz:
         keep = rng.choice(keys.shape[0], size=nnz, replace=False)
@@ -209,6 +246,18 @@ def c1(seed: int = 1000) -> SymCOO:
 def c2(seed: int = 1001) -> SymCOO:
     """20000 x 20000 x 2000, 2e6 stored, Zipf(1.3) modes 1-2, |N(0,1)| FP32."""
     return sparse_sym(20_000, 2_000, 2_000_000, zipf=1.3, values="abs", seed=seed)
+
+
+def c2_planted(seed: int = 1001) -> SymCOO:
+    """The C2 law (20000 x 20000 x 2000, Zipf(1.3) modes 1-2, uniform mode 3,
+    |N(0,1)| FP32) with about 82k of its 2e6 stored entries given to a planted
+    rank-(5,5,5) part (superdiagonal core 3000, 2500, 2000, 1500, 1000; each
+    factor column on 40 rows / 20 slices).  The plain law has a flat mode-3
+    spectrum (uniform mode-3 indices), so its rank-(5,5,5) problem is
+    ill-conditioned; the plant gives it separated S-values."""
+    plant = planted(20_000, 2_000, (3000.0, 2500.0, 2000.0, 1500.0, 1000.0), 40, 20, seed + 7)
+    noise = sparse_sym(20_000, 2_000, 2_000_000 - plant.nnz, zipf=1.3, values="abs", seed=seed)
+    return merge(noise.astype(np.float64), plant).astype(np.float32)
 
 
 def c3(seed: int = 1002) -> SymCOO:

@@ -1,0 +1,171 @@
+"""GPU parity of bks_solve and hooi_solve with the FP64 oracle.
+
+Both sides start from the same seeded N(0,1) matrices (each orthonormalises
+them itself).  U, W and F are unique only up to rotations (eq. max), so the
+comparison is on subspaces -- sin of the largest principal angle,
+||(I - U_ref U_ref^T) U||_2 -- plus ||F|| and the S-values (Section 2.6).
+Bars: FP64 solver <= 1e-10 on well-conditioned problems; mixed-precision
+solver <= 1e-8 (the target for served solves)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import bks as obks, hooi as ohooi, sptensor
+from paper_2012_07595_amd import bks, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = bks.Ctx(0)
+    yield c
+    c.close()
+
+
+def otensor(coo):
+    return sptensor.from_coo(coo.m, coo.n, coo.i, coo.j, coo.k, coo.val.astype(np.float64))
+
+
+def dist(a, b):
+    return obks.subspace_distance(a, b)
+
+
+def compare(res, U, W, F, info, tol_angle, tol_f=1e-10):
+    du, dw = dist(res["U"], U), dist(res["W"], W)
+    nf_ref = np.sqrt(np.sum(res["F"] ** 2))
+    nf = np.sqrt(np.sum(F ** 2))
+    print(f"angle U {du:.2e} W {dw:.2e} |F| {nf:.12g} ref {nf_ref:.12g} iters {info.outer_iters} "
+          f"ref {res.get('outer_iters', res.get('iters'))} rel {info.rel_grad:.2e}")
+    assert du <= tol_angle and dw <= tol_angle
+    assert abs(nf - nf_ref) <= tol_f * nf_ref
+    # F itself is determined up to the rotations of U and W: compare the
+    # rotation-invariant mode-1 / mode-3 Gram spectra
+    s1 = np.sort(np.linalg.eigvalsh(F.reshape(F.shape[0], -1, order="F") @
+                                    F.reshape(F.shape[0], -1, order="F").T))
+    s1r = np.sort(np.linalg.eigvalsh(res["F"].reshape(F.shape[0], -1, order="F") @
+                                     res["F"].reshape(F.shape[0], -1, order="F").T))
+    np.testing.assert_allclose(s1, s1r, rtol=1e-8, atol=1e-10 * nf_ref ** 2)
+
+
+def test_bks_fp64_example1_like(ctx):
+    c = workloads.dense_signal_noise(40, 40, 2, 2, 1e-2, seed=3)
+    U0, W0 = workloads.random_start(40, 40, 2, 2, 5)
+    ref = obks.bks_solve(otensor(c), 2, 2, U0, W0)
+    t = ctx.upload_coo(c)
+    U, W, F, info, rc = ctx.solve(t, 2, 2, U0=U0, W0=W0, precision=bks.PREC_FP64)
+    assert rc == 0 and info.converged
+    assert info.rel_grad <= 1e-13
+    compare(ref, U, W, F, info, 1e-10)
+    np.testing.assert_allclose(info.svals1[:3], ref["svals1"], rtol=1e-6, atol=1e-12)
+    np.testing.assert_allclose(info.svals3[:3], ref["svals3"], rtol=1e-6, atol=1e-12)
+
+
+def test_bks_fp64_c1(ctx):
+    c = workloads.c1()
+    U0, W0 = workloads.random_start(c.m, c.n, 2, 2, 7)
+    ref = obks.bks_solve(otensor(c), 2, 2, U0, W0, max_outer=400)
+    t = ctx.upload_coo(c)
+    U, W, F, info, rc = ctx.solve(t, 2, 2, U0=U0, W0=W0, precision=bks.PREC_FP64, max_outer=400)
+    assert info.converged
+    compare(ref, U, W, F, info, 1e-9)
+
+
+def test_bks_planted_recovery(ctx):
+    P = workloads.planted(300, 40, (10.0, 5.0, 2.0), 8, 5, seed=3)
+    o = otensor(P)
+    A = sptensor.dense(o)
+    Uref = np.linalg.svd(A.reshape(300, -1), full_matrices=False)[0][:, :3]
+    Wref = np.linalg.svd(A.transpose(2, 0, 1).reshape(40, -1), full_matrices=False)[0][:, :3]
+    t = ctx.upload_coo(P)
+    U0, W0 = workloads.random_start(300, 40, 3, 3, 4)
+    for prec in (bks.PREC_FP64, bks.PREC_MIXED):
+        U, W, F, info, rc = ctx.solve(t, 3, 3, U0=U0, W0=W0, precision=prec)
+        assert info.converged
+        assert dist(Uref, U) < 1e-8 and dist(Wref, W) < 1e-8
+        assert abs(np.sqrt(np.sum(F ** 2)) - t.frob) < 1e-10 * t.frob
+
+
+def test_bks_n1_eigenproblem(ctx):
+    rng = np.random.default_rng(1)
+    G = rng.standard_normal((60, 20)) * (rng.random((60, 20)) < 0.3)
+    S = G @ G.T
+    o = sptensor.from_dense(S[:, :, None])
+    lam, V = np.linalg.eigh(S)
+    top = np.argsort(-np.abs(lam))[:3]
+    t = ctx.upload(60, 1, o.i, o.j, o.k, o.a)
+    U0, W0 = workloads.random_start(60, 1, 3, 1, 5)
+    U, W, F, info, rc = ctx.solve(t, 3, 1, U0=U0, W0=W0)
+    assert info.converged
+    assert dist(V[:, top], U) < 1e-10
+    assert abs(np.sum(F ** 2) - np.sum(lam[top] ** 2)) < 1e-10 * np.sum(lam[top] ** 2)
+
+
+@pytest.mark.parametrize("variant,s,p", [("min", 3, 4), ("max", 2, 4), ("bk", 3, 4), ("bk", 1, 4)])
+def test_bks_variants(ctx, variant, s, p):
+    c = workloads.dense_signal_noise(30, 30, 2, 2, 1e-2, seed=4)
+    U0, W0 = workloads.random_start(30, 30, 2, 2, 6)
+    ref = obks.bks_solve(otensor(c), 2, 2, U0, W0, variant=variant, s=s, p=p)
+    t = ctx.upload_coo(c)
+    U, W, F, info, rc = ctx.solve(t, 2, 2, U0=U0, W0=W0, variant=variant, s=s, p=p)
+    assert info.converged
+    compare(ref, U, W, F, info, 1e-10)
+    # near convergence the gradient directions fall to rounding level and
+    # are deflated, so the last basis size may differ; it never exceeds the
+    # schedule's size
+    assert info.k1 <= max(ref["k1"]) + 4 * p and info.k3 <= max(ref["k3"]) + 4 * p
+
+
+def c2_small(seed=1001):
+    return workloads.sparse_sym(5000, 400, 200_000, zipf=1.3, values="abs", seed=seed)
+
+
+def test_bks_mixed_vs_oracle_c2_shaped(ctx):
+    """Mixed precision (FP32 expansion and core products) reaches the FP64
+    oracle's fixed point to 1e-8 on a C2-shaped problem."""
+    c = c2_small()
+    U0, W0 = workloads.random_start(c.m, c.n, 5, 5, 11)
+    ref = obks.bks_solve(otensor(c), 5, 5, U0, W0)
+    t = ctx.upload_coo(c)
+    U, W, F, info, rc = ctx.solve(t, 5, 5, U0=U0, W0=W0, precision=bks.PREC_MIXED)
+    assert info.converged and info.rel_grad <= 1e-11
+    gap1 = ref["svals1"][4] - ref["svals1"][5]
+    gap3 = ref["svals3"][4] - ref["svals3"][5]
+    print("gaps", gap1 / ref["svals1"][0], gap3 / ref["svals3"][0])
+    compare(ref, U, W, F, info, 1e-8, tol_f=1e-12)
+    U2, W2, F2, info2, rc2 = ctx.solve(t, 5, 5, U0=U0, W0=W0, precision=bks.PREC_FP64)
+    assert info2.converged
+    compare(ref, U2, W2, F2, info2, 1e-9)
+
+
+def test_hooi_fp64_vs_oracle(ctx):
+    c = workloads.dense_signal_noise(40, 40, 2, 2, 1e-2, seed=3)
+    U0, W0 = workloads.random_start(40, 40, 2, 2, 5)
+    ref = ohooi.hooi_solve(otensor(c), 2, 2, U0, W0)
+    t = ctx.upload_coo(c)
+    U, W, F, info, rc = ctx.hooi(t, 2, 2, U0=U0, W0=W0, precision=bks.PREC_FP64)
+    assert info.converged
+    compare(ref, U, W, F, info, 1e-10)
+    assert info.outer_iters == ref["iters"]
+
+
+def test_hooi_mixed(ctx):
+    c = workloads.dense_signal_noise(40, 40, 2, 2, 1e-2, seed=3)
+    U0, W0 = workloads.random_start(40, 40, 2, 2, 5)
+    ref = ohooi.hooi_solve(otensor(c), 2, 2, U0, W0)
+    t = ctx.upload_coo(c.astype(np.float32))
+    U, W, F, info, rc = ctx.hooi(t, 2, 2, U0=U0, W0=W0, precision=bks.PREC_MIXED)
+    assert info.converged
+    assert dist(ref["U"], U) < 1e-6
+
+
+def test_solver_argument_errors(ctx):
+    c = workloads.sparse_sym(50, 10, 300, seed=1, dtype=np.float64)
+    t = ctx.upload_coo(c)
+    for (r, r3) in [(0, 1), (2, 4), (51, 1), (3, 11)]:
+        with pytest.raises(bks.BksError) as e:
+            ctx.solve(t, r, r3)
+        assert e.value.code == bks.EINVAL
+    U, W, F, info, rc = ctx.solve(t, 2, 2, max_outer=1)
+    assert rc in (0, bks.ENOTCONV)
