@@ -186,11 +186,19 @@ def newton_grassmann(C, P, S, tol, maxit):
     newton = 0
     rel = np.inf
     mu = 0.0
+    prev = np.inf
+    stall = 0
     while True:
         bl = blocks(C, P, S)
         _, _, rel = local_gradient(bl)
         if rel <= tol or it >= maxit:
             break
+        # rounding floor: two steps in a row that do not halve a gradient
+        # already below 1e-9 end the iteration
+        stall = stall + 1 if (rel < 1e-9 and rel > 0.5 * prev) else 0
+        if stall >= 2:
+            break
+        prev = rel
         b, A = newton_model(bl)
         H = -2.0 * A
         mu0 = 1e-8 * max(np.abs(np.diag(H)).max(), 1e-300)

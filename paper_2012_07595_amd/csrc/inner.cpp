@@ -83,6 +83,32 @@ void hosvd(const View &V, int r, int r3, std::vector<double> &P, std::vector<dou
     la::top_eigvecs(k3, G3.data(), r3, S.data());
 }
 
+// Leading w left singular vectors of M (rows x cols, row-major) through the
+// small Gram matrix: U = M V diag(sigma)^-1, re-orthonormalised.
+void lead_left(const std::vector<double> &M, int rows, int cols, int w, std::vector<double> &U) {
+    std::vector<double> G((size_t)cols * cols, 0.0);
+    for (int i = 0; i < rows; ++i) {
+        const double *mi = &M[(size_t)i * cols];
+        for (int a = 0; a < cols; ++a) {
+            const double v = mi[a];
+            if (v == 0.0) continue;
+            double *g = &G[(size_t)a * cols];
+            for (int b = 0; b <= a; ++b) g[b] += v * mi[b];
+        }
+    }
+    for (int a = 0; a < cols; ++a)
+        for (int b = 0; b < a; ++b) G[(size_t)b * cols + a] = G[(size_t)a * cols + b];
+    std::vector<double> Vv((size_t)cols * w), ev(w);
+    la::top_eigvecs(cols, G.data(), w, Vv.data(), ev.data());
+    for (int j = 0; j < w; ++j) {
+        const double sc = 1.0 / std::sqrt(std::max(ev[j], 1e-300));
+        for (int a = 0; a < cols; ++a) Vv[(size_t)a * w + j] *= sc;
+    }
+    U.assign((size_t)rows * w, 0.0);
+    la::gemm(rows, w, cols, M.data(), Vv.data(), U.data());
+    la::orthonormalize(rows, w, U.data());
+}
+
 // One symmetric HOOI iteration on the core (Section 5.1).
 void hooi_step(const View &V, int r, int r3, std::vector<double> &P, std::vector<double> &S) {
     const int k1 = V.k1, k3 = V.k3;
@@ -98,14 +124,7 @@ void hooi_step(const View &V, int r, int r3, std::vector<double> &P, std::vector
                 if (cv == 0.0) continue;
                 for (int j = 0; j < r; ++j) M1[(size_t)a * w1 + j + r * l] += cv * P[(size_t)b * r + j];
             }
-    std::vector<double> G((size_t)k1 * k1, 0.0);
-    la::gemm(k1, k1, w1, M1.data(), [&] {
-        std::vector<double> T((size_t)w1 * k1);
-        for (int a = 0; a < k1; ++a)
-            for (int x = 0; x < w1; ++x) T[(size_t)x * k1 + a] = M1[(size_t)a * w1 + x];
-        return T;
-    }().data(), G.data());
-    la::top_eigvecs(k1, G.data(), r, P.data());
+    lead_left(M1, k1, w1, r, P);
     // M3(c, i + r*j) = sum_{a,b} C(a,b,c) P(a,i) P(b,j)
     const int w3 = r * r;
     std::vector<double> M3((size_t)k3 * w3, 0.0);
@@ -125,14 +144,7 @@ void hooi_step(const View &V, int r, int r3, std::vector<double> &P, std::vector
                 M3[(size_t)c * w3 + i + r * j] = s;
             }
     }
-    std::vector<double> G3((size_t)k3 * k3, 0.0);
-    for (int c = 0; c < k3; ++c)
-        for (int d = 0; d <= c; ++d) {
-            double s = 0.0;
-            for (int x = 0; x < w3; ++x) s += M3[(size_t)c * w3 + x] * M3[(size_t)d * w3 + x];
-            G3[(size_t)c * k3 + d] = G3[(size_t)d * k3 + c] = s;
-        }
-    la::top_eigvecs(k3, G3.data(), r3, S.data());
+    lead_left(M3, k3, w3, r3, S);
 }
 
 struct Blocks {
@@ -397,6 +409,8 @@ void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, do
     Blocks B;
     std::vector<double> G1, G3, H, Hs, d, Pn, Sn;
     double mu = 0.0;
+    double prev = INFINITY;
+    int stall = 0;
     while (true) {
         t0 = clk();
         rotate(V, P, S, r, r3, B);
@@ -404,6 +418,11 @@ void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, do
         info.rel = local_gradient(B, G1, G3, nf);
         info.t_rotate += clk() - t0;
         if (info.rel <= tol || info.iters >= ng_max) break;
+        // at the rounding floor the gradient stops shrinking: two steps in a
+        // row that do not halve it below 1e-9 end the iteration
+        stall = (info.rel < 1e-9 && info.rel > 0.5 * prev) ? stall + 1 : 0;
+        if (stall >= 2) break;
+        prev = info.rel;
         if (B.A1 * r + B.C1 * r3 == 0) break;
         t0 = clk();
         newton_matrix(B, H);
