@@ -251,6 +251,83 @@ class Ctx:
         return U, W, F, info, rc
 
 
+class Server:
+    """Continuous-batching BKS server (bks_server_*).  Output buffers are
+    held here until the request completes."""
+
+    def __init__(self, ctx: Ctx, max_active=4, host_workers=4, mem_budget=0):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        h = C.c_void_p()
+        prm = ServerParams(max_active, host_workers, mem_budget)
+        ctx.check(self.lib.bks_server_create(ctx.h, C.byref(prm), C.byref(h)))
+        self.h = h
+        self._out = {}
+
+    def _params(self, r, r3, precision, U0, W0, p, s, tol, max_outer, seed):
+        prm = Params(r, r3, s, p, 0, precision, tol, 0.0, max_outer, -1, 0, None, None, seed, 0)
+        keep = []
+        if U0 is not None:
+            u = np.asfortranarray(U0, dtype=np.float64)
+            w = np.asfortranarray(W0, dtype=np.float64)
+            keep += [u, w]
+            prm.U0 = u.ctypes.data
+            prm.W0 = w.ctypes.data
+        return prm, keep
+
+    def submit(self, t, r, r3, precision=PREC_MIXED, U0=None, W0=None, p=4, s=2, tol=0.0,
+               max_outer=0, seed=0, coo=None):
+        """Submit a solve of tensor `t`, or of host coordinates `coo` (then t
+        is None and the server uploads after admission).  Returns the id."""
+        m, n = (t.m, t.n) if t is not None else (coo.m, coo.n)
+        prm, keep = self._params(r, r3, precision, U0, W0, p, s, tol, max_outer, seed)
+        U = np.zeros((m, r), order="F")
+        W = np.zeros((n, r3), order="F")
+        F = np.zeros((r, r, r3), order="F")
+        rid = C.c_uint64()
+        if t is not None:
+            rc = self.lib.bks_server_submit(self.h, t.h, C.byref(prm), _ptr(U), _ptr(W), _ptr(F),
+                                            C.byref(rid))
+        else:
+            i = np.ascontiguousarray(coo.i, np.int32)
+            j = np.ascontiguousarray(coo.j, np.int32)
+            k = np.ascontiguousarray(coo.k, np.int32)
+            v = np.ascontiguousarray(coo.val, np.float32)
+            rc = self.lib.bks_server_submit_coo(self.h, m, n, int(i.shape[0]), _ptr(i), _ptr(j),
+                                                _ptr(k), _ptr(v), C.byref(prm), _ptr(U), _ptr(W),
+                                                _ptr(F), C.byref(rid))
+        if rc != OK:
+            raise BksError(rc, "submit refused")
+        self._out[rid.value] = (U, W, F, keep)
+        return rid.value
+
+    def poll(self, rid):
+        res = Result()
+        self.ctx.check(self.lib.bks_server_poll(self.h, rid, C.byref(res)))
+        return res
+
+    def wait(self, rid):
+        """Block until done; returns (U, W, F, result)."""
+        res = Result()
+        self.ctx.check(self.lib.bks_server_wait(self.h, rid, C.byref(res)))
+        U, W, F, _ = self._out.pop(rid)
+        return U, W, F, res
+
+    def now(self):
+        return self.lib.bks_server_now(self.h)
+
+    def close(self):
+        if self.h:
+            self.lib.bks_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Tensor:
     def __init__(self, ctx: Ctx, h):
         self.ctx = ctx

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -97,6 +98,8 @@ struct Ctx {
     std::mutex mu;
     std::mutex tensors_mu;
     std::vector<Tensor *> tensors;  // live tensors uploaded through this ctx
+    // optional bracket around host-side dense solves (serving: bounded pool)
+    std::function<void()> host_acquire, host_release;
     bool prof = false;
     std::mutex prof_mu;
     std::map<std::string, ProfClass> prof_stats;

@@ -672,6 +672,30 @@ void fill_info(bks_info *info, const Solver::StepOut &o, int iters, bool conv, i
 
 }  // namespace
 
+// Device bytes a bks_solve of an m x m x n tensor allocates (the buffers of
+// Solver::allocate plus the product workspaces), for admission control.
+size_t solve_footprint(int64_t m, int64_t n, const bks_params &prm) {
+    Ctx c;
+    Tensor t;
+    t.m = m;
+    t.n = n;
+    const bool mixed = prm.precision == BKS_PREC_MIXED;
+    Solver S(c, t, nullptr, prm.r, prm.r3, prm.p > 0 ? prm.p : 4, prm.s > 0 ? prm.s : 2,
+             prm.variant, mixed);
+    S.plan();
+    const size_t k1 = S.k1cap, k3 = S.k3cap, q = S.qcap, rows = (size_t)std::max(m, n);
+    const size_t Q = k1 * (k1 + 1) / 2;
+    size_t b = (size_t)m * k1 * 8 + (size_t)n * k3 * 8;
+    if (mixed) b += (size_t)m * k1 * 4 + (size_t)n * k3 * 4 + rows * q * 4;
+    b += rows * q * 8 + 2 * rows * std::max<size_t>(q, std::max(prm.r, prm.r3)) * 8;
+    b += (size_t)m * prm.r * prm.r3 * 8 + (size_t)n * (prm.r * (prm.r + 1) / 2) * 8;
+    b += (size_t)n * Q * (mixed ? 4 : 8) + k3 * Q * 8;
+    b += 2 * std::max(k1, k3) * std::max<size_t>(q, 64) * 8 + 64 * 64 * 16;
+    // product partials and the split reductions (grow-only workspaces)
+    b += (size_t)n * Q * 8 / 4 + rows * 64 * 8 + (size_t)(1 << 20) * 8;
+    return b;
+}
+
 int run_bks(Ctx &c, Tensor &t, const bks_params &prm, double *U, double *W, double *F,
             bks_info *info, hipStream_t s) {
     const double t0 = now_s();
@@ -735,7 +759,14 @@ int run_bks(Ctx &c, Tensor &t, const bks_params &prm, double *U, double *W, doub
             for (int j = 0; j < r; ++j) P[(size_t)j * r + j] = 1.0;
             for (int j = 0; j < r3; ++j) Sm[(size_t)j * r3 + j] = 1.0;
         }
-        inner_solve(C, S.k1, S.k3, r, r3, itol, hooi_warm, ng_max, warm, P, Sm, ii);
+        if (c.host_acquire) c.host_acquire();
+        try {
+            inner_solve(C, S.k1, S.k3, r, r3, itol, hooi_warm, ng_max, warm, P, Sm, ii);
+        } catch (...) {
+            if (c.host_release) c.host_release();
+            throw;
+        }
+        if (c.host_release) c.host_release();
         inner_newton += ii.newton;
         ti += now_s() - a;
         a = now_s();
