@@ -213,6 +213,74 @@ def ttmc_sweep(args):
         print(json.dumps({"op": name, "p": p2, "roofline": rl}), flush=True)
 
 
+def serving(args):
+    """C4-shaped serving trace (one JSON line): requests of different sizes and
+    ranks, uploaded by the server after admission; closed-loop throughput, then
+    Poisson arrivals at 0.7x that rate for the mixed-precision server and the
+    plain FP64 server on the same trace."""
+    import threading
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    reqs = workloads.c4_requests(count=args.requests, rate_per_s=1.0, nnz_range=(10_000, args.max_nnz))
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        coos = list(ex.map(workloads.request_tensor, reqs))
+    gen_s = time.perf_counter() - t0
+    starts = [workloads.random_start(q.m, q.n, q.r, q.r, q.seed + 1) for q in reqs]
+    assert torch.cuda.is_available()
+    ctx = bks.Ctx(0)
+
+    def run(precision, arrivals):
+        srv = bks.Server(ctx, max_active=args.slots, host_workers=args.slots)
+        ids = [None] * len(reqs)
+        t_begin = srv.now()
+
+        def submitter():
+            for q, req in enumerate(reqs):
+                if arrivals is not None:
+                    delay = t_begin + arrivals[q] - srv.now()
+                    if delay > 0:
+                        time.sleep(delay)
+                ids[q] = srv.submit(None, req.r, req.r, precision=precision, U0=starts[q][0],
+                                    W0=starts[q][1], coo=coos[q], tol=1e-11, max_outer=args.max_outer)
+        th = threading.Thread(target=submitter)
+        th.start()
+        th.join()
+        out = []
+        for q in range(len(reqs)):
+            U, W, F, res = srv.wait(ids[q])
+            out.append((U, W, res))
+        makespan = max(r.t_end for _, _, r in out) - t_begin
+        srv.close()
+        lat = np.array([r.t_end - r.t_submit for _, _, r in out])
+        return out, makespan, lat
+
+    closed, mk_closed, _ = run(bks.PREC_MIXED, None)
+    rate = 0.7 * len(reqs) / mk_closed
+    arr = np.cumsum(np.random.default_rng(1003).exponential(1.0 / rate, size=len(reqs)))
+    arr -= arr[0]
+    mixed, mk_m, lat_m = run(bks.PREC_MIXED, arr)
+    fp64, mk_f, lat_f = run(bks.PREC_FP64, arr)
+    ang = max(max(dist(a[0], b[0]), dist(a[1], b[1])) for a, b in zip(mixed, fp64))
+    conv = sum(int(r.info.converged) for _, _, r in mixed)
+    out = {
+        "metric": "BKS solves/s + p50/p99 latency (serving, Poisson arrivals)",
+        "requests": len(reqs), "slots": args.slots, "arrival_rate_per_s": round(rate, 3),
+        "closed_loop_solves_per_s": round(len(reqs) / mk_closed, 3),
+        "mixed": {"solves_per_s": round(len(reqs) / mk_m, 3), "p50_ms": round(1e3 * np.percentile(lat_m, 50), 1),
+                  "p99_ms": round(1e3 * np.percentile(lat_m, 99), 1), "converged": conv},
+        "fp64": {"solves_per_s": round(len(reqs) / mk_f, 3), "p50_ms": round(1e3 * np.percentile(lat_f, 50), 1),
+                 "p99_ms": round(1e3 * np.percentile(lat_f, 99), 1),
+                 "converged": sum(int(r.info.converged) for _, _, r in fp64)},
+        "max_angle_mixed_vs_fp64": ang,
+        "config": {"workload": f"C4-shaped: I~U[1e3,1e5], K~U[100,5000], nnz~U[1e4,{args.max_nnz:.0e}] "
+                               "Zipf(1.3)/uniform |N(0,1)| FP32 + planted rank-r, r in {2,3,5,8,10}",
+                   "latency": "upload + solve + result"},
+        "gen_s": round(gen_s, 1),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,12 +291,18 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--ttmc-sweep", action="store_true")
     ap.add_argument("--widths", type=int, nargs="*", default=[5, 10, 20])
+    ap.add_argument("--serving", action="store_true")
+    ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--max-nnz", type=int, default=5_000_000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
               "(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
         sys.exit(2)
-    if args.ttmc_sweep:
+    if args.serving:
+        serving(args)
+    elif args.ttmc_sweep:
         ttmc_sweep(args)
     else:
         run_bks(args)

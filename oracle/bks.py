@@ -102,6 +102,13 @@ def bks_solve(T: SymTensor, r: int, r3: int, U_init: np.ndarray, W_init: np.ndar
         k3s.append(Z.shape[1])
         C = core_tensor(T, X, Z)
         P, S, info = core.inner_solve(C, r, r3, inner_tol, hooi_iters, ng_max)
+        # eq. Fnon-decr needs the inner solve to end no lower than the current
+        # point E0 (the leading coordinates of X, Z); a HOSVD start can reach
+        # a lower local maximum, so then solve again from E0 (a reading)
+        E1 = np.eye(C.shape[0], r)
+        E3 = np.eye(C.shape[2], r3)
+        if core.objective(C, P, S) < core.objective(C, E1, E3) * (1.0 - 1e-14):
+            P, S, _, _, _ = core.newton_grassmann(C, E1, E3, inner_tol, ng_max)
         inner.append(info)
         U0 = orthonormalize(X @ P)
         W0 = orthonormalize(Z @ S)

@@ -188,14 +188,15 @@ def newton_grassmann(C, P, S, tol, maxit):
     mu = 0.0
     prev = np.inf
     stall = 0
+    last_plain = False
     while True:
         bl = blocks(C, P, S)
         _, _, rel = local_gradient(bl)
         if rel <= tol or it >= maxit:
             break
-        # rounding floor: two steps in a row that do not halve a gradient
-        # already below 1e-9 end the iteration
-        stall = stall + 1 if (rel < 1e-9 and rel > 0.5 * prev) else 0
+        # rounding floor: two undamped Newton steps in a row that do not halve
+        # a gradient already below 1e-9 end the iteration
+        stall = stall + 1 if (last_plain and rel < 1e-9 and rel > 0.5 * prev) else 0
         if stall >= 2:
             break
         prev = rel
@@ -219,6 +220,7 @@ def newton_grassmann(C, P, S, tol, maxit):
             if objective(C, Pn, Sn) >= g0 * (1.0 - 4e-16):
                 P, S = Pn, Sn
                 accepted = True
+                last_plain = mu == 0.0
                 mu = mu / 4.0 if mu > mu0 else 0.0
                 break
             mu = max(4.0 * mu, mu0)
@@ -226,6 +228,7 @@ def newton_grassmann(C, P, S, tol, maxit):
         if accepted:
             newton += 1
         else:
+            last_plain = False
             P, S = hooi_step(C, P, S)
     return P, S, it, rel, newton
 

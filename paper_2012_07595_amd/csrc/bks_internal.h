@@ -80,6 +80,19 @@ struct Schedule {
 
 struct Tensor;
 
+// Device Cholesky solver for large inner Newton systems (devsolve.cpp).
+struct DevSolver {
+    void *handle = nullptr;  // rocblas_handle
+    DevBuf dA, db;
+    DevSolver() = default;
+    DevSolver(const DevSolver &) = delete;
+    DevSolver &operator=(const DevSolver &) = delete;
+    ~DevSolver();
+    // Solve H x = b (H N x N symmetric, row-major host) in place of b; false
+    // if H is not positive definite.
+    bool solve(hipStream_t s, int N, const double *H, double *b);
+};
+
 // Event-timed launches of one kernel class (profiling).
 struct ProfClass {
     int64_t calls = 0;
@@ -100,6 +113,7 @@ struct Ctx {
     std::vector<Tensor *> tensors;  // live tensors uploaded through this ctx
     // optional bracket around host-side dense solves (serving: bounded pool)
     std::function<void()> host_acquire, host_release;
+    DevSolver devsolve;
     bool prof = false;
     std::mutex prof_mu;
     std::map<std::string, ProfClass> prof_stats;

@@ -391,9 +391,15 @@ void retract(int k, int r, const std::vector<double> &Q, const double *D, std::v
 
 }  // namespace
 
+double inner_objective(const std::vector<double> &C, int k1, int k3, const std::vector<double> &P,
+                       const std::vector<double> &S, int r, int r3) {
+    View V{C.data(), k1, k3};
+    return objective(V, P, S, r, r3);
+}
+
 void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, double tol,
                  int hooi_warm, int ng_max, bool warm, std::vector<double> &P,
-                 std::vector<double> &S, InnerInfo &info) {
+                 std::vector<double> &S, InnerInfo &info, const BigSolve &big) {
     View V{C.data(), k1, k3};
     info = InnerInfo{};
     auto clk = [] {
@@ -411,6 +417,7 @@ void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, do
     double mu = 0.0;
     double prev = INFINITY;
     int stall = 0;
+    bool last_plain = false;
     while (true) {
         t0 = clk();
         rotate(V, P, S, r, r3, B);
@@ -418,9 +425,10 @@ void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, do
         info.rel = local_gradient(B, G1, G3, nf);
         info.t_rotate += clk() - t0;
         if (info.rel <= tol || info.iters >= ng_max) break;
-        // at the rounding floor the gradient stops shrinking: two steps in a
-        // row that do not halve it below 1e-9 end the iteration
-        stall = (info.rel < 1e-9 && info.rel > 0.5 * prev) ? stall + 1 : 0;
+        // at the rounding floor the gradient stops shrinking: two undamped
+        // Newton steps in a row that do not halve it below 1e-9 end the
+        // iteration (damped steps may legitimately progress slowly)
+        stall = (last_plain && info.rel < 1e-9 && info.rel > 0.5 * prev) ? stall + 1 : 0;
         if (stall >= 2) break;
         prev = info.rel;
         if (B.A1 * r + B.C1 * r3 == 0) break;
@@ -440,24 +448,35 @@ void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, do
         for (int attempt = 0; attempt < 40 && !accepted; ++attempt) {
             Hs = H;
             for (int i = 0; i < N; ++i) Hs[(size_t)i * N + i] += mu;
-            t0 = clk();
-            double piv = 0.0;
-            const bool pd = la::cholesky(N, Hs.data(), &piv);
-            info.t_chol += clk() - t0;
-            if (!pd) {
-                // the failed pivot bounds how far the spectrum reaches below 0
-                mu = std::max({4.0 * mu, mu0, mu + 2.0 * std::fabs(piv)});
-                continue;
-            }
             d.assign(N, 0.0);
             for (int i = 0; i < nd; ++i) d[i] = 4.0 * G1[i];
             for (int i = 0; i < N - nd; ++i) d[nd + i] = 2.0 * G3[i];
-            la::chol_solve(N, Hs.data(), d.data());
+            t0 = clk();
+            if (big && N >= kDeviceSolveMin) {
+                const bool pd = big(N, Hs.data(), d.data());
+                info.t_chol += clk() - t0;
+                if (!pd) {
+                    // no pivot from the device factorisation: escalate by 10
+                    mu = std::max(10.0 * mu, mu0);
+                    continue;
+                }
+            } else {
+                double piv = 0.0;
+                const bool pd = la::cholesky(N, Hs.data(), &piv);
+                info.t_chol += clk() - t0;
+                if (!pd) {
+                    // the failed pivot bounds how far the spectrum reaches below 0
+                    mu = std::max({4.0 * mu, mu0, mu + 2.0 * std::fabs(piv)});
+                    continue;
+                }
+                la::chol_solve(N, Hs.data(), d.data());
+            }
             retract(k1, r, B.Qp, d.data(), Pn);
             retract(k3, r3, B.Qs, d.data() + nd, Sn);
             const double g1 = objective(V, Pn, Sn, r, r3);
             if (g1 >= g0 * (1.0 - 4e-16)) {
                 accepted = true;
+                last_plain = (mu == 0.0);
                 P.swap(Pn);
                 S.swap(Sn);
                 mu = mu > mu0 ? mu / 4.0 : 0.0;
@@ -469,6 +488,7 @@ void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, do
         if (accepted) {
             ++info.newton;
         } else {
+            last_plain = false;
             hooi_step(V, r, r3, P, S);
         }
     }

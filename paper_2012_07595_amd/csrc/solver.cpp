@@ -761,7 +761,28 @@ int run_bks(Ctx &c, Tensor &t, const bks_params &prm, double *U, double *W, doub
         }
         if (c.host_acquire) c.host_acquire();
         try {
-            inner_solve(C, S.k1, S.k3, r, r3, itol, hooi_warm, ng_max, warm, P, Sm, ii);
+            const BigSolve big = [&](int N, const double *H, double *b) {
+                return c.devsolve.solve(s, N, H, b);
+            };
+            inner_solve(C, S.k1, S.k3, r, r3, itol, hooi_warm, ng_max, warm, P, Sm, ii, big);
+            if (!warm) {
+                // keep the outer objective non-decreasing (eq. Fnon-decr): if
+                // the HOSVD-started solve ends below the current point E0,
+                // solve again from E0 (accepted steps only increase g)
+                std::vector<double> P0((size_t)S.k1 * r, 0.0), S0((size_t)S.k3 * r3, 0.0);
+                for (int j = 0; j < r; ++j) P0[(size_t)j * r + j] = 1.0;
+                for (int j = 0; j < r3; ++j) S0[(size_t)j * r3 + j] = 1.0;
+                const double g_new = inner_objective(C, S.k1, S.k3, P, Sm, r, r3);
+                const double g_cur = inner_objective(C, S.k1, S.k3, P0, S0, r, r3);
+                if (g_new < g_cur * (1.0 - 1e-14)) {
+                    InnerInfo i2;
+                    inner_solve(C, S.k1, S.k3, r, r3, itol, hooi_warm, ng_max, true, P0, S0, i2,
+                                big);
+                    P.swap(P0);
+                    Sm.swap(S0);
+                    ii.newton += i2.newton;
+                }
+            }
         } catch (...) {
             if (c.host_release) c.host_release();
             throw;
