@@ -223,8 +223,11 @@ def serving(args):
     from concurrent.futures import ThreadPoolExecutor
     reqs = workloads.c4_requests(count=args.requests, rate_per_s=1.0, nnz_range=(10_000, args.max_nnz))
     t0 = time.perf_counter()
+    coos = []
     with ThreadPoolExecutor(max_workers=4) as ex:
-        coos = list(ex.map(workloads.request_tensor, reqs))
+        for q, coo in enumerate(ex.map(workloads.request_tensor, reqs)):
+            coos.append(coo)
+            print(f"[serving] generated request {q}", file=sys.stderr, flush=True)
     gen_s = time.perf_counter() - t0
     starts = [workloads.random_start(q.m, q.n, q.r, q.r, q.seed + 1) for q in reqs]
     assert torch.cuda.is_available()
@@ -246,6 +249,17 @@ def serving(args):
         th = threading.Thread(target=submitter)
         th.start()
         th.join()
+        pending = set(range(len(reqs)))
+        while pending:
+            for q in sorted(pending):
+                res = srv.poll(ids[q])
+                if res.done:
+                    pending.discard(q)
+                    print(f"[serving] prec {precision} request {q} m={reqs[q].m} n={reqs[q].n} "
+                          f"nnz={reqs[q].nnz} r={reqs[q].r} status {res.status} "
+                          f"iters {res.info.outer_iters} latency {res.t_end - res.t_submit:.3f}s",
+                          file=sys.stderr, flush=True)
+            time.sleep(0.05)
         out = []
         for q in range(len(reqs)):
             U, W, F, res = srv.wait(ids[q])

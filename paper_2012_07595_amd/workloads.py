@@ -304,12 +304,13 @@ def c4_requests(count: int = 512, rate_per_s: float = 10.0, seed: int = 1003,
 
 def request_tensor(req: Request, plant: bool = True) -> SymCOO:
     """Tensor of a serving request.  With ``plant`` a rank-(r, r, r) part with
-    separated S-values (superdiagonal core 300, 260, ..., factors on 12 rows
-    and 6 slices per column) replaces part of the entries: the plain law has a
-    flat mode-3 spectrum, so its rank-r problems are ill-conditioned."""
+    separated S-values (superdiagonal core 5000, 4600, ..., above the noise's
+    mean component; factors on 12 rows and 6 slices per column) replaces part
+    of the entries: the plain law has a flat mode-3 spectrum, so its rank-r
+    problems are ill-conditioned."""
     if not plant:
         return sparse_sym(req.m, req.n, req.nnz, zipf=1.3, values="abs", seed=req.seed)
-    p = planted(req.m, req.n, tuple(300.0 - 40.0 * x for x in range(req.r)), 12,
+    p = planted(req.m, req.n, tuple(5000.0 - 400.0 * x for x in range(req.r)), 12,
                 min(6, req.n // max(req.r, 1)), req.seed + 100_000)
     base = sparse_sym(req.m, req.n, max(req.nnz - p.nnz, 0), zipf=1.3, values="abs", seed=req.seed)
     return merge(base.astype(np.float64), p).astype(np.float32)
