@@ -52,6 +52,15 @@ def roofline_of(stats):
                 "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": None,
                 "launches": calls, "avg_launch_us": round(avg_s * 1e6, 2),
                 "algorithmic_flops_per_launch": fl / calls}
+    alu_peak = FP32_PEAK_TFLOPS if name.endswith("_f32") else FP64_PEAK_TFLOPS
+    if fl / (alu_peak * 1e12) > by / (HBM_PEAK_GBS * 1e9):
+        # more time at the vector ALU peak than at the HBM peak: ALU-bound
+        ach = fl / calls / avg_s / 1e12
+        return {"kernel": "ttmc_" + name, "bound": "alu", "achieved": round(ach, 3),
+                "peak": alu_peak, "unit": "TFLOP/s", "frac": round(ach / alu_peak, 4),
+                "traffic": None, "launches": calls, "avg_launch_us": round(avg_s * 1e6, 2),
+                "algorithmic_flops_per_launch": fl / calls,
+                "hbm_GBs": round(by / calls / avg_s / 1e9, 1)}
     ach = by / calls / avg_s / 1e9
     return {"kernel": "ttmc_" + name, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
@@ -183,6 +192,8 @@ def ttmc_sweep(args):
     cases = []
     for p in args.widths:
         cases += [("free3_sym", p, p), ("free3", p, p), ("free1", p, p), ("mode3", 0, p)]
+    if args.ops:
+        cases = [c for c in cases if c[0] in args.ops]
     for name, p1, p2 in cases:
         X = torch.randn(t.m, max(p1, 1), device=dev, dtype=torch.float32)
         Y = torch.randn(t.m, max(p1, 1), device=dev, dtype=torch.float32)
@@ -211,6 +222,16 @@ def ttmc_sweep(args):
         ctx.profile(False)
         rl = roofline_of(st)
         print(json.dumps({"op": name, "p": p2, "roofline": rl}), flush=True)
+    if args.copy_ref_mb:
+        # a plain device copy of known size: the reference that scales the
+        # FETCH_SIZE / WRITE_SIZE counters of the products above
+        nb = args.copy_ref_mb << 20
+        a = torch.ones(nb // 4, device=dev, dtype=torch.float32)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_ref_bytes": nb}), flush=True)
 
 
 def serving(args):
@@ -305,14 +326,17 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--ttmc-sweep", action="store_true")
     ap.add_argument("--widths", type=int, nargs="*", default=[5, 10, 20])
+    ap.add_argument("--ops", nargs="*", default=None,
+                    choices=["free3_sym", "free3", "free1", "mode3"])
+    ap.add_argument("--copy-ref-mb", type=int, default=0)
     ap.add_argument("--serving", action="store_true")
     ap.add_argument("--requests", type=int, default=64)
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--max-nnz", type=int, default=5_000_000)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              "(the multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path "
+              "runs on one GPU; sharding across GPUs is not built)", file=sys.stderr)
         sys.exit(2)
     if args.serving:
         serving(args)

@@ -46,8 +46,8 @@ struct Segmented {
     int64_t nseg = 0;
     int64_t nent = 0;
     DevBuf segptr;   // int64 [nseg + 1]
-    DevBuf c1;       // int32 [nent] (may be empty)
-    DevBuf c2;       // int32 [nent]
+    DevBuf c1;       // int32 pairs (c1, c2) interleaved [2 nent] (slice- and row-major)
+    DevBuf c2;       // int32 [nent] (pair pattern: k only)
     DevBuf v32;      // float [nent]
     DevBuf v64;      // double [nent] (only for FP64-valued tensors)
     std::vector<int64_t> h_segptr;  // host copy for schedule building
@@ -107,7 +107,8 @@ struct Ctx {
     std::string last_error;
     hipStream_t stream = nullptr;   // ctx-owned stream for solver work
     DevBuf ws_partial;              // TTMc partial rows
-    DevBuf ws_pack1, ws_pack2;      // packed factor copies
+    DevBuf ws_pack1, ws_pack2;      // dense-kernel partials
+    DevBuf ws_fac1, ws_fac2;        // block-packed factor copies for TTMc
     std::mutex mu;
     std::mutex tensors_mu;
     std::vector<Tensor *> tensors;  // live tensors uploaded through this ctx
@@ -143,7 +144,7 @@ struct Tensor {
 void build_formats(Tensor &t, const int32_t *i, const int32_t *j, const int32_t *k,
                    const void *val, int val_dtype, unsigned flags);
 
-// Schedules: heavy items take CH = E * kHeavySteps entries; light segments
+// Schedules: heavy items take CH = max(E * kHeavySteps, 2048) entries; light segments
 // are at most kLightMax entries long.
 constexpr int kHeavySteps = 32;
 constexpr int kLightMax = 48;

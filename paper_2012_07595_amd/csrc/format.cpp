@@ -195,19 +195,18 @@ void build_formats(Tensor &t, const int32_t *I, const int32_t *J, const int32_t 
         std::vector<int64_t> ptr(n + 1, 0);
         for (int64_t e = 0; e < S; ++e) ptr[sk[e] + 1]++;
         for (int64_t q = 0; q < n; ++q) ptr[q + 1] += ptr[q];
-        std::vector<int32_t> c1(S), c2(S);
+        std::vector<int32_t> c12(2 * S);
         std::vector<float> v32(S);
         for (int64_t e = 0; e < S; ++e) {
-            c1[e] = (int32_t)si[e];
-            c2[e] = (int32_t)sj[e];
+            c12[2 * e] = (int32_t)si[e];
+            c12[2 * e + 1] = (int32_t)sj[e];
             v32[e] = (float)sv[e];
         }
         Segmented &o = t.o3;
         o.nseg = n;
         o.nent = S;
         upload(o.segptr, ptr.data(), ptr.size() * 8);
-        upload(o.c1, c1.data(), S * 4);
-        upload(o.c2, c2.data(), S * 4);
+        upload(o.c1, c12.data(), S * 8);
         upload(o.v32, v32.data(), S * 4);
         if (f64) upload(o.v64, sv.data(), S * 8);
         o.h_segptr = std::move(ptr);
@@ -232,7 +231,7 @@ void build_formats(Tensor &t, const int32_t *I, const int32_t *J, const int32_t 
         }
         radix_sort(b, bits_for(((uint64_t)m * m) * n));
         std::vector<int64_t> rptr(m + 1, 0);
-        std::vector<int32_t> c1(F), c2(F);
+        std::vector<int32_t> c12(2 * F);
         std::vector<float> v32(F);
         std::vector<double> v64(f64 ? F : 0);
         std::vector<int64_t> pptr;
@@ -250,8 +249,8 @@ void build_formats(Tensor &t, const int32_t *I, const int32_t *J, const int32_t 
             int64_t col = (int64_t)(rc % (uint64_t)m), row = (int64_t)(rc / (uint64_t)m);
             double v = sv[b[q].idx];
             rptr[row + 1]++;
-            c1[q] = (int32_t)col;
-            c2[q] = (int32_t)kk;
+            c12[2 * q] = (int32_t)col;
+            c12[2 * q + 1] = (int32_t)kk;
             v32[q] = (float)v;
             if (f64) v64[q] = v;
             if (row <= col) {
@@ -274,8 +273,7 @@ void build_formats(Tensor &t, const int32_t *I, const int32_t *J, const int32_t 
         o.nseg = m;
         o.nent = F;
         upload(o.segptr, rptr.data(), rptr.size() * 8);
-        upload(o.c1, c1.data(), F * 4);
-        upload(o.c2, c2.data(), F * 4);
+        upload(o.c1, c12.data(), F * 8);
         upload(o.v32, v32.data(), F * 4);
         if (f64) upload(o.v64, v64.data(), F * 8);
         o.h_segptr = std::move(rptr);
@@ -298,7 +296,7 @@ void build_formats(Tensor &t, const int32_t *I, const int32_t *J, const int32_t 
 void build_schedule(const std::vector<int64_t> &segptr, int E, std::vector<Item> &items,
                     std::vector<Fixup> &fix, int64_t &nslots) {
     const int64_t nseg = (int64_t)segptr.size() - 1;
-    const int64_t CH = (int64_t)E * kHeavySteps;
+    const int64_t CH = std::max<int64_t>((int64_t)E * kHeavySteps, 2048);
     items.clear();
     fix.clear();
     nslots = 0;

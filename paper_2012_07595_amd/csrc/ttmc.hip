@@ -30,62 +30,63 @@ namespace bks {
 namespace {
 
 constexpr int kMaxP = 5;
+constexpr int kStageBytes = 10240;  // LDS staging budget of one wave
+constexpr int kIdxRegs = 4;         // batch entries held in registers per lane
 
 enum { MODE_TWO = 0, MODE_ONE = 1, MODE_M3 = 2 };
 enum { OUT_RECT = 0, OUT_SYM = 1 };
 
-struct BlockMap {
-    int8_t a[64];
-    int8_t b[64];
+// 16-byte vector of the compute type (the unit of every row gather); native
+// vector types keep register arrays of them in registers.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef int i32x2 __attribute__((ext_vector_type(2)));
+template <typename CT> struct Vec;
+template <> struct Vec<float> {
+    using T = f32x4;
+    static constexpr int V = 4;
+};
+template <> struct Vec<double> {
+    using T = f64x2;
+    static constexpr int V = 2;
 };
 
-template <typename CT, typename VT>
-__device__ __forceinline__ CT cv(VT v) {
-    return static_cast<CT>(v);
-}
+__host__ __device__ constexpr int pad_to(int x, int v) { return (x + v - 1) / v * v; }
 
-template <typename VT, typename CT, int PA, int PB, int MODE>
-__device__ __forceinline__ void accumulate(int64_t e, const int32_t *__restrict__ c1,
-                                           const int32_t *__restrict__ c2,
-                                           const VT *__restrict__ val,
-                                           const CT *__restrict__ F1, int64_t ld1,
-                                           const CT *__restrict__ F2, int64_t ld2, int a0,
-                                           int b0, int px, int py, CT (&acc)[PA][PB]) {
-    const int i2 = c2[e];
-    const CT v = cv<CT>(val[e]);
-    CT yb[PB];
+// Launch geometry shared by host and kernel.  Factors arrive block-packed:
+// row r of a packed factor holds its lane blocks one after another, block t
+// in [t*PAD, t*PAD + P) of the row and zero padding up to PAD (a multiple of
+// one 16-byte vector), so every gather is an aligned vector load.
+struct Geo {
+    int px, py;        // logical widths
+    int W1, W2;        // packed row widths (elements)
+    int PAD1, PAD2;    // padded lane-block widths
+    int G;             // lanes per entry
+    int ga;            // lane blocks across the first output index
+    int NB;            // entries staged per batch
+    int PS;            // LDS plane stride in 16-byte units (NB + 1)
+    int same;          // FREE3: Y rows are X rows
+    int outmode;
+    int q;             // output columns
+    int offv, offw, offa, offb;  // LDS element offsets (compute type)
+};
+
+// Read P consecutive row values of one staged entry.  Rows sit in LDS
+// unit-major: 16-byte unit u of entry e of a plane set is at
+// p + u * pse + e * V (pse = plane stride in elements), so lanes that read
+// consecutive entries read consecutive 16-byte words (no bank conflicts).
+template <typename CT, int P>
+__device__ __forceinline__ void lds_block(const CT *p, int pse, CT (&r)[P]) {
+    using VT4 = typename Vec<CT>::T;
+    constexpr int V = Vec<CT>::V;
 #pragma unroll
-    for (int b = 0; b < PB; ++b)
-        yb[b] = (b0 + b < py) ? F2[(int64_t)i2 * ld2 + b0 + b] : CT(0);
-    if constexpr (MODE == MODE_M3) {
+    for (int u = 0; u < P / V; ++u) {
+        const VT4 x = *reinterpret_cast<const VT4 *>(p + u * pse);
 #pragma unroll
-        for (int b = 0; b < PB; ++b) acc[0][b] += v * yb[b];
-    } else {
-        const int i1 = c1[e];
-        CT xa[PA];
-#pragma unroll
-        for (int a = 0; a < PA; ++a)
-            xa[a] = (a0 + a < px) ? v * F1[(int64_t)i1 * ld1 + a0 + a] : CT(0);
-#pragma unroll
-        for (int a = 0; a < PA; ++a)
-#pragma unroll
-            for (int b = 0; b < PB; ++b) acc[a][b] = fma(xa[a], yb[b], acc[a][b]);
-        if constexpr (MODE == MODE_TWO) {
-            // mirrored entry (j, i, k); absent on the diagonal i == j
-            const CT w = (i1 != i2) ? v : CT(0);
-            CT xa2[PA], yb2[PB];
-#pragma unroll
-            for (int a = 0; a < PA; ++a)
-                xa2[a] = (a0 + a < px) ? w * F1[(int64_t)i2 * ld1 + a0 + a] : CT(0);
-#pragma unroll
-            for (int b = 0; b < PB; ++b)
-                yb2[b] = (b0 + b < py) ? F2[(int64_t)i1 * ld2 + b0 + b] : CT(0);
-#pragma unroll
-            for (int a = 0; a < PA; ++a)
-#pragma unroll
-                for (int b = 0; b < PB; ++b) acc[a][b] = fma(xa2[a], yb2[b], acc[a][b]);
-        }
+        for (int t = 0; t < V; ++t) r[V * u + t] = x[t];
     }
+#pragma unroll
+    for (int t = P / V * V; t < P; ++t) r[t] = p[(t / V) * pse + (t % V)];
 }
 
 __device__ __forceinline__ int out_col(int alpha, int beta, int px, int outmode) {
@@ -93,34 +94,287 @@ __device__ __forceinline__ int out_col(int alpha, int beta, int px, int outmode)
     return alpha + px * beta;
 }
 
+// Lane group g of an entry owns output block (a, b): column-major over a
+// ga x gb grid for rectangular outputs, the upper triangle a <= b in
+// column order for the symmetric half, (0, g) for the mode-3 product.
+template <int MODE>
+__device__ __forceinline__ void lane_block(int g, const Geo &geo, int &a, int &b) {
+    if constexpr (MODE == MODE_M3) {
+        a = 0;
+        b = g;
+    } else {
+        if (geo.outmode == OUT_SYM) {
+            b = 0;
+            while ((b + 1) * (b + 2) / 2 <= g) ++b;
+            a = g - b * (b + 1) / 2;
+        } else {
+            b = g / geo.ga;
+            a = g - b * geo.ga;
+        }
+    }
+}
+
+// Stage the packed factor rows of `cnt` entries into LDS, NR rows per
+// entry (row_of(e, w), w < NR), each row U = W / V 16-byte units.  Lanes
+// work as U unit groups of spl = 64 / U entries (lane = u * spl + e), so
+// a store instruction writes consecutive words of one plane; row w, unit u
+// of entry e goes to dst + ((w * U + u) * PS + e) * V.  Each lane issues its
+// gathers for kGather / NR entries before the first LDS store so their
+// latencies overlap.  `after_issue()` runs once, right after the first
+// round of gathers is issued: that round is straight-line code, so loads
+// started there (the next batch's indices) stay in flight while the
+// gathered rows are stored.
+constexpr int kGather = 8;
+
+template <typename CT, int NR, typename RowOf>
+__device__ __forceinline__ void gather_round(const CT *__restrict__ F, int W, int cnt, int base,
+                                             int spl, int lu, RowOf row_of,
+                                             typename Vec<CT>::T (&r)[kGather / NR][NR]) {
+    using VT4 = typename Vec<CT>::T;
+    constexpr int V = Vec<CT>::V;
+#pragma unroll
+    for (int x = 0; x < kGather / NR; ++x) {
+        // every lane loads (entries past the end re-read entry 0's rows,
+        // which are in bounds), so the loads carry no control flow
+        const int e = base + x * spl;
+        const int ee = e < cnt ? e : 0;
+#pragma unroll
+        for (int w = 0; w < NR; ++w)
+            r[x][w] = *reinterpret_cast<const VT4 *>(F + row_of(ee, w) * W + lu * V);
+    }
+}
+
+template <typename CT, int NR>
+__device__ __forceinline__ void store_round(CT *dst, int U, int PS, int cnt, int base, int spl,
+                                            int lu, const typename Vec<CT>::T (&r)[kGather / NR][NR]) {
+    using VT4 = typename Vec<CT>::T;
+    constexpr int V = Vec<CT>::V;
+#pragma unroll
+    for (int x = 0; x < kGather / NR; ++x) {
+        const int e = base + x * spl;
+        if (e < cnt)
+#pragma unroll
+            for (int w = 0; w < NR; ++w)
+                *reinterpret_cast<VT4 *>(dst + ((int64_t)(w * U + lu) * PS + e) * V) = r[x][w];
+    }
+}
+
+template <typename CT, int NR, typename RowOf, typename Hook>
+__device__ __forceinline__ void stage_rows(const CT *__restrict__ F, int W, int PS, int cnt,
+                                           CT *dst, RowOf row_of, Hook after_issue) {
+    using VT4 = typename Vec<CT>::T;
+    constexpr int V = Vec<CT>::V;
+    const int U = W / V;
+    if (U > 64) {
+        after_issue();
+        for (int e = 0; e < cnt; ++e)
+            for (int w = 0; w < NR; ++w) {
+                const int64_t row = row_of(e, w);
+                for (int u = threadIdx.x; u < U; u += 64)
+                    *reinterpret_cast<VT4 *>(dst + ((int64_t)(w * U + u) * PS + e) * V) =
+                        *reinterpret_cast<const VT4 *>(F + row * W + u * V);
+            }
+        return;
+    }
+    const int spl = 64 / U;
+    const int lu = threadIdx.x / spl;
+    int ls = threadIdx.x - lu * spl;
+    const bool act = lu < U;
+    if (!act) ls = cnt;  // idle lanes: every entry they touch is past the end
+    const int luc = act ? lu : 0;
+    constexpr int K = kGather / NR;
+    VT4 r[K][NR];
+    gather_round<CT, NR>(F, W, cnt, ls, spl, luc, row_of, r);
+    after_issue();
+    store_round<CT, NR>(dst, U, PS, cnt, ls, spl, luc, r);
+    for (int base = ls + K * spl; base < cnt; base += K * spl) {
+        gather_round<CT, NR>(F, W, cnt, base, spl, luc, row_of, r);
+        store_round<CT, NR>(dst, U, PS, cnt, base, spl, luc, r);
+    }
+}
+
+// One work item per 64-lane wave.  Entries are taken in batches of NB:
+// the wave loads their index pairs and values coalesced, gathers every
+// factor row they touch into LDS with one aligned vector per lane (rows of
+// one entry are read by neighbouring lanes, so each row costs one cache
+// line), then each lane multiplies out its PA x PB output block from LDS.
+// Heavy items split a long segment into chunks (lanes stride the entries,
+// LDS tree at the end); light items hold whole short segments, one lane
+// group per segment.
 template <typename VT, typename CT, int PA, int PB, int MODE>
 __global__ __launch_bounds__(64) void ttmc_wave(
     const Item *__restrict__ items, const int64_t *__restrict__ segptr,
-    const int32_t *__restrict__ c1, const int32_t *__restrict__ c2,
-    const VT *__restrict__ val, const CT *__restrict__ F1, int64_t ld1,
-    const CT *__restrict__ F2, int64_t ld2, int px, int py, int G, BlockMap bm,
-    CT *__restrict__ out, int64_t ldo, CT *__restrict__ partial, int q, int outmode) {
-    __shared__ CT red[64 * PA * PB];
+    const int2 *__restrict__ c12, const int32_t *__restrict__ ck, const VT *__restrict__ val,
+    const CT *__restrict__ F1, const CT *__restrict__ F2, Geo geo,
+    CT *__restrict__ out, int64_t ldo, CT *__restrict__ partial) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    CT *lds = reinterpret_cast<CT *>(lds_raw);
+    i32x2 *s_idx = reinterpret_cast<i32x2 *>(lds_raw);
+    const i32x2 *__restrict__ cp = reinterpret_cast<const i32x2 *>(c12);
+    CT *s_v = lds + geo.offv;
+    CT *s_w = lds + geo.offw;
+    CT *s_a = lds + geo.offa;
+    CT *s_b = lds + geo.offb;
+
     const Item it = items[blockIdx.x];
     const int lane = threadIdx.x;
+    const int G = geo.G;
     const int E = 64 / G;
     const int el = lane / G;
     const int g = lane - el * G;
     const bool active = el < E;
-    const int a0 = active ? bm.a[g] * PA : 0;
-    const int b0 = active ? bm.b[g] * PB : 0;
+    int ba = 0, bb = 0;
+    if (active) lane_block<MODE>(g, geo, ba, bb);
+    const int offa = ba * geo.PAD1, offb = bb * geo.PAD2;
+    const bool heavy = it.seg_end < 0;
+    const int NB = geo.NB;
+
     CT acc[PA][PB];
 #pragma unroll
     for (int a = 0; a < PA; ++a)
 #pragma unroll
         for (int b = 0; b < PB; ++b) acc[a][b] = CT(0);
 
-    if (it.seg_end < 0) {
-        // heavy: one chunk of one segment
-        if (active)
-            for (int64_t e = it.beg + el; e < it.end; e += E)
-                accumulate<VT, CT, PA, PB, MODE>(e, c1, c2, val, F1, ld1, F2, ld2, a0, b0, px,
-                                                 py, acc);
+    int64_t beg, end, s0 = 0, s1 = 0;
+    int64_t myseg = -1;
+    if (heavy) {
+        beg = it.beg;
+        end = it.end;
+    } else {
+        beg = segptr[it.seg];
+        end = segptr[it.seg_end];
+        myseg = (int64_t)it.seg + el;
+        if (active && myseg < it.seg_end) {
+            s0 = segptr[myseg];
+            s1 = segptr[myseg + 1];
+        }
+    }
+
+    const int nA = MODE == MODE_TWO ? 2 : (MODE == MODE_ONE ? 1 : 0);
+    const int nB = MODE == MODE_TWO ? (geo.same ? 0 : 2) : 1;
+    // element offsets of this lane's first unit in each staged plane set
+    constexpr int V = Vec<CT>::V;
+    const int pse = geo.PS * V;
+    const int U1 = geo.W1 / V;
+    const int UB = (MODE == MODE_TWO && geo.same) ? U1 : geo.W2 / V;
+    const CT *rowsB = (MODE == MODE_TWO && geo.same) ? s_a : s_b;
+    const int pa0 = (offa / V) * pse, pa1 = (U1 + offa / V) * pse;
+    const int pb0 = (offb / V) * pse, pb1 = (UB + offb / V) * pse;
+
+    // index pairs and values of the next batch are loaded into registers
+    // while the current one is gathered and multiplied (NB <= 64 kIdxRegs)
+    i32x2 pc[kIdxRegs];
+    VT pv[kIdxRegs];
+    auto fetch = [&](int64_t b0) {
+        const int cnt = (int)min<int64_t>(NB, end - b0);
+#pragma unroll
+        for (int u = 0; u < kIdxRegs; ++u) {
+            // unconditional, clamped into the batch (see stage_rows)
+            const int x = min(lane + 64 * u, cnt - 1);
+            if constexpr (MODE == MODE_M3)
+                pc[u] = i32x2{0, ck[b0 + x]};
+            else
+                pc[u] = cp[b0 + x];
+            pv[u] = val[b0 + x];
+        }
+    };
+    if (beg < end) fetch(beg);
+    for (int64_t b0 = beg; b0 < end; b0 += NB) {
+        const int cnt = (int)min<int64_t>(NB, end - b0);
+#pragma unroll
+        for (int u = 0; u < kIdxRegs; ++u) {
+            const int x = lane + 64 * u;
+            if (x < cnt) {
+                const i32x2 c = pc[u];
+                s_idx[x] = c;
+                const CT v = static_cast<CT>(pv[u]);
+                s_v[x] = v;
+                if constexpr (MODE == MODE_TWO) s_w[x] = (c.x != c.y) ? v : CT(0);
+            }
+        }
+        __syncthreads();
+        // unconditional (the last batch re-reads itself) so no branch
+        // separates these loads from the gathers' waits
+        auto next = [&]() { fetch(b0 + NB < end ? b0 + NB : b0); };
+        auto none = []() {};
+        const int PS = geo.PS;
+        if constexpr (MODE == MODE_TWO) {
+            // row 0: i, row 1: j
+            auto ij = [&](int e, int w) {
+                const i32x2 c = s_idx[e];
+                return (int64_t)(w ? c.y : c.x);
+            };
+            if (geo.same) {
+                stage_rows<CT, 2>(F1, geo.W1, PS, cnt, s_a, ij, next);
+            } else {
+                stage_rows<CT, 2>(F1, geo.W1, PS, cnt, s_a, ij, none);
+                stage_rows<CT, 2>(F2, geo.W2, PS, cnt, s_b, ij, next);
+            }
+        } else {
+            auto rk = [&](int e, int) { return (int64_t)s_idx[e].y; };
+            if constexpr (MODE == MODE_ONE) {
+                stage_rows<CT, 1>(F1, geo.W1, PS, cnt, s_a,
+                                  [&](int e, int) { return (int64_t)s_idx[e].x; }, next);
+                stage_rows<CT, 1>(F2, geo.W2, PS, cnt, s_b, rk, none);
+            } else {
+                stage_rows<CT, 1>(F2, geo.W2, PS, cnt, s_b, rk, next);
+            }
+        }
+        (void)nA;
+        (void)nB;
+        __syncthreads();
+
+        int lo, hi, step;
+        if (heavy) {
+            lo = active ? el : cnt;
+            hi = cnt;
+            step = E;
+        } else {
+            lo = (int)max<int64_t>(s0 - b0, 0);
+            hi = (int)min<int64_t>(s1 - b0, cnt);
+            step = 1;
+        }
+        for (int e = lo; e < hi; e += step) {
+            const CT v = s_v[e];
+            if constexpr (MODE == MODE_M3) {
+                CT zb[PB];
+                lds_block<CT, PB>(s_b + pb0 + e * V, pse, zb);
+#pragma unroll
+                for (int b = 0; b < PB; ++b) acc[0][b] = fma(v, zb[b], acc[0][b]);
+            } else if constexpr (MODE == MODE_ONE) {
+                CT ya[PA], zb[PB];
+                lds_block<CT, PA>(s_a + pa0 + e * V, pse, ya);
+                lds_block<CT, PB>(s_b + pb0 + e * V, pse, zb);
+#pragma unroll
+                for (int a = 0; a < PA; ++a) {
+                    const CT x = v * ya[a];
+#pragma unroll
+                    for (int b = 0; b < PB; ++b) acc[a][b] = fma(x, zb[b], acc[a][b]);
+                }
+            } else {
+                // A.(X, Y)_{1,2} gets v X(i,:)^T Y(j,:) and, off the
+                // diagonal, the mirrored entry's v X(j,:)^T Y(i,:)
+                const CT w = s_w[e];
+                CT xi[PA], xj[PA], yi[PB], yj[PB];
+                lds_block<CT, PA>(s_a + pa0 + e * V, pse, xi);
+                lds_block<CT, PA>(s_a + pa1 + e * V, pse, xj);
+                lds_block<CT, PB>(rowsB + pb0 + e * V, pse, yi);
+                lds_block<CT, PB>(rowsB + pb1 + e * V, pse, yj);
+#pragma unroll
+                for (int a = 0; a < PA; ++a) {
+                    const CT x1 = v * xi[a], x2 = w * xj[a];
+#pragma unroll
+                    for (int b = 0; b < PB; ++b)
+                        acc[a][b] = fma(x2, yi[b], fma(x1, yj[b], acc[a][b]));
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    const int a0 = ba * PA, bl0 = bb * PB;
+    if (heavy) {
+        CT *red = lds;
 #pragma unroll
         for (int a = 0; a < PA; ++a)
 #pragma unroll
@@ -131,34 +385,46 @@ __global__ __launch_bounds__(64) void ttmc_wave(
             const int gg = o / (PA * PB);
             const int ab = o - gg * PA * PB;
             const int a = ab / PB, b = ab - (ab / PB) * PB;
-            const int alpha = bm.a[gg] * PA + a, beta = bm.b[gg] * PB + b;
-            if (alpha >= px || beta >= py) continue;
-            if (outmode == OUT_SYM && alpha > beta) continue;
+            int ga_, gb_;
+            lane_block<MODE>(gg, geo, ga_, gb_);
+            const int alpha = ga_ * PA + a, beta = gb_ * PB + b;
+            if (alpha >= geo.px || beta >= geo.py) continue;
+            if (geo.outmode == OUT_SYM && alpha > beta) continue;
             CT s = CT(0);
             for (int x = 0; x < E; ++x) s += red[(x * G + gg) * PA * PB + ab];
-            const int col = out_col(alpha, beta, px, outmode);
+            const int col = out_col(alpha, beta, geo.px, geo.outmode);
             if (it.slot < 0)
                 out[(int64_t)it.seg * ldo + col] = s;
             else
-                partial[(int64_t)it.slot * q + col] = s;
+                partial[(int64_t)it.slot * geo.q + col] = s;
         }
-    } else {
-        // light: whole short segments, one lane group each
-        const int64_t seg = (int64_t)it.seg + el;
-        if (active && seg < it.seg_end) {
-            const int64_t e1 = segptr[seg + 1];
-            for (int64_t e = segptr[seg]; e < e1; ++e)
-                accumulate<VT, CT, PA, PB, MODE>(e, c1, c2, val, F1, ld1, F2, ld2, a0, b0, px,
-                                                 py, acc);
+    } else if (active && myseg < it.seg_end) {
 #pragma unroll
-            for (int a = 0; a < PA; ++a)
+        for (int a = 0; a < PA; ++a)
 #pragma unroll
-                for (int b = 0; b < PB; ++b) {
-                    const int alpha = a0 + a, beta = b0 + b;
-                    if (alpha < px && beta < py && (outmode == OUT_RECT || alpha <= beta))
-                        out[seg * ldo + out_col(alpha, beta, px, outmode)] = acc[a][b];
-                }
-        }
+            for (int b = 0; b < PB; ++b) {
+                const int alpha = a0 + a, beta = bl0 + b;
+                if (alpha < geo.px && beta < geo.py &&
+                    (geo.outmode == OUT_RECT || alpha <= beta))
+                    out[myseg * ldo + out_col(alpha, beta, geo.px, geo.outmode)] = acc[a][b];
+            }
+    }
+}
+
+// Block-pack a factor: out(r, t*PAD + u) = F(r, t*P + u) for u < P and
+// t*P + u < p, else 0.
+template <typename CT>
+__global__ __launch_bounds__(256) void pack_blocks(const CT *__restrict__ F, int64_t ld,
+                                                   int64_t rows, int p, int P, int PAD, int W,
+                                                   CT *__restrict__ out) {
+    const int64_t total = rows * W;
+    for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < total;
+         x += (int64_t)gridDim.x * 256) {
+        const int64_t r = x / W;
+        const int c = (int)(x - r * W);
+        const int t = c / PAD, u = c - t * PAD;
+        const int col = t * P + u;
+        out[x] = (u < P && col < p) ? F[r * ld + col] : CT(0);
     }
 }
 
@@ -201,8 +467,8 @@ constexpr int kChunk = 32;
 
 template <typename VT, typename CT>
 __global__ __launch_bounds__(256) void ttmc_sym_wide(
-    const int64_t *__restrict__ segptr, const int32_t *__restrict__ ci,
-    const int32_t *__restrict__ cj, const VT *__restrict__ val, const CT *__restrict__ X,
+    const int64_t *__restrict__ segptr, const int2 *__restrict__ c12,
+    const VT *__restrict__ val, const CT *__restrict__ X,
     int64_t ldx, int p, int ntile, CT *__restrict__ out, int64_t ldo) {
     __shared__ CT xai[kChunk][kTile];
     __shared__ CT xbj[kChunk][kTile];
@@ -233,7 +499,8 @@ __global__ __launch_bounds__(256) void ttmc_sym_wide(
             CT vi = CT(0), vj = CT(0), wi = CT(0), wj = CT(0);
             if (e < cnt) {
                 const int64_t ee = base + e;
-                const int i = ci[ee], j = cj[ee];
+                const int2 ij = c12[ee];
+                const int i = ij.x, j = ij.y;
                 const CT v = static_cast<CT>(val[ee]);
                 const CT w = (i != j) ? v : CT(0);
                 const int ca = ta * kTile + c, cb = tb * kTile + c;
@@ -285,26 +552,20 @@ __global__ __launch_bounds__(256) void ttmc_sym_wide(
 }
 
 // ---------------------------------------------------------------- dispatch
-using WaveFn = void (*)(const Item *, const int64_t *, const int32_t *, const int32_t *,
-                        const void *, const void *, int64_t, const void *, int64_t, int, int,
-                        int, BlockMap, void *, int64_t, void *, int, int);
-
 template <typename VT, typename CT, int PA, int PB, int MODE>
-void launch_wave(dim3 grid, hipStream_t s, const Item *items, const int64_t *segptr,
-                 const int32_t *c1, const int32_t *c2, const void *val, const void *F1,
-                 int64_t ld1, const void *F2, int64_t ld2, int px, int py, int G,
-                 const BlockMap &bm, void *out, int64_t ldo, void *partial, int q,
-                 int outmode) {
-    hipLaunchKernelGGL((ttmc_wave<VT, CT, PA, PB, MODE>), grid, dim3(64), 0, s, items, segptr,
-                       c1, c2, static_cast<const VT *>(val), static_cast<const CT *>(F1), ld1,
-                       static_cast<const CT *>(F2), ld2, px, py, G, bm,
-                       static_cast<CT *>(out), ldo, static_cast<CT *>(partial), q, outmode);
+void launch_wave(dim3 grid, size_t lds, hipStream_t s, const Item *items,
+                 const int64_t *segptr, const int2 *c12, const int32_t *ck, const void *val,
+                 const void *F1, const void *F2, const Geo &geo, void *out,
+                 int64_t ldo, void *partial) {
+    hipLaunchKernelGGL((ttmc_wave<VT, CT, PA, PB, MODE>), grid, dim3(64), lds, s, items,
+                       segptr, c12, ck, static_cast<const VT *>(val),
+                       static_cast<const CT *>(F1), static_cast<const CT *>(F2), geo,
+                       static_cast<CT *>(out), ldo, static_cast<CT *>(partial));
 }
 
-using Launcher = void (*)(dim3, hipStream_t, const Item *, const int64_t *, const int32_t *,
-                          const int32_t *, const void *, const void *, int64_t, const void *,
-                          int64_t, int, int, int, const BlockMap &, void *, int64_t, void *,
-                          int, int);
+using Launcher = void (*)(dim3, size_t, hipStream_t, const Item *, const int64_t *,
+                          const int2 *, const int32_t *, const void *, const void *,
+                          const void *, const Geo &, void *, int64_t, void *);
 
 template <typename VT, typename CT, int MODE>
 struct Table {
@@ -360,7 +621,7 @@ void launch_sym_wide(const Segmented &o, const VT *val, const CT *X, int64_t ldx
     const int64_t blocks = n * (int64_t)(ntile * (ntile + 1) / 2);
     if (blocks == 0) return;
     hipLaunchKernelGGL((ttmc_sym_wide<VT, CT>), dim3((unsigned)blocks), dim3(256), 0, s,
-                       o.segptr.as<int64_t>(), o.c1.as<int32_t>(), o.c2.as<int32_t>(), val, X,
+                       o.segptr.as<int64_t>(), o.c1.as<int2>(), val, X,
                        ldx, p, ntile, out, ldo);
 }
 
@@ -524,8 +785,6 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
     }
 
     int PA, ga, PB, gb;
-    BlockMap bm;
-    std::memset(&bm, 0, sizeof(bm));
     int G;
     if (mode == MODE_M3) {
         PA = 1;
@@ -533,34 +792,80 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
         choose_block(py, PB, gb);
         G = gb;
         if (G > 64) fail(BKS_EINVAL, "MODE3 width too large");
-        for (int x = 0; x < G; ++x) {
-            bm.a[x] = 0;
-            bm.b[x] = (int8_t)x;
-        }
     } else if (outmode == OUT_SYM) {
         choose_block(px, PA, ga);
         PB = PA;
         gb = ga;
         G = ga * (ga + 1) / 2;
         if (G > 64) fail(BKS_EINVAL, "width too large");
-        int x = 0;
-        for (int bb = 0; bb < ga; ++bb)
-            for (int aa = 0; aa <= bb; ++aa) {
-                bm.a[x] = (int8_t)aa;
-                bm.b[x] = (int8_t)bb;
-                ++x;
-            }
     } else {
         choose_block(px, PA, ga);
         choose_block(py, PB, gb);
         G = ga * gb;
         if (G > 64) fail(BKS_EINVAL, "widths too large for the narrow kernel");
-        for (int x = 0; x < G; ++x) {
-            bm.a[x] = (int8_t)(x % ga);
-            bm.b[x] = (int8_t)(x / ga);
-        }
     }
     const int E = 64 / G;
+    const int V = dbl ? 2 : 4;
+    Geo geo;
+    std::memset(&geo, 0, sizeof(geo));
+    geo.px = px;
+    geo.py = py;
+    geo.G = G;
+    geo.ga = ga;
+    geo.outmode = outmode;
+    geo.q = q;
+    geo.same = (mode == MODE_TWO && F2 == F1 && l2 == l1 && py == px) ? 1 : 0;
+    geo.PAD1 = pad_to(PA, V);
+    geo.PAD2 = pad_to(PB, V);
+    geo.W1 = mode == MODE_M3 ? 0 : ga * geo.PAD1;
+    geo.W2 = gb * geo.PAD2;
+    const int nA = mode == MODE_TWO ? 2 : (mode == MODE_ONE ? 1 : 0);
+    const int nB = mode == MODE_TWO ? (geo.same ? 0 : 2) : 1;
+    // entries per batch: fill the staging budget, a multiple of E when possible
+    const size_t bpe = 8 + 2 * cts + (size_t)(nA * geo.W1 + nB * geo.W2) * cts;
+    int NB = (int)std::min<size_t>(64 * kIdxRegs, std::max<size_t>(1, kStageBytes / bpe));
+    if (NB >= E) NB = NB / E * E;
+    geo.NB = NB;
+    geo.offv = pad_to((int)((size_t)NB * 8 / cts), V);
+    geo.offw = geo.offv + pad_to(NB, V);
+    geo.PS = NB + 1;  // one spare unit per plane staggers the planes' banks
+    geo.offa = geo.offw + pad_to(NB, V);
+    geo.offb = geo.offa + geo.PS * nA * geo.W1;
+    const size_t lds_elems = (size_t)geo.offb + (size_t)geo.PS * nB * geo.W2;
+    const size_t lds = std::max(lds_elems, (size_t)64 * PA * PB) * cts;
+    if (lds > 65536) fail(BKS_EINVAL, "widths too large for the narrow kernel");
+
+    // block-pack the factors (rows of X/Y: m; rows of Z: n)
+    const void *P1 = nullptr, *P2 = nullptr;
+    auto pack = [&](DevBuf &ws, const void *F, int64_t ld, int64_t rows, int p, int P, int PAD,
+                    int W) -> const void * {
+        ws.ensure((size_t)std::max<int64_t>(rows, 1) * W * cts);
+        const int64_t total = rows * W;
+        const unsigned grid = (unsigned)std::max<int64_t>(
+            1, std::min<int64_t>((total + 255) / 256, 4096));
+        if (total > 0) {
+            if (dbl)
+                hipLaunchKernelGGL(pack_blocks<double>, dim3(grid), dim3(256), 0, s,
+                                   static_cast<const double *>(F), ld, rows, p, P, PAD, W,
+                                   ws.as<double>());
+            else
+                hipLaunchKernelGGL(pack_blocks<float>, dim3(grid), dim3(256), 0, s,
+                                   static_cast<const float *>(F), ld, rows, p, P, PAD, W,
+                                   ws.as<float>());
+            HIPCHECK(hipGetLastError());
+        }
+        return ws.ptr;
+    };
+    if (mode == MODE_TWO) {
+        P1 = pack(c.ws_fac1, F1, l1, t.m, px, PA, geo.PAD1, geo.W1);
+        P2 = geo.same ? P1 : pack(c.ws_fac2, F2, l2, t.m, py, PB, geo.PAD2, geo.W2);
+    } else if (mode == MODE_ONE) {
+        P1 = pack(c.ws_fac1, F1, l1, t.m, px, PA, geo.PAD1, geo.W1);
+        P2 = pack(c.ws_fac2, F2, l2, t.n, py, PB, geo.PAD2, geo.W2);
+    } else {
+        P2 = pack(c.ws_fac2, F2, l2, t.n, py, PB, geo.PAD2, geo.W2);
+    }
+
     const Schedule &sc = t.schedule(order, E);
     void *partial = nullptr;
     if (sc.nslots > 0) {
@@ -576,9 +881,10 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
         fn = pick<float, double>(mode, PA, PB);
     if (!fn) fail(BKS_EINVAL, "no kernel for this width");
     if (sc.nitems > 0)
-        fn(dim3((unsigned)sc.nitems), s, sc.items.as<Item>(), o.segptr.as<int64_t>(),
-           o.c1.as<int32_t>(), o.c2.as<int32_t>(), val, F1, l1, F2, l2, px, py, G, bm, out, ldo,
-           partial, q, outmode);
+        fn(dim3((unsigned)sc.nitems), lds, s, sc.items.as<Item>(), o.segptr.as<int64_t>(),
+           mode == MODE_M3 ? nullptr : o.c1.as<int2>(),
+           mode == MODE_M3 ? o.c2.as<int32_t>() : nullptr, val, P1, P2, geo, out, ldo,
+           partial);
     HIPCHECK(hipGetLastError());
     if (sc.nfix > 0) {
         if (dbl)

@@ -248,15 +248,18 @@ def c2(seed: int = 1001) -> SymCOO:
     return sparse_sym(20_000, 2_000, 2_000_000, zipf=1.3, values="abs", seed=seed)
 
 
-def c2_planted(seed: int = 1001) -> SymCOO:
+def c2_planted(seed: int = 1001, m: int = 20_000, n: int = 2_000, nnz: int = 2_000_000,
+               rows_per_col: int = 40, slices_per_col: int = 20) -> SymCOO:
     """The C2 law (20000 x 20000 x 2000, Zipf(1.3) modes 1-2, uniform mode 3,
     |N(0,1)| FP32) with about 82k of its 2e6 stored entries given to a planted
     rank-(5,5,5) part (superdiagonal core 3000, 2500, 2000, 1500, 1000; each
     factor column on 40 rows / 20 slices).  The plain law has a flat mode-3
     spectrum (uniform mode-3 indices), so its rank-(5,5,5) problem is
-    ill-conditioned; the plant gives it separated S-values."""
-    plant = planted(20_000, 2_000, (3000.0, 2500.0, 2000.0, 1500.0, 1000.0), 40, 20, seed + 7)
-    noise = sparse_sym(20_000, 2_000, 2_000_000 - plant.nnz, zipf=1.3, values="abs", seed=seed)
+    ill-conditioned; the plant gives it separated S-values.  The size
+    arguments give smaller tensors of the same law."""
+    plant = planted(m, n, (3000.0, 2500.0, 2000.0, 1500.0, 1000.0), rows_per_col,
+                    slices_per_col, seed + 7)
+    noise = sparse_sym(m, n, nnz - plant.nnz, zipf=1.3, values="abs", seed=seed)
     return merge(noise.astype(np.float64), plant).astype(np.float32)
 
 

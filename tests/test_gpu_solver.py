@@ -122,23 +122,29 @@ def test_bks_variants(ctx, variant, s, p):
 
 
 def c2_small(seed=1001):
-    return workloads.sparse_sym(5000, 400, 200_000, zipf=1.3, values="abs", seed=seed)
+    # the C2 law (Zipf(1.3) modes 1-2, uniform mode 3, |N(0,1)| FP32) at
+    # 5000 x 5000 x 400 with 2e5 stored entries and the rank-(5,5,5) plant
+    return workloads.c2_planted(seed, m=5000, n=400, nnz=200_000, rows_per_col=30,
+                                slices_per_col=15)
 
 
 def test_bks_mixed_vs_oracle_c2_shaped(ctx):
     """Mixed precision (FP32 expansion and core products) reaches the FP64
-    oracle's fixed point to 1e-8 on a C2-shaped problem."""
+    oracle's fixed point to 1e-8 on a C2-shaped problem; so does the FP64
+    solver."""
     c = c2_small()
     U0, W0 = workloads.random_start(c.m, c.n, 5, 5, 11)
-    ref = obks.bks_solve(otensor(c), 5, 5, U0, W0)
+    # at this size the FP64 gradient floors near 1e-12 (oracle and device);
+    # 1e-11 is far below what a 1e-8 subspace angle needs
+    ref = obks.bks_solve(otensor(c), 5, 5, U0, W0, tol=1e-11, inner_tol=1e-13)
+    assert ref["rel_hist"][-1] <= 1e-11
     t = ctx.upload_coo(c)
-    U, W, F, info, rc = ctx.solve(t, 5, 5, U0=U0, W0=W0, precision=bks.PREC_MIXED)
+    U, W, F, info, rc = ctx.solve(t, 5, 5, U0=U0, W0=W0, precision=bks.PREC_MIXED, tol=1e-11,
+                                  inner_tol=1e-13)
     assert info.converged and info.rel_grad <= 1e-11
-    gap1 = ref["svals1"][4] - ref["svals1"][5]
-    gap3 = ref["svals3"][4] - ref["svals3"][5]
-    print("gaps", gap1 / ref["svals1"][0], gap3 / ref["svals3"][0])
     compare(ref, U, W, F, info, 1e-8, tol_f=1e-12)
-    U2, W2, F2, info2, rc2 = ctx.solve(t, 5, 5, U0=U0, W0=W0, precision=bks.PREC_FP64)
+    U2, W2, F2, info2, rc2 = ctx.solve(t, 5, 5, U0=U0, W0=W0, precision=bks.PREC_FP64,
+                                       tol=1e-11, inner_tol=1e-13)
     assert info2.converged
     compare(ref, U2, W2, F2, info2, 1e-9)
 
