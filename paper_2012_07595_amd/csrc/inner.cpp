@@ -35,48 +35,26 @@ struct View {
 };
 
 // CS(a, b, l) = sum_c C(a, b, c) Sv(c, l) for the columns [l0, l0+nl) of Sv
-// (k3 x ldS row-major).  Output layout: a + k1*(b + k1*l).
+// (k3 x ldS row-major).  Output layout: a + k1*(b + k1*l).  The slices of C
+// (a, b) are exactly symmetric, so so is every CS(:, :, l), and row a of a
+// slice is contiguous at a * k1.
 void mode3_product(const View &V, const double *Sv, int ldS, int l0, int nl,
                    std::vector<double> &out) {
     const int k1 = V.k1, k3 = V.k3;
-    const size_t sl = (size_t)k1 * k1;
-    out.assign(sl * nl, 0.0);
-    for (int c = 0; c < k3; ++c) {
-        const double *slice = V.C + sl * c;
-        for (int l = 0; l < nl; ++l) {
-            const double w = Sv[(size_t)c * ldS + l0 + l];
-            if (w == 0.0) continue;
-            double *o = &out[sl * l];
-            for (size_t x = 0; x < sl; ++x) o[x] += w * slice[x];
-        }
-    }
+    const int sl = k1 * k1;
+    out.resize((size_t)sl * nl);
+    la::dgemm(true, false, nl, sl, k3, 1.0, Sv + l0, ldS, V.C, sl, 0.0, out.data(), sl, true);
 }
 
 void hosvd(const View &V, int r, int r3, std::vector<double> &P, std::vector<double> &S) {
     const int k1 = V.k1, k3 = V.k3;
     const size_t sl = (size_t)k1 * k1;
-    // G1 = C_(1) C_(1)^T over the columns (b, c)
-    std::vector<double> G1((size_t)k1 * k1, 0.0);
-    const size_t ncol = (size_t)k1 * k3;
-    for (size_t col = 0; col < ncol; ++col) {
-        const double *v = V.C + (size_t)k1 * col;
-        for (int a = 0; a < k1; ++a) {
-            const double va = v[a];
-            if (va == 0.0) continue;
-            double *g = &G1[(size_t)a * k1];
-            for (int b = 0; b <= a; ++b) g[b] += va * v[b];
-        }
-    }
-    for (int a = 0; a < k1; ++a)
-        for (int b = 0; b < a; ++b) G1[(size_t)b * k1 + a] = G1[(size_t)a * k1 + b];
-    std::vector<double> G3((size_t)k3 * k3, 0.0);
-    for (int c = 0; c < k3; ++c)
-        for (int d = 0; d <= c; ++d) {
-            const double *x = V.C + sl * c, *y = V.C + sl * d;
-            double s = 0.0;
-            for (size_t t = 0; t < sl; ++t) s += x[t] * y[t];
-            G3[(size_t)c * k3 + d] = G3[(size_t)d * k3 + c] = s;
-        }
+    // G1 = C_(1) C_(1)^T: the mode-1 fibres C(:, b, c) are the rows of a
+    // (k1 k3) x k1 matrix; G3 = C_(3) C_(3)^T: slice c is row c of k3 x k1^2
+    std::vector<double> G1((size_t)k1 * k1), G3((size_t)k3 * k3);
+    la::dgemm(true, false, k1, k1, k1 * k3, 1.0, V.C, k1, V.C, k1, 0.0, G1.data(), k1, true);
+    la::dgemm(false, true, k3, k3, (int)sl, 1.0, V.C, (int)sl, V.C, (int)sl, 0.0, G3.data(), k3,
+              true);
     P.assign((size_t)k1 * r, 0.0);
     S.assign((size_t)k3 * r3, 0.0);
     la::top_eigvecs(k1, G1.data(), r, P.data());
@@ -86,64 +64,44 @@ void hosvd(const View &V, int r, int r3, std::vector<double> &P, std::vector<dou
 // Leading w left singular vectors of M (rows x cols, row-major) through the
 // small Gram matrix: U = M V diag(sigma)^-1, re-orthonormalised.
 void lead_left(const std::vector<double> &M, int rows, int cols, int w, std::vector<double> &U) {
-    std::vector<double> G((size_t)cols * cols, 0.0);
-    for (int i = 0; i < rows; ++i) {
-        const double *mi = &M[(size_t)i * cols];
-        for (int a = 0; a < cols; ++a) {
-            const double v = mi[a];
-            if (v == 0.0) continue;
-            double *g = &G[(size_t)a * cols];
-            for (int b = 0; b <= a; ++b) g[b] += v * mi[b];
-        }
-    }
-    for (int a = 0; a < cols; ++a)
-        for (int b = 0; b < a; ++b) G[(size_t)b * cols + a] = G[(size_t)a * cols + b];
+    std::vector<double> G((size_t)cols * cols);
+    la::dgemm(true, false, cols, cols, rows, 1.0, M.data(), cols, M.data(), cols, 0.0, G.data(),
+              cols, true);
     std::vector<double> Vv((size_t)cols * w), ev(w);
     la::top_eigvecs(cols, G.data(), w, Vv.data(), ev.data());
     for (int j = 0; j < w; ++j) {
         const double sc = 1.0 / std::sqrt(std::max(ev[j], 1e-300));
         for (int a = 0; a < cols; ++a) Vv[(size_t)a * w + j] *= sc;
     }
-    U.assign((size_t)rows * w, 0.0);
-    la::gemm(rows, w, cols, M.data(), Vv.data(), U.data());
+    U.resize((size_t)rows * w);
+    la::dgemm(false, false, rows, w, cols, 1.0, M.data(), cols, Vv.data(), w, 0.0, U.data(), w);
     la::orthonormalize(rows, w, U.data());
 }
 
 // One symmetric HOOI iteration on the core (Section 5.1).
 void hooi_step(const View &V, int r, int r3, std::vector<double> &P, std::vector<double> &S) {
     const int k1 = V.k1, k3 = V.k3;
+    const size_t sl = (size_t)k1 * k1;
     std::vector<double> CS;
     mode3_product(V, S.data(), r3, 0, r3, CS);  // k1 x k1 x r3
     // M1(a, j + r*l) = sum_b CS(a, b, l) P(b, j)
     const int w1 = r * r3;
-    std::vector<double> M1((size_t)k1 * w1, 0.0);
-    for (int l = 0; l < r3; ++l)
-        for (int b = 0; b < k1; ++b)
-            for (int a = 0; a < k1; ++a) {
-                const double cv = CS[a + (size_t)k1 * (b + (size_t)k1 * l)];
-                if (cv == 0.0) continue;
-                for (int j = 0; j < r; ++j) M1[(size_t)a * w1 + j + r * l] += cv * P[(size_t)b * r + j];
-            }
+    std::vector<double> M1((size_t)k1 * w1);
+    la::parallel_for(r3, [&](int l) {
+        la::dgemm(false, false, k1, r, k1, 1.0, &CS[sl * l], k1, P.data(), r, 0.0, &M1[(size_t)r * l],
+                  w1);
+    });
     lead_left(M1, k1, w1, r, P);
     // M3(c, i + r*j) = sum_{a,b} C(a,b,c) P(a,i) P(b,j)
     const int w3 = r * r;
-    std::vector<double> M3((size_t)k3 * w3, 0.0);
-    std::vector<double> CP((size_t)r * k1);
-    for (int c = 0; c < k3; ++c) {
-        std::fill(CP.begin(), CP.end(), 0.0);
-        for (int b = 0; b < k1; ++b)
-            for (int a = 0; a < k1; ++a) {
-                const double cv = V.at(a, b, c);
-                if (cv == 0.0) continue;
-                for (int i = 0; i < r; ++i) CP[(size_t)i * k1 + b] += cv * P[(size_t)a * r + i];
-            }
+    std::vector<double> M3((size_t)k3 * w3);
+    la::parallel_for(k3, [&](int c) {
+        std::vector<double> CP((size_t)k1 * r), T((size_t)r * r);
+        la::dgemm(false, false, k1, r, k1, 1.0, V.C + sl * c, k1, P.data(), r, 0.0, CP.data(), r);
+        la::dgemm(true, false, r, r, k1, 1.0, P.data(), r, CP.data(), r, 0.0, T.data(), r);
         for (int i = 0; i < r; ++i)
-            for (int j = 0; j < r; ++j) {
-                double s = 0.0;
-                for (int b = 0; b < k1; ++b) s += CP[(size_t)i * k1 + b] * P[(size_t)b * r + j];
-                M3[(size_t)c * w3 + i + r * j] = s;
-            }
-    }
+            for (int j = 0; j < r; ++j) M3[(size_t)c * w3 + i + r * j] = T[(size_t)i * r + j];
+    });
     lead_left(M3, k3, w3, r3, S);
 }
 
@@ -169,55 +127,38 @@ void rotate(const View &V, const std::vector<double> &P, const std::vector<doubl
     la::qr_full(k1, r, P.data(), B.Qp.data());
     la::qr_full(k3, r3, S.data(), B.Qs.data());
     const int A1 = B.A1, C1 = B.C1;
-    // R0 = C.(Qp, Qp, S)  (all of modes 1-2, the first r3 of mode 3)
+    // CS(:, :, l) = C.(I, I, Qs(:, l)) for all k3 columns: the first r3 give
+    // R0 = C.(Qp, Qp, S), the rest R1 = C.(Qp, P, S_perp)
     std::vector<double> CS;
-    mode3_product(V, B.Qs.data(), k3, 0, r3, CS);
-    std::vector<double> tmp((size_t)k1 * k1), Y((size_t)k1 * k1);
+    mode3_product(V, B.Qs.data(), k3, 0, k3, CS);
+    const size_t sl = (size_t)k1 * k1;
     B.F.assign((size_t)r * r * r3, 0.0);
     B.B100.assign((size_t)A1 * r * r3, 0.0);
     B.B110.assign((size_t)A1 * A1 * r3, 0.0);
-    for (int l = 0; l < r3; ++l) {
-        // Xl(a, b) = CS(a, b, l) at a + k1*b (symmetric);  Y = Qp^T Xl Qp
-        const double *Xl = &CS[(size_t)k1 * k1 * l];
-        // tmp(a, y) = sum_b Xl(a, b) Qp(b, y)
-        std::fill(tmp.begin(), tmp.end(), 0.0);
-        for (int a = 0; a < k1; ++a)
-            for (int b = 0; b < k1; ++b) {
-                const double xv = Xl[a + (size_t)k1 * b];
-                if (xv == 0.0) continue;
-                const double *qb = &B.Qp[(size_t)b * k1];
-                double *t = &tmp[(size_t)a * k1];
-                for (int y = 0; y < k1; ++y) t[y] += xv * qb[y];
-            }
-        la::gemm_tn(k1, k1, k1, B.Qp.data(), tmp.data(), Y.data());  // Y(x, y)
-        for (int x = 0; x < k1; ++x)
-            for (int y = 0; y < k1; ++y) {
-                const double v = Y[(size_t)x * k1 + y];
-                if (x < r && y < r) B.F[x + r * (y + (size_t)r * l)] = v;
-                else if (x >= r && y < r) B.B100[(x - r) + (size_t)A1 * (y + (size_t)r * l)] = v;
-                else if (x >= r && y >= r)
-                    B.B110[(x - r) + (size_t)A1 * ((y - r) + (size_t)A1 * l)] = v;
-            }
-    }
-    // R1 = C.(Qp, P, S_perp)
     B.B001.assign((size_t)r * r * C1, 0.0);
     B.B101.assign((size_t)A1 * r * C1, 0.0);
-    if (C1 > 0) {
-        std::vector<double> CSp;
-        mode3_product(V, B.Qs.data(), k3, r3, C1, CSp);
-        std::vector<double> t2((size_t)k1 * r), Y2((size_t)k1 * r);
-        for (int z = 0; z < C1; ++z) {
-            const double *Xz = &CSp[(size_t)k1 * k1 * z];
-            std::fill(t2.begin(), t2.end(), 0.0);
-            for (int a = 0; a < k1; ++a)
-                for (int b = 0; b < k1; ++b) {
-                    const double xv = Xz[a + (size_t)k1 * b];
-                    if (xv == 0.0) continue;
-                    const double *qb = &B.Qp[(size_t)b * k1];
-                    double *t = &t2[(size_t)a * r];
-                    for (int j = 0; j < r; ++j) t[j] += xv * qb[j];
+    la::parallel_for(k3, [&](int l) {
+        const double *Xl = &CS[sl * l];  // symmetric: row a contiguous
+        if (l < r3) {
+            // Y = Qp^T X_l Qp, split into F, B100, B110
+            std::vector<double> tmp(sl), Y(sl);
+            la::dgemm(false, false, k1, k1, k1, 1.0, Xl, k1, B.Qp.data(), k1, 0.0, tmp.data(), k1);
+            la::dgemm(true, false, k1, k1, k1, 1.0, B.Qp.data(), k1, tmp.data(), k1, 0.0, Y.data(),
+                      k1);
+            for (int x = 0; x < k1; ++x)
+                for (int y = 0; y < k1; ++y) {
+                    const double v = Y[(size_t)x * k1 + y];
+                    if (x < r && y < r) B.F[x + r * (y + (size_t)r * l)] = v;
+                    else if (x >= r && y < r) B.B100[(x - r) + (size_t)A1 * (y + (size_t)r * l)] = v;
+                    else if (x >= r && y >= r)
+                        B.B110[(x - r) + (size_t)A1 * ((y - r) + (size_t)A1 * l)] = v;
                 }
-            la::gemm_tn(k1, r, k1, B.Qp.data(), t2.data(), Y2.data());  // (x, j)
+        } else {
+            // Y2 = Qp^T X_z P (P = the first r columns of Qp), split into B001, B101
+            const int z = l - r3;
+            std::vector<double> t2((size_t)k1 * r), Y2((size_t)k1 * r);
+            la::dgemm(false, false, k1, r, k1, 1.0, Xl, k1, B.Qp.data(), k1, 0.0, t2.data(), r);
+            la::dgemm(true, false, k1, r, k1, 1.0, B.Qp.data(), k1, t2.data(), r, 0.0, Y2.data(), r);
             for (int x = 0; x < k1; ++x)
                 for (int j = 0; j < r; ++j) {
                     const double v = Y2[(size_t)x * r + j];
@@ -225,7 +166,7 @@ void rotate(const View &V, const std::vector<double> &P, const std::vector<doubl
                     else B.B101[(x - r) + (size_t)A1 * (j + (size_t)r * z)] = v;
                 }
         }
-    }
+    });
 }
 
 double local_gradient(const Blocks &B, std::vector<double> &G1, std::vector<double> &G3,
@@ -293,7 +234,7 @@ void newton_matrix(const Blocks &B, std::vector<double> &H) {
         }
     std::vector<double> A((size_t)N * N, 0.0);
     // Delta-Delta block
-    for (int x = 0; x < A1; ++x)
+    la::parallel_for(A1, [&](int x) {
         for (int a = 0; a < r; ++a) {
             const int row = x * r + a;
             for (int y = 0; y < A1; ++y)
@@ -311,8 +252,9 @@ void newton_matrix(const Blocks &B, std::vector<double> &H) {
                     A[(size_t)row * N + col] = v;
                 }
         }
+    });
     // Delta-Theta blocks
-    for (int x = 0; x < A1; ++x)
+    la::parallel_for(A1, [&](int x) {
         for (int a = 0; a < r; ++a) {
             const int row = x * r + a;
             for (int z = 0; z < C1; ++z)
@@ -325,6 +267,7 @@ void newton_matrix(const Blocks &B, std::vector<double> &H) {
                     A[(size_t)col * N + row] = 2.0 * s;
                 }
         }
+    });
     // Theta-Theta block
     for (int z = 0; z < C1; ++z)
         for (int w = 0; w <= z; ++w) {
@@ -354,26 +297,20 @@ void newton_matrix(const Blocks &B, std::vector<double> &H) {
 double objective(const View &V, const std::vector<double> &P, const std::vector<double> &S, int r,
                  int r3) {
     const int k1 = V.k1;
+    const size_t sl = (size_t)k1 * k1;
     std::vector<double> CS;
     mode3_product(V, S.data(), r3, 0, r3, CS);
-    std::vector<double> t((size_t)k1 * r);
+    std::vector<double> gl(r3, 0.0);
+    la::parallel_for(r3, [&](int l) {
+        std::vector<double> t((size_t)k1 * r), T((size_t)r * r);
+        la::dgemm(false, false, k1, r, k1, 1.0, &CS[sl * l], k1, P.data(), r, 0.0, t.data(), r);
+        la::dgemm(true, false, r, r, k1, 1.0, P.data(), r, t.data(), r, 0.0, T.data(), r);
+        double g = 0.0;
+        for (double v : T) g += v * v;
+        gl[l] = g;
+    });
     double g = 0.0;
-    for (int l = 0; l < r3; ++l) {
-        const double *Xl = &CS[(size_t)k1 * k1 * l];
-        std::fill(t.begin(), t.end(), 0.0);
-        for (int b = 0; b < k1; ++b)
-            for (int a = 0; a < k1; ++a) {
-                const double xv = Xl[a + (size_t)k1 * b];
-                if (xv == 0.0) continue;
-                for (int j = 0; j < r; ++j) t[(size_t)a * r + j] += xv * P[(size_t)b * r + j];
-            }
-        for (int i = 0; i < r; ++i)
-            for (int j = 0; j < r; ++j) {
-                double s = 0.0;
-                for (int a = 0; a < k1; ++a) s += P[(size_t)a * r + i] * t[(size_t)a * r + j];
-                g += s * s;
-            }
-    }
+    for (double v : gl) g += v;
     return g;
 }
 
@@ -425,10 +362,12 @@ void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, do
         info.rel = local_gradient(B, G1, G3, nf);
         info.t_rotate += clk() - t0;
         if (info.rel <= tol || info.iters >= ng_max) break;
-        // at the rounding floor the gradient stops shrinking: two undamped
-        // Newton steps in a row that do not halve it below 1e-9 end the
-        // iteration (damped steps may legitimately progress slowly)
-        stall = (last_plain && info.rel < 1e-9 && info.rel > 0.5 * prev) ? stall + 1 : 0;
+        // at the rounding floor the gradient stops shrinking: two steps in a
+        // row that do not halve it below 1e-9 end the iteration (above 1e-9
+        // only undamped steps count: damped ones may legitimately progress
+        // slowly far from the maximum)
+        const bool at_floor = info.rel < 1e-9;
+        stall = ((last_plain || at_floor) && at_floor && info.rel > 0.5 * prev) ? stall + 1 : 0;
         if (stall >= 2) break;
         prev = info.rel;
         if (B.A1 * r + B.C1 * r3 == 0) break;
@@ -445,7 +384,11 @@ void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, do
         const double mu0 = 1e-8 * std::max(hmax, 1e-300);
         const double g0 = nf * nf;
         bool accepted = false;
-        for (int attempt = 0; attempt < 40 && !accepted; ++attempt) {
+        // far below 1e-9 no ascent direction survives rounding after a few
+        // shifts: there a rejected step ends the iteration
+        const bool deep_floor = info.rel < 1e-10;
+        const int max_attempts = deep_floor ? 4 : 40;
+        for (int attempt = 0; attempt < max_attempts && !accepted; ++attempt) {
             Hs = H;
             for (int i = 0; i < N; ++i) Hs[(size_t)i * N + i] += mu;
             d.assign(N, 0.0);
@@ -488,6 +431,8 @@ void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, do
         if (accepted) {
             ++info.newton;
         } else {
+            // no step raises g: at the floor that is the maximum to rounding
+            if (deep_floor) break;
             last_plain = false;
             hooi_step(V, r, r3, P, S);
         }

@@ -1,13 +1,20 @@
 // Small dense FP64 linear algebra (host).  Textbook algorithms: Householder
 // reduction to tridiagonal form followed by the implicitly shifted QL
-// iteration for symmetric eigenproblems, right-looking Cholesky, Householder
-// QR.
+// iteration for symmetric eigenproblems, blocked right-looking Cholesky,
+// Householder QR, and a register-blocked product on AVX2 FMA.
 #include "linalg.h"
 
+#include <immintrin.h>
+
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <condition_variable>
+#include <cstdlib>
+#include <mutex>
 #include <numeric>
 #include <stdexcept>
+#include <thread>
 
 namespace bks {
 namespace la {
@@ -187,24 +194,39 @@ void top_eigvecs(int n, const double *A, int r, double *Vr, double *wr) {
 }
 
 bool cholesky(int n, double *A, double *fail_pivot) {
-    // Right-looking A = U^T U on the upper triangle (row j of U contiguous,
-    // trailing update as row AXPYs), then L = U^T into the lower triangle.
-    for (int j = 0; j < n; ++j) {
-        double *uj = &A[(size_t)j * n];
-        const double s = uj[j];
-        if (!(s > 0.0)) {
-            if (fail_pivot) *fail_pivot = s;
-            return false;
+    // Blocked right-looking A = U^T U on the upper triangle (row j of U
+    // contiguous): factor the rows of one diagonal block (row AXPYs inside
+    // the block), update the trailing upper triangle with dgemm, then copy
+    // L = U^T into the lower triangle.
+    constexpr int NB = 48, RB = 64;
+    for (int j0 = 0; j0 < n; j0 += NB) {
+        const int r0 = std::min(n, j0 + NB), jb = r0 - j0;
+        for (int j = j0; j < r0; ++j) {
+            double *uj = &A[(size_t)j * n];
+            const double s = uj[j];
+            if (!(s > 0.0)) {
+                if (fail_pivot) *fail_pivot = s;
+                return false;
+            }
+            const double d = std::sqrt(s);
+            const double inv = 1.0 / d;
+            uj[j] = d;
+            for (int k = j + 1; k < n; ++k) uj[k] *= inv;
+            for (int i = j + 1; i < r0; ++i) {
+                const double f = uj[i];
+                if (f == 0.0) continue;
+                double *ai = &A[(size_t)i * n];
+                for (int k = i; k < n; ++k) ai[k] -= f * uj[k];
+            }
         }
-        const double d = std::sqrt(s);
-        const double inv = 1.0 / d;
-        uj[j] = d;
-        for (int k = j + 1; k < n; ++k) uj[k] *= inv;
-        for (int i = j + 1; i < n; ++i) {
-            const double f = uj[i];
-            if (f == 0.0) continue;
-            double *ai = &A[(size_t)i * n];
-            for (int k = i; k < n; ++k) ai[k] -= f * uj[k];
+        if (r0 < n) {
+            // A(i, k) -= sum_{t in block} U(t, i) U(t, k), rows in panels of RB
+            const int nrb = (n - r0 + RB - 1) / RB;
+            parallel_for(nrb, [&](int b) {
+                const int i0 = r0 + b * RB, i1 = std::min(n, i0 + RB);
+                dgemm(true, false, i1 - i0, n - i0, jb, -1.0, &A[(size_t)j0 * n + i0], n,
+                      &A[(size_t)j0 * n + i0], n, 1.0, &A[(size_t)i0 * n + i0], n);
+            });
         }
     }
     for (int i = 0; i < n; ++i)
@@ -307,6 +329,217 @@ void gemm_tn(int m, int n, int k, const double *A, const double *B, double *C) {
             for (int j = 0; j < n; ++j) ci[j] += a * bl[j];
         }
     }
+}
+
+// ---------------------------------------------------------------- threads
+namespace {
+thread_local int t_threads = 0;
+thread_local bool t_in_pool = false;
+
+int default_threads() {
+    if (const char *e = std::getenv("BKS_HOST_THREADS")) {
+        const int v = std::atoi(e);
+        if (v > 0) return v;
+    }
+    const int hw = (int)std::thread::hardware_concurrency();
+    return std::max(1, std::min(hw > 0 ? hw : 1, 8));
+}
+
+// A persistent pool of workers that runs one index loop at a time; the
+// caller works on the loop too.  A caller that finds the pool busy (another
+// host thread's loop) or is itself inside a loop runs its loop inline, so
+// the host is never oversubscribed.  The pool lives until the process ends.
+struct Pool {
+    std::mutex run_mu, mu;
+    std::condition_variable cv_work, cv_done;
+    const std::function<void(int)> *job = nullptr;
+    int n = 0, pending = 0;
+    std::atomic<int> next{0};
+    uint64_t gen = 0;
+    int nworkers = 0;
+
+    explicit Pool(int nw) : nworkers(nw) {
+        for (int w = 0; w < nw; ++w) std::thread([this] { loop(); }).detach();
+    }
+    void loop() {
+        t_in_pool = true;
+        uint64_t seen = 0;
+        for (;;) {
+            const std::function<void(int)> *f;
+            int cnt;
+            {
+                std::unique_lock<std::mutex> g(mu);
+                cv_work.wait(g, [&] { return gen != seen; });
+                seen = gen;
+                f = job;
+                cnt = n;
+            }
+            for (int i; (i = next.fetch_add(1)) < cnt;) (*f)(i);
+            std::lock_guard<std::mutex> g(mu);
+            if (--pending == 0) cv_done.notify_one();
+        }
+    }
+    void run(int cnt, const std::function<void(int)> &f) {
+        {
+            std::lock_guard<std::mutex> g(mu);
+            job = &f;
+            n = cnt;
+            next = 0;
+            pending = nworkers;
+            ++gen;
+        }
+        cv_work.notify_all();
+        t_in_pool = true;
+        for (int i; (i = next.fetch_add(1)) < cnt;) f(i);
+        t_in_pool = false;
+        std::unique_lock<std::mutex> g(mu);
+        cv_done.wait(g, [&] { return pending == 0; });
+    }
+};
+
+Pool *pool() {
+    static Pool *p = new Pool(std::max(0, default_threads() - 1));
+    return p;
+}
+}  // namespace
+
+void set_threads(int n) { t_threads = n; }
+
+int threads() {
+    if (t_threads > 0) return t_threads;
+    static const int def = default_threads();
+    return def;
+}
+
+void parallel_for(int n, const std::function<void(int)> &fn) {
+    if (n <= 0) return;
+    Pool *p = (n > 1 && threads() > 1 && !t_in_pool) ? pool() : nullptr;
+    if (p && p->nworkers > 0 && p->run_mu.try_lock()) {
+        p->run(n, fn);
+        p->run_mu.unlock();
+        return;
+    }
+    for (int i = 0; i < n; ++i) fn(i);
+}
+
+// ---------------------------------------------------------------- dgemm
+namespace {
+
+constexpr int MR = 4, NR = 8;
+
+// acc(4 x 8) = sum_l a(l, 0:4)^T b(l, 0:8), l in order; a(l, r) at
+// Ap[l * sa + r], b(l, c) at Bp[l * sb + c]
+inline void micro_4x8(int k, const double *Ap, int sa, const double *Bp, int sb, double *acc) {
+    __m256d c0a = _mm256_setzero_pd(), c0b = _mm256_setzero_pd();
+    __m256d c1a = _mm256_setzero_pd(), c1b = _mm256_setzero_pd();
+    __m256d c2a = _mm256_setzero_pd(), c2b = _mm256_setzero_pd();
+    __m256d c3a = _mm256_setzero_pd(), c3b = _mm256_setzero_pd();
+    for (int l = 0; l < k; ++l) {
+        const double *bl = Bp + (size_t)l * sb, *al = Ap + (size_t)l * sa;
+        const __m256d b0 = _mm256_loadu_pd(bl), b1 = _mm256_loadu_pd(bl + 4);
+        __m256d a = _mm256_broadcast_sd(al);
+        c0a = _mm256_fmadd_pd(a, b0, c0a);
+        c0b = _mm256_fmadd_pd(a, b1, c0b);
+        a = _mm256_broadcast_sd(al + 1);
+        c1a = _mm256_fmadd_pd(a, b0, c1a);
+        c1b = _mm256_fmadd_pd(a, b1, c1b);
+        a = _mm256_broadcast_sd(al + 2);
+        c2a = _mm256_fmadd_pd(a, b0, c2a);
+        c2b = _mm256_fmadd_pd(a, b1, c2b);
+        a = _mm256_broadcast_sd(al + 3);
+        c3a = _mm256_fmadd_pd(a, b0, c3a);
+        c3b = _mm256_fmadd_pd(a, b1, c3b);
+    }
+    _mm256_storeu_pd(acc + 0, c0a);
+    _mm256_storeu_pd(acc + 4, c0b);
+    _mm256_storeu_pd(acc + 8, c1a);
+    _mm256_storeu_pd(acc + 12, c1b);
+    _mm256_storeu_pd(acc + 16, c2a);
+    _mm256_storeu_pd(acc + 20, c2b);
+    _mm256_storeu_pd(acc + 24, c3a);
+    _mm256_storeu_pd(acc + 28, c3b);
+}
+
+}  // namespace
+
+void dgemm(bool ta, bool tb, int m, int n, int k, double alpha, const double *A, int lda,
+           const double *B, int ldb, double beta, double *C, int ldc, bool parallel) {
+    if (m <= 0 || n <= 0) return;
+    if (k <= 0 || alpha == 0.0) {
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < n; ++j)
+                C[(size_t)i * ldc + j] = beta == 0.0 ? 0.0 : beta * C[(size_t)i * ldc + j];
+        return;
+    }
+    const int mp = (m + MR - 1) / MR, np = (n + NR - 1) / NR;
+    // A panel ip holds rows ip*MR.. of op(A) as a(l, r); B panel jp holds
+    // columns jp*NR.. of op(B) as b(l, c).  Full panels of A^T (ta) and of a
+    // row-major B (!tb) are read in place; the others are packed.
+    auto a_at = [&](int i, int l) {
+        return ta ? A[(size_t)l * lda + i] : A[(size_t)i * lda + l];
+    };
+    auto b_at = [&](int l, int j) {
+        return tb ? B[(size_t)j * ldb + l] : B[(size_t)l * ldb + j];
+    };
+    std::vector<const double *> ap(mp), bp(np);
+    std::vector<int> as(mp), bs(np);
+    int npa = 0, npb = 0;
+    for (int ip = 0; ip < mp; ++ip)
+        if (!(ta && ip * MR + MR <= m)) ++npa;
+    for (int jp = 0; jp < np; ++jp)
+        if (!(!tb && jp * NR + NR <= n)) ++npb;
+    std::vector<double> Apk((size_t)npa * k * MR), Bpk((size_t)npb * k * NR);
+    for (int ip = 0, q = 0; ip < mp; ++ip) {
+        if (ta && ip * MR + MR <= m) {
+            ap[ip] = A + ip * MR;
+            as[ip] = lda;
+            continue;
+        }
+        double *dst = &Apk[(size_t)q++ * k * MR];
+        for (int l = 0; l < k; ++l)
+            for (int r = 0; r < MR; ++r) {
+                const int i = ip * MR + r;
+                dst[(size_t)l * MR + r] = i < m ? a_at(i, l) : 0.0;
+            }
+        ap[ip] = dst;
+        as[ip] = MR;
+    }
+    for (int jp = 0, q = 0; jp < np; ++jp) {
+        if (!tb && jp * NR + NR <= n) {
+            bp[jp] = B + jp * NR;
+            bs[jp] = ldb;
+            continue;
+        }
+        double *dst = &Bpk[(size_t)q++ * k * NR];
+        for (int l = 0; l < k; ++l)
+            for (int c = 0; c < NR; ++c) {
+                const int j = jp * NR + c;
+                dst[(size_t)l * NR + c] = j < n ? b_at(l, j) : 0.0;
+            }
+        bp[jp] = dst;
+        bs[jp] = NR;
+    }
+    auto tile = [&](int t) {
+        const int ip = t / np, jp = t - (t / np) * np;
+        alignas(32) double acc[MR * NR];
+        micro_4x8(k, ap[ip], as[ip], bp[jp], bs[jp], acc);
+        for (int r = 0; r < MR; ++r) {
+            const int i = ip * MR + r;
+            if (i >= m) break;
+            double *ci = C + (size_t)i * ldc;
+            for (int c = 0; c < NR; ++c) {
+                const int j = jp * NR + c;
+                if (j >= n) break;
+                const double v = alpha * acc[r * NR + c];
+                ci[j] = beta == 0.0 ? v : beta * ci[j] + v;
+            }
+        }
+    };
+    const int ntile = mp * np;
+    if (parallel && (double)m * n * k > 2e5)
+        parallel_for(ntile, tile);
+    else
+        for (int t = 0; t < ntile; ++t) tile(t);
 }
 
 }  // namespace la

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <vector>
 
 namespace bks {
@@ -31,6 +32,22 @@ void chol_solve(int n, const double *L, double *b);
 void qr_full(int m, int n, const double *A, double *Q);
 // Thin orthonormalisation (first n columns of qr_full).
 void orthonormalize(int m, int n, double *A);
+
+// Host threads for the parallel loops and products below, per calling
+// thread (0: the default, BKS_HOST_THREADS or the hardware concurrency, at
+// most 8; 1: no threads).  Results never depend on it: every output element
+// is computed by one thread, in a fixed order.
+void set_threads(int n);
+int threads();
+// fn(i) for every i in [0, n), split over threads() threads.
+void parallel_for(int n, const std::function<void(int)> &fn);
+
+// C (m x n, ldc) = alpha op(A) op(B) + beta C (beta = 0: C is not read).
+// op(A) is m x k: A row-major with leading dimension lda, or A^T if ta;
+// op(B) k x n likewise.  Register-blocked (4 x 8, AVX2 FMA); `parallel`
+// spreads the output panels over threads().
+void dgemm(bool ta, bool tb, int m, int n, int k, double alpha, const double *A, int lda,
+           const double *B, int ldb, double beta, double *C, int ldc, bool parallel = false);
 
 // C (m x n) = A (m x k) * B (k x n), all row-major.
 void gemm(int m, int n, int k, const double *A, const double *B, double *C);

@@ -10,6 +10,7 @@
 // share a bounded pool of host slots.  A solve's arithmetic does not depend on
 // what else runs (fixed-order reductions, no atomics), so a request's result
 // is the same alone and in the mix.
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -18,6 +19,7 @@
 #include <thread>
 
 #include "bks_internal.h"
+#include "linalg.h"
 
 namespace bks {
 
@@ -70,6 +72,9 @@ struct bks_server_s {
 
     void worker() {
         (void)hipSetDevice(ctx->device);
+        // host solves run concurrently in up to host_slots workers: share the
+        // host threads among them (results do not depend on the count)
+        la::set_threads(std::max(1, la::threads() / std::max(1, host_slots)));
         Ctx sc;  // private workspaces and stream of this session slot
         sc.device = ctx->device;
         sc.host_acquire = [this] {

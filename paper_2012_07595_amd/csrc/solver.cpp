@@ -20,6 +20,8 @@
 #include <array>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <random>
 #include <set>
@@ -29,6 +31,16 @@
 #include "linalg.h"
 
 namespace bks {
+
+// BKS_DEBUG_INNER=1: one line per inner solve on stderr (iterations, final
+// local gradient, phase times)
+static bool debug_inner() {
+    static const bool on = [] {
+        const char *e = std::getenv("BKS_DEBUG_INNER");
+        return e && e[0] == '1';
+    }();
+    return on;
+}
 
 namespace {
 
@@ -790,6 +802,12 @@ int run_bks(Ctx &c, Tensor &t, const bks_params &prm, double *U, double *W, doub
         if (c.host_release) c.host_release();
         inner_newton += ii.newton;
         ti += now_s() - a;
+        if (debug_inner())
+            std::fprintf(stderr,
+                         "[bks] outer %d k1 %d k3 %d inner iters %d newton %d rel %.3e  "
+                         "start %.2f rotate %.2f hess %.2f chol %.2f total %.2f ms\n",
+                         it, S.k1, S.k3, ii.iters, ii.newton, ii.rel, 1e3 * ii.t_start,
+                         1e3 * ii.t_rotate, 1e3 * ii.t_hess, 1e3 * ii.t_chol, 1e3 * (now_s() - a));
         a = now_s();
         S.restart(P, Sm);
         o = S.bk_step();

@@ -64,7 +64,7 @@ struct Geo {
     int G;             // lanes per entry
     int ga;            // lane blocks across the first output index
     int NB;            // entries staged per batch
-    int PS;            // LDS plane stride in 16-byte units (NB + 1)
+    int PS;            // LDS plane stride in 16-byte units
     int same;          // FREE3: Y rows are X rows
     int outmode;
     int q;             // output columns
@@ -116,9 +116,11 @@ __device__ __forceinline__ void lane_block(int g, const Geo &geo, int &a, int &b
 
 // Stage the packed factor rows of `cnt` entries into LDS, NR rows per
 // entry (row_of(e, w), w < NR), each row U = W / V 16-byte units.  Lanes
-// work as U unit groups of spl = 64 / U entries (lane = u * spl + e), so
-// a store instruction writes consecutive words of one plane; row w, unit u
-// of entry e goes to dst + ((w * U + u) * PS + e) * V.  Each lane issues its
+// work as spl = 64 / U entries of U units (lane = e * U + u), so the units
+// of one row are loaded by neighbouring lanes (fewer cache lines per lane
+// quad); row w, unit u of entry e goes to dst + ((w * U + u) * PS + e) * V,
+// and the plane stride PS = NB + 4 puts neighbouring lanes' stores in
+// different banks.  Each lane issues its
 // gathers for kGather / NR entries before the first LDS store so their
 // latencies overlap.  `after_issue()` runs once, right after the first
 // round of gathers is issued: that round is straight-line code, so loads
@@ -177,9 +179,9 @@ __device__ __forceinline__ void stage_rows(const CT *__restrict__ F, int W, int 
         return;
     }
     const int spl = 64 / U;
-    const int lu = threadIdx.x / spl;
-    int ls = threadIdx.x - lu * spl;
-    const bool act = lu < U;
+    int ls = threadIdx.x / U;
+    const int lu = threadIdx.x - ls * U;
+    const bool act = ls < spl;
     if (!act) ls = cnt;  // idle lanes: every entry they touch is past the end
     const int luc = act ? lu : 0;
     constexpr int K = kGather / NR;
@@ -828,7 +830,7 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
     geo.NB = NB;
     geo.offv = pad_to((int)((size_t)NB * 8 / cts), V);
     geo.offw = geo.offv + pad_to(NB, V);
-    geo.PS = NB + 1;  // one spare unit per plane staggers the planes' banks
+    geo.PS = pad_to(NB, 8) + 4;  // staggers the planes' banks (see stage_rows)
     geo.offa = geo.offw + pad_to(NB, V);
     geo.offb = geo.offa + geo.PS * nA * geo.W1;
     const size_t lds_elems = (size_t)geo.offb + (size_t)geo.PS * nB * geo.W2;
