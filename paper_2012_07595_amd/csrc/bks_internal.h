@@ -135,7 +135,7 @@ struct Tensor {
     Segmented op;    // pairs (i <= j): entries (-, k)                (MODE3)
     std::vector<int32_t> pair_i, pair_j;
     std::mutex sched_mu;
-    std::map<std::pair<int, int>, std::unique_ptr<Schedule>> sched;  // (order, E) -> schedule
+    std::map<std::pair<int, int>, std::unique_ptr<Schedule>> sched;  // (order, E or CW) -> schedule
     const Schedule &schedule(int order, int E);
     void release_device();  // free every device buffer (ctx teardown)
 };
@@ -150,6 +150,12 @@ constexpr int kHeavySteps = 32;
 constexpr int kLightMax = 48;
 void build_schedule(const std::vector<int64_t> &segptr, int E, std::vector<Item> &items,
                     std::vector<Fixup> &fix, int64_t &nslots);
+// Wide symmetric products: every slice is cut into chunks of at most CW
+// entries, one item each (slot = item index); fix[s] lists slice s's items
+// (every slice, empty ones with nslots = 0).  Cached as order kWideOrder.
+constexpr int kWideOrder = 3;
+void build_wide_schedule(const std::vector<int64_t> &segptr, int CW, std::vector<Item> &items,
+                         std::vector<Fixup> &fix, int64_t &nslots);
 
 // ---------------------------------------------------------------- TTMc
 // Launch a TTMc on device buffers; dtype of B/out follows prec.

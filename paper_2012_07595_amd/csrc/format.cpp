@@ -324,6 +324,23 @@ void build_schedule(const std::vector<int64_t> &segptr, int E, std::vector<Item>
     }
 }
 
+void build_wide_schedule(const std::vector<int64_t> &segptr, int CW, std::vector<Item> &items,
+                         std::vector<Fixup> &fix, int64_t &nslots) {
+    const int64_t nseg = (int64_t)segptr.size() - 1;
+    items.clear();
+    fix.clear();
+    for (int64_t s = 0; s < nseg; ++s) {
+        const int64_t len = segptr[s + 1] - segptr[s];
+        const int64_t nch = (len + CW - 1) / CW;
+        fix.push_back({(int32_t)s, (int32_t)items.size(), (int32_t)nch, 0});
+        for (int64_t c = 0; c < nch; ++c) {
+            const int64_t b = segptr[s] + c * CW, e = std::min(segptr[s + 1], b + CW);
+            items.push_back({(int32_t)s, -1, b, e, (int32_t)items.size(), 0});
+        }
+    }
+    nslots = (int64_t)items.size();
+}
+
 void Tensor::release_device() {
     std::lock_guard<std::mutex> g(sched_mu);
     for (Segmented *o : {&o3, &o1, &op}) {
@@ -344,11 +361,15 @@ const Schedule &Tensor::schedule(int order, int E) {
     auto key = std::make_pair(order, E);
     auto it = sched.find(key);
     if (it != sched.end()) return *it->second;
-    const Segmented &o = order == 0 ? o3 : (order == 1 ? o1 : op);
     std::vector<Item> items;
     std::vector<Fixup> fx;
     auto sc = std::make_unique<Schedule>();
-    build_schedule(o.h_segptr, E, items, fx, sc->nslots);
+    if (order == kWideOrder) {
+        build_wide_schedule(o3.h_segptr, E, items, fx, sc->nslots);
+    } else {
+        const Segmented &o = order == 0 ? o3 : (order == 1 ? o1 : op);
+        build_schedule(o.h_segptr, E, items, fx, sc->nslots);
+    }
     sc->nitems = (int64_t)items.size();
     sc->nfix = (int64_t)fx.size();
     if (!items.empty()) {

@@ -553,6 +553,121 @@ __global__ __launch_bounds__(256) void ttmc_sym_wide(
         }
 }
 
+// ---------------------------------------------------------------- wide sym, Gram form
+// A.(X, X)_{1,2} for wide X as a sum of per-entry outer products: with
+// v' = v off the diagonal and v / 2 on it (i = j), the symmetric result of
+// slice k is M + M^T, M = sum over stored (i, j, k) of v' X(i,:)^T X(j,:).
+// One workgroup of T x T threads (an R x R register tile each, T*R >= p)
+// accumulates M for one item (a slice or a chunk of a long slice) from
+// rows of the block-packed X staged in LDS, kGramChunk entries at a time,
+// and writes it to its partial slot; `sym_gram_reduce` sums a slice's
+// chunks in order and writes the upper triangle of M + M^T.
+constexpr int kGramChunk = 16;
+
+template <typename VT, typename CT, int R>
+__global__ __launch_bounds__(256) void ttmc_sym_gram(const Item *__restrict__ items,
+                                                     const int2 *__restrict__ c12,
+                                                     const VT *__restrict__ val,
+                                                     const CT *__restrict__ Xp, int T, int RP,
+                                                     int p, CT *__restrict__ part) {
+    using VT4 = typename Vec<CT>::T;
+    constexpr int V = Vec<CT>::V;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int W = T * RP;  // packed row width (elements)
+    const int U = W / V;
+    CT *s_xi = reinterpret_cast<CT *>(lds_raw);  // [kGramChunk][W], scaled by v'
+    CT *s_xj = s_xi + kGramChunk * W;           // [kGramChunk][W]
+    CT *s_v = s_xj + kGramChunk * W;            // [kGramChunk]
+    i32x2 *s_ij = reinterpret_cast<i32x2 *>(s_v + pad_to(kGramChunk, V));
+    const i32x2 *__restrict__ cp = reinterpret_cast<const i32x2 *>(c12);
+
+    const Item it = items[blockIdx.x];
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int ty = tid / T, tx = tid - (tid / T) * T;
+    const bool active = ty < T;
+    CT acc[R][R];
+#pragma unroll
+    for (int a = 0; a < R; ++a)
+#pragma unroll
+        for (int b = 0; b < R; ++b) acc[a][b] = CT(0);
+    // staging walk: thread -> (entry, unit of the entry's two rows)
+    const int two_u = 2 * U;
+    const int e0 = tid / two_u, r0 = tid - e0 * two_u;
+    const int de = nth / two_u, dr = nth - de * two_u;
+
+    for (int64_t b0 = it.beg; b0 < it.end; b0 += kGramChunk) {
+        const int cnt = (int)min<int64_t>(kGramChunk, it.end - b0);
+        for (int x = tid; x < cnt; x += nth) {
+            const i32x2 c = cp[b0 + x];
+            const CT v = static_cast<CT>(val[b0 + x]);
+            s_ij[x] = c;
+            s_v[x] = c.x == c.y ? v * CT(0.5) : v;
+        }
+        __syncthreads();
+        for (int e = e0, rem = r0; e < cnt;) {
+            const int w = rem >= U ? 1 : 0;
+            const int u = rem - w * U;
+            const i32x2 c = s_ij[e];
+            VT4 d = reinterpret_cast<const VT4 *>(Xp + (int64_t)(w ? c.y : c.x) * W)[u];
+            if (!w) d = d * s_v[e];
+            reinterpret_cast<VT4 *>((w ? s_xj : s_xi) + e * W)[u] = d;
+            e += de;
+            rem += dr;
+            if (rem >= two_u) {
+                rem -= two_u;
+                ++e;
+            }
+        }
+        __syncthreads();
+        if (active) {
+            for (int e = 0; e < cnt; ++e) {
+                CT xa[R], xb[R];
+                lds_block<CT, R>(s_xi + e * W + ty * RP, V, xa);
+                lds_block<CT, R>(s_xj + e * W + tx * RP, V, xb);
+#pragma unroll
+                for (int a = 0; a < R; ++a)
+#pragma unroll
+                    for (int b = 0; b < R; ++b) acc[a][b] = fma(xa[a], xb[b], acc[a][b]);
+            }
+        }
+        __syncthreads();
+    }
+    if (active) {
+        CT *o = part + (int64_t)it.slot * p * p;
+#pragma unroll
+        for (int a = 0; a < R; ++a) {
+            const int alpha = ty * R + a;
+            if (alpha < p)
+#pragma unroll
+                for (int b = 0; b < R; ++b) {
+                    const int beta = tx * R + b;
+                    if (beta < p) o[(int64_t)alpha * p + beta] = acc[a][b];
+                }
+        }
+    }
+}
+
+// out(k, beta(beta+1)/2 + alpha) = sum over slice k's chunks c, in order, of
+// M_c(alpha, beta) + M_c(beta, alpha), alpha <= beta (zero for an empty slice).
+template <typename CT>
+__global__ __launch_bounds__(256) void sym_gram_reduce(const Fixup *__restrict__ fix,
+                                                       const CT *__restrict__ part, int p,
+                                                       CT *__restrict__ out, int64_t ldo) {
+    const Fixup f = fix[blockIdx.x];
+    const int64_t pp = (int64_t)p * p;
+    for (int x = threadIdx.x; x < p * p; x += 256) {
+        const int alpha = x / p, beta = x - (x / p) * p;
+        if (alpha > beta) continue;
+        CT s = CT(0);
+        for (int c = 0; c < f.nslots; ++c) {
+            const CT *m = part + (int64_t)(f.first_slot + c) * pp;
+            s += m[(int64_t)alpha * p + beta];
+            s += m[(int64_t)beta * p + alpha];
+        }
+        out[(int64_t)f.seg * ldo + beta * (beta + 1) / 2 + alpha] = s;
+    }
+}
+
 // ---------------------------------------------------------------- dispatch
 template <typename VT, typename CT, int PA, int PB, int MODE>
 void launch_wave(dim3 grid, size_t lds, hipStream_t s, const Item *items,
@@ -625,6 +740,57 @@ void launch_sym_wide(const Segmented &o, const VT *val, const CT *X, int64_t ldx
     hipLaunchKernelGGL((ttmc_sym_wide<VT, CT>), dim3((unsigned)blocks), dim3(256), 0, s,
                        o.segptr.as<int64_t>(), o.c1.as<int2>(), val, X,
                        ldx, p, ntile, out, ldo);
+}
+
+template <typename VT, typename CT, int R>
+void launch_gram(dim3 grid, dim3 block, size_t lds, hipStream_t s, const Item *items,
+                 const int2 *c12, const VT *val, const CT *Xp, int T, int RP, int p, CT *part) {
+    hipLaunchKernelGGL((ttmc_sym_gram<VT, CT, R>), grid, block, lds, s, items, c12, val, Xp, T,
+                       RP, p, part);
+}
+
+template <typename VT, typename CT>
+bool launch_gram_r(int R, dim3 grid, dim3 block, size_t lds, hipStream_t s, const Item *items,
+                   const int2 *c12, const VT *val, const CT *Xp, int T, int RP, int p, CT *part) {
+    switch (R) {
+    case 4: launch_gram<VT, CT, 4>(grid, block, lds, s, items, c12, val, Xp, T, RP, p, part); return true;
+    case 5: launch_gram<VT, CT, 5>(grid, block, lds, s, items, c12, val, Xp, T, RP, p, part); return true;
+    case 6: launch_gram<VT, CT, 6>(grid, block, lds, s, items, c12, val, Xp, T, RP, p, part); return true;
+    case 7: launch_gram<VT, CT, 7>(grid, block, lds, s, items, c12, val, Xp, T, RP, p, part); return true;
+    case 8: launch_gram<VT, CT, 8>(grid, block, lds, s, items, c12, val, Xp, T, RP, p, part); return true;
+    default: break;
+    }
+    if constexpr (sizeof(CT) == 4) {
+        switch (R) {
+        case 9: launch_gram<VT, CT, 9>(grid, block, lds, s, items, c12, val, Xp, T, RP, p, part); return true;
+        case 10: launch_gram<VT, CT, 10>(grid, block, lds, s, items, c12, val, Xp, T, RP, p, part); return true;
+        case 11: launch_gram<VT, CT, 11>(grid, block, lds, s, items, c12, val, Xp, T, RP, p, part); return true;
+        case 12: launch_gram<VT, CT, 12>(grid, block, lds, s, items, c12, val, Xp, T, RP, p, part); return true;
+        default: break;
+        }
+    }
+    return false;
+}
+
+// Register tile R and thread grid T x T for width p: the fewest lane-FMAs
+// per entry (whole waves x R^2) with T <= 16; R <= 12 (FP32) or 8 (FP64).
+// false if p is too wide for one workgroup.
+bool choose_gram(int p, bool dbl, int &R, int &T) {
+    const int rmax = dbl ? 8 : 12;
+    double best = 1e300;
+    R = 0;
+    for (int r = 4; r <= rmax; ++r) {
+        const int t = (p + r - 1) / r;
+        if (t > 16) continue;
+        const int waves = (t * t + 63) / 64;
+        const double cost = (double)waves * 64 * (r * r + 2 * r);
+        if (cost < best) {
+            best = cost;
+            R = r;
+            T = t;
+        }
+    }
+    return R > 0;
 }
 
 }  // namespace
@@ -771,6 +937,69 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
     const void *val = val64 ? o.v64.ptr : o.v32.ptr;
 
     if (op == BKS_FREE3 && outmode == OUT_SYM && px > kWideThreshold) {
+        int R, T;
+        if (choose_gram(px, dbl, R, T)) {
+            const int V = dbl ? 2 : 4;
+            const int RP = pad_to(R, V), W = T * RP;
+            // chunk width: at most ~512 MB of partial matrices
+            const double per_item = (double)px * px * cts;
+            const int64_t max_items = std::max<int64_t>(o.nseg + 1, (int64_t)(536870912.0 / per_item));
+            const int64_t cw64 = std::max<int64_t>(2048, t.nnz / std::max<int64_t>(1, max_items - o.nseg) + 1);
+            const int CW = (int)std::min<int64_t>(cw64, 1 << 30);
+            const Schedule &sc = t.schedule(kWideOrder, CW);
+            c.ws_fac1.ensure((size_t)std::max<int64_t>(t.m, 1) * W * cts);
+            {
+                const int64_t total = t.m * W;
+                const unsigned grid = (unsigned)std::max<int64_t>(
+                    1, std::min<int64_t>((total + 255) / 256, 4096));
+                if (dbl)
+                    hipLaunchKernelGGL(pack_blocks<double>, dim3(grid), dim3(256), 0, s,
+                                       static_cast<const double *>(F1), l1, t.m, px, R, RP, W,
+                                       c.ws_fac1.as<double>());
+                else
+                    hipLaunchKernelGGL(pack_blocks<float>, dim3(grid), dim3(256), 0, s,
+                                       static_cast<const float *>(F1), l1, t.m, px, R, RP, W,
+                                       c.ws_fac1.as<float>());
+                HIPCHECK(hipGetLastError());
+            }
+            if (sc.nitems > 0) c.ws_partial.ensure((size_t)sc.nitems * px * px * cts);
+            const dim3 block((unsigned)((T * T + 63) / 64 * 64));
+            const size_t lds = (size_t)(2 * kGramChunk * W + pad_to(kGramChunk, V)) * cts +
+                               (size_t)kGramChunk * 8;
+            bool ok = true;
+            if (sc.nitems > 0) {
+                const dim3 grid((unsigned)sc.nitems);
+                if (prec == BKS_F32)
+                    ok = launch_gram_r<float, float>(R, grid, block, lds, s, sc.items.as<Item>(),
+                                                     o.c1.as<int2>(), o.v32.as<float>(),
+                                                     c.ws_fac1.as<float>(), T, RP, px,
+                                                     c.ws_partial.as<float>());
+                else if (val64)
+                    ok = launch_gram_r<double, double>(R, grid, block, lds, s, sc.items.as<Item>(),
+                                                       o.c1.as<int2>(), o.v64.as<double>(),
+                                                       c.ws_fac1.as<double>(), T, RP, px,
+                                                       c.ws_partial.as<double>());
+                else
+                    ok = launch_gram_r<float, double>(R, grid, block, lds, s, sc.items.as<Item>(),
+                                                      o.c1.as<int2>(), o.v32.as<float>(),
+                                                      c.ws_fac1.as<double>(), T, RP, px,
+                                                      c.ws_partial.as<double>());
+                HIPCHECK(hipGetLastError());
+            }
+            if (!ok) fail(BKS_EINVAL, "no wide kernel for this width");
+            if (sc.nfix > 0) {
+                if (dbl)
+                    hipLaunchKernelGGL(sym_gram_reduce<double>, dim3((unsigned)sc.nfix), dim3(256),
+                                       0, s, sc.fix.as<Fixup>(), c.ws_partial.as<double>(), px,
+                                       static_cast<double *>(out), ldo);
+                else
+                    hipLaunchKernelGGL(sym_gram_reduce<float>, dim3((unsigned)sc.nfix), dim3(256),
+                                       0, s, sc.fix.as<Fixup>(), c.ws_partial.as<float>(), px,
+                                       static_cast<float *>(out), ldo);
+                HIPCHECK(hipGetLastError());
+            }
+            return;
+        }
         if (prec == BKS_F32)
             launch_sym_wide<float, float>(o, o.v32.as<float>(), static_cast<const float *>(F1),
                                           l1, px, static_cast<float *>(out), ldo, o.nseg, s);
