@@ -39,33 +39,53 @@ def dist(Ua, Ub):
     return float(np.linalg.norm(Qb - Qa @ (Qa.T @ Qb), 2))
 
 
-def roofline_of(stats):
-    """Dominant kernel class (by total event time) and its roofline."""
+def load_traffic(kernel_class, workload):
+    """HBM traffic per launch of `kernel_class` on `workload` from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by a
+    plain copy of known size), or None if there is none for this kernel."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            tab = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = tab.get(f"{workload}/{kernel_class}")
+    return None if ent is None else ent.get("bytes_per_launch")
+
+
+def roofline_of(stats, workload=None):
+    """Dominant kernel (by total event time of its main kernel) and its
+    roofline.  `<class>_call` entries time whole calls (packing, fixups and
+    reductions included) and are reported beside it."""
     if not stats:
         return None
-    name, (calls, ms, by, fl) = max(stats.items(), key=lambda kv: kv[1][1])
+    main = {k: v for k, v in stats.items() if not k.endswith("_call")}
+    name, (calls, ms, by, fl) = max(main.items(), key=lambda kv: kv[1][1])
+    call = stats.get(name + "_call")
+    extra = {"call_avg_us": round(call[1] / call[0] * 1e3, 2)} if call else {}
+    traffic = load_traffic(name, workload) if workload else None
     avg_s = ms / calls / 1e3
     if name.startswith("free3_sym_wide"):
         peak = FP32_PEAK_TFLOPS if name.endswith("_f32") else FP64_PEAK_TFLOPS
         ach = fl / calls / avg_s / 1e12
         return {"kernel": "ttmc_" + name, "bound": "alu", "achieved": round(ach, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": traffic,
                 "launches": calls, "avg_launch_us": round(avg_s * 1e6, 2),
-                "algorithmic_flops_per_launch": fl / calls}
+                "algorithmic_flops_per_launch": fl / calls, **extra}
     alu_peak = FP32_PEAK_TFLOPS if name.endswith("_f32") else FP64_PEAK_TFLOPS
     if fl / (alu_peak * 1e12) > by / (HBM_PEAK_GBS * 1e9):
         # more time at the vector ALU peak than at the HBM peak: ALU-bound
         ach = fl / calls / avg_s / 1e12
         return {"kernel": "ttmc_" + name, "bound": "alu", "achieved": round(ach, 3),
                 "peak": alu_peak, "unit": "TFLOP/s", "frac": round(ach / alu_peak, 4),
-                "traffic": None, "launches": calls, "avg_launch_us": round(avg_s * 1e6, 2),
+                "traffic": traffic, "launches": calls, "avg_launch_us": round(avg_s * 1e6, 2),
                 "algorithmic_flops_per_launch": fl / calls,
-                "hbm_GBs": round(by / calls / avg_s / 1e9, 1)}
+                "hbm_GBs": round(by / calls / avg_s / 1e9, 1), **extra}
     ach = by / calls / avg_s / 1e9
     return {"kernel": "ttmc_" + name, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
             "launches": calls, "avg_launch_us": round(avg_s * 1e6, 2),
-            "algorithmic_bytes_per_launch": by / calls}
+            "algorithmic_bytes_per_launch": by / calls, **extra}
 
 
 def cpu_baseline(coo, r, U0, W0, gpu_iters):
@@ -168,12 +188,28 @@ def run_bks(args):
         "svals1": list(np.round(info.svals1[:rank + 1], 4)),
         "svals3": list(np.round(info.svals3[:rank + 1], 4)),
         "kernels": {k: {"calls": v[0], "ms": round(v[1], 3)} for k, v in stats.items()},
-        "roofline": roofline_of(stats),
+        "roofline": roofline_of(stats, workload=args.workload),
         "gen_s": round(t_gen, 2),
     }
+    if args.copy_ref_mb:
+        copy_reference(args.copy_ref_mb)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(coo, rank, U0, W0, iters)
     print(json.dumps(out), flush=True)
+
+
+def copy_reference(mb):
+    """A plain device copy of `mb` MiB (outside any timed region): the
+    reference that scales the FETCH_SIZE / WRITE_SIZE counters of a profiled
+    run to bytes."""
+    import torch
+    nb = mb << 20
+    a = torch.ones(nb // 4, device="cuda:0", dtype=torch.float32)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_ref_bytes": nb}), file=sys.stderr, flush=True)
 
 
 def ttmc_sweep(args):
@@ -220,18 +256,10 @@ def ttmc_sweep(args):
         torch.cuda.synchronize()
         st = ctx.profile_read()
         ctx.profile(False)
-        rl = roofline_of(st)
+        rl = roofline_of(st, workload=f"c3/{name}{p2}")
         print(json.dumps({"op": name, "p": p2, "roofline": rl}), flush=True)
     if args.copy_ref_mb:
-        # a plain device copy of known size: the reference that scales the
-        # FETCH_SIZE / WRITE_SIZE counters of the products above
-        nb = args.copy_ref_mb << 20
-        a = torch.ones(nb // 4, device=dev, dtype=torch.float32)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_ref_bytes": nb}), flush=True)
+        copy_reference(args.copy_ref_mb)
 
 
 def serving(args):

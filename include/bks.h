@@ -137,7 +137,10 @@ void bks_tensor_free(bks_tensor t);
  * prec: BKS_F32 (B1, B2, out are float), BKS_F64 or BKS_F32IN_F64ACC
  * (double).  ld1/ld2/ldo are row strides in elements.  Widths p1, p2 must be
  * >= 1; FREE1 and X != Y products need p1*p2 <= 1600.  The result overwrites
- * out; every output row is written.  Device workspace is owned by ctx.
+ * out; every output row is written.  Device workspace (block-packed factor
+ * copies, split-segment partial rows) is owned by ctx and grows on demand:
+ * calls on one ctx whose execution overlaps on different streams race on
+ * it, so use one stream per ctx (or one ctx per stream).
  * Errors: BKS_EINVAL, BKS_ENOMEM, BKS_EDEVICE. */
 int bks_ttmc(bks_ctx ctx, bks_tensor t, int op, const void *B1, int64_t ld1, int p1,
              const void *B2, int64_t ld2, int p2, int sym_half, int prec, void *out,

@@ -703,7 +703,11 @@ size_t solve_footprint(int64_t m, int64_t n, const bks_params &prm) {
     b += (size_t)m * prm.r * prm.r3 * 8 + (size_t)n * (prm.r * (prm.r + 1) / 2) * 8;
     b += (size_t)n * Q * (mixed ? 4 : 8) + k3 * Q * 8;
     b += 2 * std::max(k1, k3) * std::max<size_t>(q, 64) * 8 + 64 * 64 * 16;
-    // product partials and the split reductions (grow-only workspaces)
+    // product partials and the split reductions (grow-only workspaces): the
+    // wide core product keeps one k1 x k1 partial per slice chunk and a
+    // block-packed copy of X
+    const size_t cts = mixed ? 4 : 8;
+    b += (size_t)n * k1 * k1 * cts + (size_t)m * (k1 + 16) * cts;
     b += (size_t)n * Q * 8 / 4 + rows * 64 * 8 + (size_t)(1 << 20) * 8;
     return b;
 }

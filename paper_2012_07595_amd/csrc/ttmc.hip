@@ -800,7 +800,7 @@ constexpr int kWideThresholdPublic = kWideThreshold;
 
 static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, int p1,
                         const void *B2, int64_t ld2, int p2, bool sym_half, int prec, void *out,
-                        int64_t ldo, hipStream_t s);
+                        int64_t ldo, hipStream_t s, hipEvent_t *mk = nullptr);
 
 // Algorithmic traffic and flops of one product: the stored tensor read once
 // (two 4-byte indices and the value per stored entry; the mode-3 product
@@ -835,16 +835,22 @@ void ttmc(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, int p1, const 
         ttmc_launch(c, t, op, B1, ld1, p1, B2, ld2, p2, sym_half, prec, out, ldo, s);
         return;
     }
-    hipEvent_t a, b;
+    // two classes per product: `name` times its main kernel alone (what a
+    // kernel trace reports for it), `name_call` the whole call (factor
+    // packing, split-segment fixup or chunk reduction included)
+    hipEvent_t a, b, mk[2];
     HIPCHECK(hipEventCreate(&a));
     HIPCHECK(hipEventCreate(&b));
+    HIPCHECK(hipEventCreate(&mk[0]));
+    HIPCHECK(hipEventCreate(&mk[1]));
     HIPCHECK(hipEventRecord(a, s));
-    ttmc_launch(c, t, op, B1, ld1, p1, B2, ld2, p2, sym_half, prec, out, ldo, s);
+    ttmc_launch(c, t, op, B1, ld1, p1, B2, ld2, p2, sym_half, prec, out, ldo, s, mk);
     HIPCHECK(hipEventRecord(b, s));
     std::string name;
     double bytes, flops;
     ttmc_cost(t, op, p1, p2, sym_half, B2 == nullptr || B2 == B1, prec, name, bytes, flops);
-    c.prof_record(name, a, b, bytes, flops);
+    c.prof_record(name, mk[0], mk[1], bytes, flops);
+    c.prof_record(name + "_call", a, b, bytes, flops);
 }
 
 void Ctx::prof_record(const std::string &name, hipEvent_t a, hipEvent_t b, double bytes,
@@ -874,7 +880,11 @@ void Ctx::prof_flush() {
 
 static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, int p1,
                         const void *B2, int64_t ld2, int p2, bool sym_half, int prec, void *out,
-                        int64_t ldo, hipStream_t s) {
+                        int64_t ldo, hipStream_t s, hipEvent_t *mk) {
+    // mk (profiling): events recorded right around the product's main kernel
+    auto mark = [&](int w) {
+        if (mk) HIPCHECK(hipEventRecord(mk[w], s));
+    };
     if (prec != BKS_F32 && prec != BKS_F64 && prec != BKS_F32IN_F64ACC)
         fail(BKS_EINVAL, "unknown precision");
     const bool dbl = prec != BKS_F32;
@@ -933,7 +943,11 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
     }
     if (!out) fail(BKS_EINVAL, "null output");
     const Segmented &o = order == 0 ? t.o3 : (order == 1 ? t.o1 : t.op);
-    if (o.nseg == 0) return;
+    if (o.nseg == 0) {
+        mark(0);
+        mark(1);
+        return;
+    }
     const void *val = val64 ? o.v64.ptr : o.v32.ptr;
 
     if (op == BKS_FREE3 && outmode == OUT_SYM && px > kWideThreshold) {
@@ -967,6 +981,7 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
             const size_t lds = (size_t)(2 * kGramChunk * W + pad_to(kGramChunk, V)) * cts +
                                (size_t)kGramChunk * 8;
             bool ok = true;
+            mark(0);
             if (sc.nitems > 0) {
                 const dim3 grid((unsigned)sc.nitems);
                 if (prec == BKS_F32)
@@ -986,6 +1001,7 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
                                                       c.ws_partial.as<double>());
                 HIPCHECK(hipGetLastError());
             }
+            mark(1);
             if (!ok) fail(BKS_EINVAL, "no wide kernel for this width");
             if (sc.nfix > 0) {
                 if (dbl)
@@ -1000,6 +1016,7 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
             }
             return;
         }
+        mark(0);
         if (prec == BKS_F32)
             launch_sym_wide<float, float>(o, o.v32.as<float>(), static_cast<const float *>(F1),
                                           l1, px, static_cast<float *>(out), ldo, o.nseg, s);
@@ -1011,6 +1028,7 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
             launch_sym_wide<float, double>(o, o.v32.as<float>(),
                                            static_cast<const double *>(F1), l1, px,
                                            static_cast<double *>(out), ldo, o.nseg, s);
+        mark(1);
         HIPCHECK(hipGetLastError());
         return;
     }
@@ -1111,11 +1129,13 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
     else
         fn = pick<float, double>(mode, PA, PB);
     if (!fn) fail(BKS_EINVAL, "no kernel for this width");
+    mark(0);
     if (sc.nitems > 0)
         fn(dim3((unsigned)sc.nitems), lds, s, sc.items.as<Item>(), o.segptr.as<int64_t>(),
            mode == MODE_M3 ? nullptr : o.c1.as<int2>(),
            mode == MODE_M3 ? o.c2.as<int32_t>() : nullptr, val, P1, P2, geo, out, ldo,
            partial);
+    mark(1);
     HIPCHECK(hipGetLastError());
     if (sc.nfix > 0) {
         if (dbl)
