@@ -43,14 +43,29 @@ def load_traffic(kernel_class, workload):
     """HBM traffic per launch of `kernel_class` on `workload` from the committed
     rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by a
     plain copy of known size), or None if there is none for this kernel."""
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
+    root = os.path.dirname(os.path.abspath(__file__))
     try:
-        with open(path) as f:
+        with open(os.path.join(root, "profiles", "traffic.json")) as f:
             tab = json.load(f)
     except (OSError, ValueError):
         return None
+    # counters taken on another revision of the kernels do not count
+    for rel, sha in tab.get("_kernel_sources_sha1", {}).items():
+        if file_sha1(os.path.join(root, rel)) != sha:
+            return None
     ent = tab.get(f"{workload}/{kernel_class}")
     return None if ent is None else ent.get("bytes_per_launch")
+
+
+def file_sha1(path):
+    """git's blob id of a file (sha1 of 'blob <size>\\0' + content)."""
+    import hashlib
+    try:
+        with open(path, "rb") as f:
+            data = f.read()
+    except OSError:
+        return None
+    return hashlib.sha1(b"blob %d\0" % len(data) + data).hexdigest()
 
 
 def roofline_of(stats, workload=None):

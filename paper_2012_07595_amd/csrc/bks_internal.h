@@ -73,10 +73,19 @@ struct Fixup {
 struct Schedule {
     int64_t nitems = 0;
     int64_t nfix = 0;
-    int64_t nslots = 0;
+    int64_t nslots = 0;  // partial slots incl. the tree levels' slots
     DevBuf items;  // Item[nitems]
-    DevBuf fix;    // Fixup[nfix]
+    DevBuf fix;    // Fixup[nfix]: final sums into the output rows
+    // Segments with more than kFixFan partial slots are first reduced in a
+    // fixed tree: each level's Fixup sums up to kFixFan slots into the slot
+    // named by its `seg` field; levels run in order before `fix`.
+    struct Level {
+        int64_t nfix = 0;
+        DevBuf fix;
+    };
+    std::vector<std::unique_ptr<Level>> levels;
 };
+constexpr int kFixFan = 64;
 
 struct Tensor;
 

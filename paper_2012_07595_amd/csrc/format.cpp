@@ -370,6 +370,33 @@ const Schedule &Tensor::schedule(int order, int E) {
         const Segmented &o = order == 0 ? o3 : (order == 1 ? o1 : op);
         build_schedule(o.h_segptr, E, items, fx, sc->nslots);
     }
+    // tree levels for segments with many partial slots (see Schedule); the
+    // wide schedule's chunks are summed by their own reduce kernel
+    while (order != kWideOrder) {
+        bool deep = false;
+        for (const Fixup &f : fx) deep = deep || f.nslots > kFixFan;
+        if (!deep) break;
+        std::vector<Fixup> lv, next;
+        for (const Fixup &f : fx) {
+            if (f.nslots <= kFixFan) {
+                next.push_back(f);
+                continue;
+            }
+            const int32_t ng = (f.nslots + kFixFan - 1) / kFixFan;
+            for (int32_t g = 0; g < ng; ++g)
+                lv.push_back({(int32_t)(sc->nslots + g), f.first_slot + g * kFixFan,
+                              std::min<int32_t>(kFixFan, f.nslots - g * kFixFan), 0});
+            next.push_back({f.seg, (int32_t)sc->nslots, ng, 0});
+            sc->nslots += ng;
+        }
+        auto L = std::make_unique<Schedule::Level>();
+        L->nfix = (int64_t)lv.size();
+        L->fix.alloc(lv.size() * sizeof(Fixup));
+        HIPCHECK(hipMemcpy(L->fix.ptr, lv.data(), lv.size() * sizeof(Fixup),
+                           hipMemcpyHostToDevice));
+        sc->levels.push_back(std::move(L));
+        fx.swap(next);
+    }
     sc->nitems = (int64_t)items.size();
     sc->nfix = (int64_t)fx.size();
     if (!items.empty()) {

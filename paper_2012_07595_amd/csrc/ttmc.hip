@@ -433,10 +433,12 @@ __global__ __launch_bounds__(256) void pack_blocks(const CT *__restrict__ F, int
 // Sum the partial rows of one split segment: 256 threads as (slot lane,
 // column); each lane sums a strided subset of the slots, then a fixed-order
 // tree over the lanes in LDS (deterministic).
+// (Tree levels call it with out = partial, ldo = q: the slots read and the
+// slot written are disjoint.)
 template <typename CT>
 __global__ __launch_bounds__(256) void ttmc_fixup(const Fixup *__restrict__ fix,
-                                                  const CT *__restrict__ partial, int q,
-                                                  CT *__restrict__ out, int64_t ldo) {
+                                                  const CT *partial, int q, CT *out,
+                                                  int64_t ldo) {
     __shared__ CT red[256];
     const Fixup f = fix[blockIdx.x];
     const int cols = q < 256 ? q : 256;
@@ -1137,6 +1139,17 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
            partial);
     mark(1);
     HIPCHECK(hipGetLastError());
+    for (const auto &L : sc.levels) {
+        if (dbl)
+            hipLaunchKernelGGL(ttmc_fixup<double>, dim3((unsigned)L->nfix), dim3(256), 0, s,
+                               L->fix.as<Fixup>(), static_cast<const double *>(partial), q,
+                               static_cast<double *>(partial), (int64_t)q);
+        else
+            hipLaunchKernelGGL(ttmc_fixup<float>, dim3((unsigned)L->nfix), dim3(256), 0, s,
+                               L->fix.as<Fixup>(), static_cast<const float *>(partial), q,
+                               static_cast<float *>(partial), (int64_t)q);
+        HIPCHECK(hipGetLastError());
+    }
     if (sc.nfix > 0) {
         if (dbl)
             hipLaunchKernelGGL(ttmc_fixup<double>, dim3((unsigned)sc.nfix), dim3(256), 0, s,
