@@ -39,6 +39,18 @@ def dist(Ua, Ub):
     return float(np.linalg.norm(Qb - Qa @ (Qa.T @ Qb), 2))
 
 
+WORKLOAD_TEXT = {
+    "c2p": "C2-shaped (1,2)-symmetric 20000x20000x2000, 2e6 stored, Zipf(1.3) modes 1-2, "
+           "uniform mode 3, |N(0,1)| FP32 + planted rank-(5,5,5)",
+    "c2": "C2-shaped (1,2)-symmetric 20000x20000x2000, 2e6 stored, Zipf(1.3) modes 1-2, "
+          "uniform mode 3, |N(0,1)| FP32",
+    "c3": "C3-shaped (1,2)-symmetric 200000x200000x10000, 5e7 stored, Zipf(1.5) modes 1-2, "
+          "uniform mode 3, |N(0,1)| FP32",
+    "c3p": "C3-shaped (1,2)-symmetric 200000x200000x10000, 5e7 stored, Zipf(1.5) modes 1-2, "
+           "uniform mode 3, |N(0,1)| FP32 + planted rank-(10,10,10)",
+}
+
+
 def load_traffic(kernel_class, workload):
     """HBM traffic per launch of `kernel_class` on `workload` from the committed
     rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by a
@@ -135,9 +147,10 @@ def cpu_baseline(coo, r, U0, W0, gpu_iters):
 
 def run_bks(args):
     import torch
-    rank = 5
+    rank = args.rank if args.rank else (10 if args.workload.startswith("c3") else 5)
     t_gen = time.perf_counter()
-    coo = workloads.c2_planted() if args.workload == "c2p" else workloads.c2()
+    coo = {"c2p": workloads.c2_planted, "c2": workloads.c2, "c3": workloads.c3,
+           "c3p": workloads.c3_planted}[args.workload]()
     U0, W0 = workloads.random_start(coo.m, coo.n, rank, rank, 2024)
     t_gen = time.perf_counter() - t_gen
     assert torch.cuda.is_available(), "bench needs a GPU"
@@ -182,9 +195,7 @@ def run_bks(args):
         "dtype": "f32 products + f64 orthogonalisation/inner solve (mixed)",
         "data": "synthetic",
         "config": {
-            "workload": ("C2-shaped (1,2)-symmetric 20000x20000x2000, 2e6 stored, Zipf(1.3) modes 1-2, "
-                         "uniform mode 3, |N(0,1)| FP32" +
-                         (" + planted rank-(5,5,5)" if args.workload == "c2p" else "")),
+            "workload": WORKLOAD_TEXT[args.workload],
             "rank": [rank, rank, rank], "method": f"BKS(2,4;{info.k1},{info.k3})",
             "precision": "mixed", "tol": 1e-11, "max_outer": args.max_outer,
         },
@@ -364,7 +375,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["c2p", "c2"], default="c2p")
+    ap.add_argument("--workload", choices=["c2p", "c2", "c3", "c3p"], default="c2p")
+    ap.add_argument("--rank", type=int, default=0)
     ap.add_argument("--max-outer", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--ttmc-sweep", action="store_true")

@@ -12,6 +12,8 @@
 #include <vector>
 
 #include "../../include/bks.h"
+#include "inner.h"
+#include "schedule.h"
 
 namespace bks {
 
@@ -53,23 +55,6 @@ struct Segmented {
     std::vector<int64_t> h_segptr;  // host copy for schedule building
 };
 
-// One wave-sized unit of work.  Heavy items cover [beg, end) of a single
-// long segment; light items cover whole short segments seg .. seg_end-1.
-struct Item {
-    int32_t seg;
-    int32_t seg_end;  // light: one past the last segment; heavy: -1
-    int64_t beg, end; // heavy entry range
-    int32_t slot;     // heavy split segment: partial slot, else -1
-    int32_t pad;
-};
-
-struct Fixup {
-    int32_t seg;
-    int32_t first_slot;
-    int32_t nslots;
-    int32_t pad;
-};
-
 struct Schedule {
     int64_t nitems = 0;
     int64_t nfix = 0;
@@ -85,21 +70,38 @@ struct Schedule {
     };
     std::vector<std::unique_ptr<Level>> levels;
 };
-constexpr int kFixFan = 64;
 
 struct Tensor;
 
 // Device Cholesky solver for large inner Newton systems (devsolve.cpp).
 struct DevSolver {
     void *handle = nullptr;  // rocblas_handle
-    DevBuf dA, db;
+    void *get_handle(hipStream_t s);  // created on first use, bound to s
+    DevBuf dH, dA, db, dones;
     DevSolver() = default;
     DevSolver(const DevSolver &) = delete;
     DevSolver &operator=(const DevSolver &) = delete;
     ~DevSolver();
-    // Solve H x = b (H N x N symmetric, row-major host) in place of b; false
-    // if H is not positive definite.
-    bool solve(hipStream_t s, int N, const double *H, double *b);
+    // Solve (H + mu I) x = b (H N x N symmetric, row-major host) in place of
+    // b; false if it is not positive definite.  H is uploaded only when
+    // new_matrix (it stays on the device between calls).
+    bool solve(hipStream_t s, int N, const double *H, double mu, bool new_matrix, double *b);
+};
+
+// Device products of the inner solve for large cores (devsolve.cpp):
+// rocBLAS FP64 on the ctx stream, sharing the DevSolver's handle.
+struct DevInner : InnerDevice {
+    DevSolver *ds = nullptr;
+    hipStream_t s = nullptr;
+    int k1 = 0, k3 = 0;
+    DevBuf dC, dA, dB, dOut, dT, dY;
+    void set_core(const double *C, int k1, int k3) override;
+    void gram1(double *G1) override;
+    void gram3(double *G3) override;
+    void mode3(const double *Sv, int ldS, int l0, int nl, double *out) override;
+    void hooi3(const double *P, int r, double *M3) override;
+    void rotate(const double *Qp, const double *Qs, int r, int r3, double *Y,
+                double *Y2) override;
 };
 
 // Event-timed launches of one kernel class (profiling).
@@ -124,6 +126,7 @@ struct Ctx {
     // optional bracket around host-side dense solves (serving: bounded pool)
     std::function<void()> host_acquire, host_release;
     DevSolver devsolve;
+    DevInner devinner;
     bool prof = false;
     std::mutex prof_mu;
     std::map<std::string, ProfClass> prof_stats;
@@ -152,19 +155,6 @@ struct Tensor {
 // Build formats from host COO (validated, canonicalised).  Throws Error.
 void build_formats(Tensor &t, const int32_t *i, const int32_t *j, const int32_t *k,
                    const void *val, int val_dtype, unsigned flags);
-
-// Schedules: heavy items take CH = max(E * kHeavySteps, 2048) entries; light segments
-// are at most kLightMax entries long.
-constexpr int kHeavySteps = 32;
-constexpr int kLightMax = 48;
-void build_schedule(const std::vector<int64_t> &segptr, int E, std::vector<Item> &items,
-                    std::vector<Fixup> &fix, int64_t &nslots);
-// Wide symmetric products: every slice is cut into chunks of at most CW
-// entries, one item each (slot = item index); fix[s] lists slice s's items
-// (every slice, empty ones with nslots = 0).  Cached as order kWideOrder.
-constexpr int kWideOrder = 3;
-void build_wide_schedule(const std::vector<int64_t> &segptr, int CW, std::vector<Item> &items,
-                         std::vector<Fixup> &fix, int64_t &nslots);
 
 // ---------------------------------------------------------------- TTMc
 // Launch a TTMc on device buffers; dtype of B/out follows prec.

@@ -1,8 +1,14 @@
-// Cholesky solve of the (shifted) Newton system of the inner solve on the
-// device, for systems too large for the host (N = r(k1 - r) + r3(k3 - r3)
-// reaches 2750 at rank (10,10,10)).  rocSOLVER's FP64 potrf/potrs on the
-// ctx's stream; the matrix is symmetric, so row-major input is its own
-// column-major transpose.
+// Device help for the inner solve (Algorithm 5 step (i)) of large cores:
+//  - Cholesky solve of the (shifted) Newton system, for systems too large for
+//    the host (N = r(k1 - r) + r3(k3 - r3) reaches 2750 at rank (10,10,10)):
+//    rocSOLVER's FP64 potrf/potrs on the ctx's stream; the matrix is
+//    symmetric, so row-major input is its own column-major transpose;
+//  - the dense products of the core (HOSVD Grams, mode-3 products, the
+//    rotation into [P P_perp], [S S_perp] coordinates) as rocBLAS FP64
+//    GEMMs.  Device matrices are column-major; a row-major host matrix
+//    uploaded as is reads as its transpose.
+#include <vector>
+
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
@@ -14,7 +20,7 @@ DevSolver::~DevSolver() {
     if (handle) rocblas_destroy_handle(static_cast<rocblas_handle>(handle));
 }
 
-bool DevSolver::solve(hipStream_t s, int N, const double *H, double *b) {
+void *DevSolver::get_handle(hipStream_t s) {
     if (!handle) {
         rocblas_handle h = nullptr;
         if (rocblas_create_handle(&h) != rocblas_status_success) fail(BKS_EDEVICE, "rocblas handle");
@@ -22,9 +28,31 @@ bool DevSolver::solve(hipStream_t s, int N, const double *H, double *b) {
     }
     rocblas_handle h = static_cast<rocblas_handle>(handle);
     if (rocblas_set_stream(h, s) != rocblas_status_success) fail(BKS_EDEVICE, "rocblas stream");
-    dA.ensure((size_t)N * N * 8);
+    return handle;
+}
+
+bool DevSolver::solve(hipStream_t s, int N, const double *H, double mu, bool new_matrix,
+                      double *b) {
+    rocblas_handle h = static_cast<rocblas_handle>(get_handle(s));
+    const size_t bytes = (size_t)N * N * 8;
+    if (new_matrix || dH.bytes < bytes) {
+        dH.ensure(bytes);
+        HIPCHECK(hipMemcpyAsync(dH.ptr, H, bytes, hipMemcpyHostToDevice, s));
+    }
+    dA.ensure(bytes);
     db.ensure((size_t)N * 8 + 64);
-    HIPCHECK(hipMemcpyAsync(dA.ptr, H, (size_t)N * N * 8, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(dA.ptr, dH.ptr, bytes, hipMemcpyDeviceToDevice, s));
+    if (mu != 0.0) {
+        // A += mu I: an AXPY of a vector of ones onto the diagonal (stride N + 1)
+        if (dones.bytes < (size_t)N * 8) {
+            std::vector<double> ones(N, 1.0);
+            dones.ensure((size_t)N * 8);
+            HIPCHECK(hipMemcpy(dones.ptr, ones.data(), (size_t)N * 8, hipMemcpyHostToDevice));
+        }
+        if (rocblas_daxpy(h, N, &mu, dones.as<double>(), 1, dA.as<double>(), N + 1) !=
+            rocblas_status_success)
+            fail(BKS_EDEVICE, "rocblas_daxpy");
+    }
     HIPCHECK(hipMemcpyAsync(db.ptr, b, (size_t)N * 8, hipMemcpyHostToDevice, s));
     rocblas_int *dinfo = reinterpret_cast<rocblas_int *>(db.as<char>() + (size_t)N * 8);
     if (rocsolver_dpotrf(h, rocblas_fill_lower, N, dA.as<double>(), N, dinfo) !=
@@ -40,6 +68,120 @@ bool DevSolver::solve(hipStream_t s, int N, const double *H, double *b) {
     HIPCHECK(hipMemcpyAsync(b, db.ptr, (size_t)N * 8, hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
     return true;
+}
+
+
+// ---------------------------------------------------------------- DevInner
+namespace {
+void check_rb(rocblas_status st, const char *what) {
+    if (st != rocblas_status_success) fail(BKS_EDEVICE, what);
+}
+void dgemm_sb(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
+              const double *A, int lda, int64_t sA, const double *B, int ldb, int64_t sB,
+              double *C, int ldc, int64_t sC, int batch) {
+    const double one = 1.0, zero = 0.0;
+    check_rb(rocblas_dgemm_strided_batched(h, ta, tb, m, n, k, &one, A, lda, sA, B, ldb, sB, &zero,
+                                           C, ldc, sC, batch),
+             "rocblas_dgemm_strided_batched");
+}
+}  // namespace
+
+void DevInner::set_core(const double *C, int k1_, int k3_) {
+    k1 = k1_;
+    k3 = k3_;
+    const size_t n = (size_t)k1 * k1 * k3;
+    dC.ensure(n * 8);
+    HIPCHECK(hipMemcpyAsync(dC.ptr, C, n * 8, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipStreamSynchronize(s));
+}
+
+void DevInner::gram1(double *G1) {
+    rocblas_handle h = static_cast<rocblas_handle>(ds->get_handle(s));
+    dOut.ensure((size_t)k1 * k1 * 8);
+    // C is the column-major k1 x (k1 k3) matrix C_(1)
+    dgemm_sb(h, rocblas_operation_none, rocblas_operation_transpose, k1, k1, k1 * k3, dC.as<double>(),
+             k1, 0, dC.as<double>(), k1, 0, dOut.as<double>(), k1, 0, 1);
+    HIPCHECK(hipMemcpyAsync(G1, dOut.ptr, (size_t)k1 * k1 * 8, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+}
+
+void DevInner::gram3(double *G3) {
+    rocblas_handle h = static_cast<rocblas_handle>(ds->get_handle(s));
+    const int sl = k1 * k1;
+    dOut.ensure((size_t)k3 * k3 * 8);
+    // C is the column-major (k1^2) x k3 matrix C_(3)^T
+    dgemm_sb(h, rocblas_operation_transpose, rocblas_operation_none, k3, k3, sl, dC.as<double>(), sl,
+             0, dC.as<double>(), sl, 0, dOut.as<double>(), k3, 0, 1);
+    HIPCHECK(hipMemcpyAsync(G3, dOut.ptr, (size_t)k3 * k3 * 8, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+}
+
+void DevInner::mode3(const double *Sv, int ldS, int l0, int nl, double *out) {
+    rocblas_handle h = static_cast<rocblas_handle>(ds->get_handle(s));
+    const int sl = k1 * k1;
+    std::vector<double> Sc((size_t)k3 * nl);  // column-major k3 x nl
+    for (int c = 0; c < k3; ++c)
+        for (int l = 0; l < nl; ++l) Sc[c + (size_t)k3 * l] = Sv[(size_t)c * ldS + l0 + l];
+    dA.ensure(Sc.size() * 8);
+    dOut.ensure((size_t)sl * nl * 8);
+    HIPCHECK(hipMemcpyAsync(dA.ptr, Sc.data(), Sc.size() * 8, hipMemcpyHostToDevice, s));
+    dgemm_sb(h, rocblas_operation_none, rocblas_operation_none, sl, nl, k3, dC.as<double>(), sl, 0,
+             dA.as<double>(), k3, 0, dOut.as<double>(), sl, 0, 1);
+    HIPCHECK(hipMemcpyAsync(out, dOut.ptr, (size_t)sl * nl * 8, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+}
+
+void DevInner::hooi3(const double *P, int r, double *M3) {
+    rocblas_handle h = static_cast<rocblas_handle>(ds->get_handle(s));
+    const int64_t sl = (int64_t)k1 * k1;
+    // P row-major k1 x r reads as the column-major r x k1 matrix P^T
+    dA.ensure((size_t)k1 * r * 8);
+    dT.ensure((size_t)k1 * r * k3 * 8);
+    dOut.ensure((size_t)r * r * k3 * 8);
+    HIPCHECK(hipMemcpyAsync(dA.ptr, P, (size_t)k1 * r * 8, hipMemcpyHostToDevice, s));
+    // CP_c = C_c P (k1 x r), then M_c = P^T CP_c (r x r, M_c(i, j) at i + r j)
+    dgemm_sb(h, rocblas_operation_none, rocblas_operation_transpose, k1, r, k1, dC.as<double>(), k1,
+             sl, dA.as<double>(), r, 0, dT.as<double>(), k1, (int64_t)k1 * r, k3);
+    dgemm_sb(h, rocblas_operation_none, rocblas_operation_none, r, r, k1, dA.as<double>(), r, 0,
+             dT.as<double>(), k1, (int64_t)k1 * r, dOut.as<double>(), r, (int64_t)r * r, k3);
+    HIPCHECK(hipMemcpyAsync(M3, dOut.ptr, (size_t)r * r * k3 * 8, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+}
+
+void DevInner::rotate(const double *Qp, const double *Qs, int r, int r3, double *Y, double *Y2) {
+    rocblas_handle h = static_cast<rocblas_handle>(ds->get_handle(s));
+    const int64_t sl = (int64_t)k1 * k1;
+    const int C1 = k3 - r3;
+    // row-major Qp, Qs read as Qp^T, Qs^T
+    dA.ensure((size_t)k1 * k1 * 8);
+    dB.ensure((size_t)k3 * k3 * 8);
+    dOut.ensure((size_t)sl * k3 * 8);
+    dT.ensure((size_t)std::max<int64_t>(sl * r3, (int64_t)k1 * r * C1) * 8);
+    dY.ensure((size_t)(sl * r3 + (int64_t)k1 * r * C1) * 8);
+    HIPCHECK(hipMemcpyAsync(dA.ptr, Qp, (size_t)k1 * k1 * 8, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(dB.ptr, Qs, (size_t)k3 * k3 * 8, hipMemcpyHostToDevice, s));
+    // X_l = C.(I, I, Qs(:, l)) for every l: (k1^2 x k3) times Qs
+    dgemm_sb(h, rocblas_operation_none, rocblas_operation_transpose, (int)sl, k3, k3,
+             dC.as<double>(), (int)sl, 0, dB.as<double>(), k3, 0, dOut.as<double>(), (int)sl, 0,
+             1);
+    double *dYl = dY.as<double>(), *dY2 = dY.as<double>() + sl * r3;
+    // Y_l = Qp^T (X_l Qp), l < r3
+    dgemm_sb(h, rocblas_operation_none, rocblas_operation_transpose, k1, k1, k1, dOut.as<double>(),
+             k1, sl, dA.as<double>(), k1, 0, dT.as<double>(), k1, sl, r3);
+    dgemm_sb(h, rocblas_operation_none, rocblas_operation_none, k1, k1, k1, dA.as<double>(), k1, 0,
+             dT.as<double>(), k1, sl, dYl, k1, sl, r3);
+    if (C1 > 0) {
+        // Y2_z = Qp^T (X_{r3+z} Qp(:, :r)); Qp(:, :r)^T is the first r rows of the array
+        dgemm_sb(h, rocblas_operation_none, rocblas_operation_transpose, k1, r, k1,
+                 dOut.as<double>() + sl * r3, k1, sl, dA.as<double>(), k1, 0, dT.as<double>(), k1,
+                 (int64_t)k1 * r, C1);
+        dgemm_sb(h, rocblas_operation_none, rocblas_operation_none, k1, r, k1, dA.as<double>(), k1, 0,
+                 dT.as<double>(), k1, (int64_t)k1 * r, dY2, k1, (int64_t)k1 * r, C1);
+    }
+    HIPCHECK(hipMemcpyAsync(Y, dYl, (size_t)sl * r3 * 8, hipMemcpyDeviceToHost, s));
+    if (C1 > 0)
+        HIPCHECK(hipMemcpyAsync(Y2, dY2, (size_t)k1 * r * C1 * 8, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
 }
 
 }  // namespace bks

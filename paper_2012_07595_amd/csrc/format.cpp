@@ -293,54 +293,6 @@ void build_formats(Tensor &t, const int32_t *I, const int32_t *J, const int32_t 
     t.dev_bytes = bytes(t.o3) + bytes(t.o1) + bytes(t.op);
 }
 
-void build_schedule(const std::vector<int64_t> &segptr, int E, std::vector<Item> &items,
-                    std::vector<Fixup> &fix, int64_t &nslots) {
-    const int64_t nseg = (int64_t)segptr.size() - 1;
-    const int64_t CH = std::max<int64_t>((int64_t)E * kHeavySteps, 2048);
-    items.clear();
-    fix.clear();
-    nslots = 0;
-    int64_t s = 0;
-    while (s < nseg) {
-        int64_t len = segptr[s + 1] - segptr[s];
-        if (len > kLightMax) {
-            int64_t nch = (len + CH - 1) / CH;
-            if (nch == 1) {
-                items.push_back({(int32_t)s, -1, segptr[s], segptr[s + 1], -1, 0});
-            } else {
-                fix.push_back({(int32_t)s, (int32_t)nslots, (int32_t)nch, 0});
-                for (int64_t c = 0; c < nch; ++c) {
-                    int64_t b = segptr[s] + c * CH, e = std::min(segptr[s + 1], b + CH);
-                    items.push_back({(int32_t)s, -1, b, e, (int32_t)(nslots + c), 0});
-                }
-                nslots += nch;
-            }
-            ++s;
-        } else {
-            int64_t s0 = s;
-            while (s < nseg && s - s0 < E && segptr[s + 1] - segptr[s] <= kLightMax) ++s;
-            items.push_back({(int32_t)s0, (int32_t)s, 0, 0, -1, 0});
-        }
-    }
-}
-
-void build_wide_schedule(const std::vector<int64_t> &segptr, int CW, std::vector<Item> &items,
-                         std::vector<Fixup> &fix, int64_t &nslots) {
-    const int64_t nseg = (int64_t)segptr.size() - 1;
-    items.clear();
-    fix.clear();
-    for (int64_t s = 0; s < nseg; ++s) {
-        const int64_t len = segptr[s + 1] - segptr[s];
-        const int64_t nch = (len + CW - 1) / CW;
-        fix.push_back({(int32_t)s, (int32_t)items.size(), (int32_t)nch, 0});
-        for (int64_t c = 0; c < nch; ++c) {
-            const int64_t b = segptr[s] + c * CW, e = std::min(segptr[s + 1], b + CW);
-            items.push_back({(int32_t)s, -1, b, e, (int32_t)items.size(), 0});
-        }
-    }
-    nslots = (int64_t)items.size();
-}
-
 void Tensor::release_device() {
     std::lock_guard<std::mutex> g(sched_mu);
     for (Segmented *o : {&o3, &o1, &op}) {
@@ -372,30 +324,17 @@ const Schedule &Tensor::schedule(int order, int E) {
     }
     // tree levels for segments with many partial slots (see Schedule); the
     // wide schedule's chunks are summed by their own reduce kernel
-    while (order != kWideOrder) {
-        bool deep = false;
-        for (const Fixup &f : fx) deep = deep || f.nslots > kFixFan;
-        if (!deep) break;
-        std::vector<Fixup> lv, next;
-        for (const Fixup &f : fx) {
-            if (f.nslots <= kFixFan) {
-                next.push_back(f);
-                continue;
-            }
-            const int32_t ng = (f.nslots + kFixFan - 1) / kFixFan;
-            for (int32_t g = 0; g < ng; ++g)
-                lv.push_back({(int32_t)(sc->nslots + g), f.first_slot + g * kFixFan,
-                              std::min<int32_t>(kFixFan, f.nslots - g * kFixFan), 0});
-            next.push_back({f.seg, (int32_t)sc->nslots, ng, 0});
-            sc->nslots += ng;
+    if (order != kWideOrder) {
+        std::vector<std::vector<Fixup>> lv;
+        build_fix_tree(fx, sc->nslots, lv);
+        for (auto &l : lv) {
+            auto L = std::make_unique<Schedule::Level>();
+            L->nfix = (int64_t)l.size();
+            L->fix.alloc(l.size() * sizeof(Fixup));
+            HIPCHECK(hipMemcpy(L->fix.ptr, l.data(), l.size() * sizeof(Fixup),
+                               hipMemcpyHostToDevice));
+            sc->levels.push_back(std::move(L));
         }
-        auto L = std::make_unique<Schedule::Level>();
-        L->nfix = (int64_t)lv.size();
-        L->fix.alloc(lv.size() * sizeof(Fixup));
-        HIPCHECK(hipMemcpy(L->fix.ptr, lv.data(), lv.size() * sizeof(Fixup),
-                           hipMemcpyHostToDevice));
-        sc->levels.push_back(std::move(L));
-        fx.swap(next);
     }
     sc->nitems = (int64_t)items.size();
     sc->nfix = (int64_t)fx.size();

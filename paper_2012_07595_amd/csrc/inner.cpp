@@ -31,6 +31,7 @@ namespace {
 struct View {
     const double *C;
     int k1, k3;
+    InnerDevice *dev = nullptr;  // large cores: dense products on the device
     double at(int a, int b, int c) const { return C[a + (size_t)k1 * (b + (size_t)k1 * c)]; }
 };
 
@@ -43,6 +44,10 @@ void mode3_product(const View &V, const double *Sv, int ldS, int l0, int nl,
     const int k1 = V.k1, k3 = V.k3;
     const int sl = k1 * k1;
     out.resize((size_t)sl * nl);
+    if (V.dev) {
+        V.dev->mode3(Sv, ldS, l0, nl, out.data());
+        return;
+    }
     la::dgemm(true, false, nl, sl, k3, 1.0, Sv + l0, ldS, V.C, sl, 0.0, out.data(), sl, true);
 }
 
@@ -52,9 +57,23 @@ void hosvd(const View &V, int r, int r3, std::vector<double> &P, std::vector<dou
     // G1 = C_(1) C_(1)^T: the mode-1 fibres C(:, b, c) are the rows of a
     // (k1 k3) x k1 matrix; G3 = C_(3) C_(3)^T: slice c is row c of k3 x k1^2
     std::vector<double> G1((size_t)k1 * k1), G3((size_t)k3 * k3);
-    la::dgemm(true, false, k1, k1, k1 * k3, 1.0, V.C, k1, V.C, k1, 0.0, G1.data(), k1, true);
-    la::dgemm(false, true, k3, k3, (int)sl, 1.0, V.C, (int)sl, V.C, (int)sl, 0.0, G3.data(), k3,
-              true);
+    if (V.dev) {
+        V.dev->gram1(G1.data());
+        V.dev->gram3(G3.data());
+        // exact symmetry (the device sums G(i, j) and G(j, i) separately)
+        for (int a = 0; a < k1; ++a)
+            for (int b = 0; b < a; ++b)
+                G1[(size_t)a * k1 + b] = G1[(size_t)b * k1 + a] =
+                    0.5 * (G1[(size_t)a * k1 + b] + G1[(size_t)b * k1 + a]);
+        for (int a = 0; a < k3; ++a)
+            for (int b = 0; b < a; ++b)
+                G3[(size_t)a * k3 + b] = G3[(size_t)b * k3 + a] =
+                    0.5 * (G3[(size_t)a * k3 + b] + G3[(size_t)b * k3 + a]);
+    } else {
+        la::dgemm(true, false, k1, k1, k1 * k3, 1.0, V.C, k1, V.C, k1, 0.0, G1.data(), k1, true);
+        la::dgemm(false, true, k3, k3, (int)sl, 1.0, V.C, (int)sl, V.C, (int)sl, 0.0, G3.data(),
+                  k3, true);
+    }
     P.assign((size_t)k1 * r, 0.0);
     S.assign((size_t)k3 * r3, 0.0);
     la::top_eigvecs(k1, G1.data(), r, P.data());
@@ -95,6 +114,11 @@ void hooi_step(const View &V, int r, int r3, std::vector<double> &P, std::vector
     // M3(c, i + r*j) = sum_{a,b} C(a,b,c) P(a,i) P(b,j)
     const int w3 = r * r;
     std::vector<double> M3((size_t)k3 * w3);
+    if (V.dev) {
+        V.dev->hooi3(P.data(), r, M3.data());
+        lead_left(M3, k3, w3, r3, S);
+        return;
+    }
     la::parallel_for(k3, [&](int c) {
         std::vector<double> CP((size_t)k1 * r), T((size_t)r * r);
         la::dgemm(false, false, k1, r, k1, 1.0, V.C + sl * c, k1, P.data(), r, 0.0, CP.data(), r);
@@ -127,16 +151,37 @@ void rotate(const View &V, const std::vector<double> &P, const std::vector<doubl
     la::qr_full(k1, r, P.data(), B.Qp.data());
     la::qr_full(k3, r3, S.data(), B.Qs.data());
     const int A1 = B.A1, C1 = B.C1;
-    // CS(:, :, l) = C.(I, I, Qs(:, l)) for all k3 columns: the first r3 give
-    // R0 = C.(Qp, Qp, S), the rest R1 = C.(Qp, P, S_perp)
-    std::vector<double> CS;
-    mode3_product(V, B.Qs.data(), k3, 0, k3, CS);
-    const size_t sl = (size_t)k1 * k1;
     B.F.assign((size_t)r * r * r3, 0.0);
     B.B100.assign((size_t)A1 * r * r3, 0.0);
     B.B110.assign((size_t)A1 * A1 * r3, 0.0);
     B.B001.assign((size_t)r * r * C1, 0.0);
     B.B101.assign((size_t)A1 * r * C1, 0.0);
+    if (V.dev) {
+        std::vector<double> Y((size_t)k1 * k1 * r3), Y2((size_t)k1 * r * C1);
+        V.dev->rotate(B.Qp.data(), B.Qs.data(), r, r3, Y.data(), Y2.data());
+        for (int l = 0; l < r3; ++l)
+            for (int y = 0; y < k1; ++y)
+                for (int x = 0; x < k1; ++x) {
+                    const double v = Y[x + (size_t)k1 * (y + (size_t)k1 * l)];
+                    if (x < r && y < r) B.F[x + r * (y + (size_t)r * l)] = v;
+                    else if (x >= r && y < r) B.B100[(x - r) + (size_t)A1 * (y + (size_t)r * l)] = v;
+                    else if (x >= r && y >= r)
+                        B.B110[(x - r) + (size_t)A1 * ((y - r) + (size_t)A1 * l)] = v;
+                }
+        for (int z = 0; z < C1; ++z)
+            for (int j = 0; j < r; ++j)
+                for (int x = 0; x < k1; ++x) {
+                    const double v = Y2[x + (size_t)k1 * (j + (size_t)r * z)];
+                    if (x < r) B.B001[x + r * (j + (size_t)r * z)] = v;
+                    else B.B101[(x - r) + (size_t)A1 * (j + (size_t)r * z)] = v;
+                }
+        return;
+    }
+    // CS(:, :, l) = C.(I, I, Qs(:, l)) for all k3 columns: the first r3 give
+    // R0 = C.(Qp, Qp, S), the rest R1 = C.(Qp, P, S_perp)
+    std::vector<double> CS;
+    mode3_product(V, B.Qs.data(), k3, 0, k3, CS);
+    const size_t sl = (size_t)k1 * k1;
     la::parallel_for(k3, [&](int l) {
         const double *Xl = &CS[sl * l];  // symmetric: row a contiguous
         if (l < r3) {
@@ -199,15 +244,22 @@ double local_gradient(const Blocks &B, std::vector<double> &G1, std::vector<doub
 }
 
 // Negative Hessian H = -2A (N x N row-major) of the second-order model.
+// The sums over one core index are products of rearranged blocks:
+//   Delta-Delta  A[(x,a),(y,b)] = 2 [a=b] <M_x, M_y> + 2 sum_c M(x,b,c) M(y,a,c)
+//                                + 2 sum_c F(a,b,c) B110(x,y,c) - 2 [x=y] S1(a,b)
+//   Delta-Theta  A[(x,a),(z,c)] = 2 sum_b (M(x,b,c) B001(a,b,z) + F(a,b,c) B101(x,b,z))
+//   Theta-Theta  A[(z,c),(w,d)] = [c=d] <B001_z, B001_w> - [z=w] S3(c,d)
+// with M = B100, S1 = <F, F>_{-1}, S3 = <F, F>_{-3}.
 void newton_matrix(const Blocks &B, std::vector<double> &H) {
     const int r = B.r, r3 = B.r3, A1 = B.A1, C1 = B.C1;
     const int nd = A1 * r, nt = C1 * r3, N = nd + nt;
-    H.assign((size_t)N * N, 0.0);
+    const int rr = r * r;
+    // every Delta row is written in full below; the Theta rows accumulate
+    H.resize((size_t)N * N);
+    std::fill(H.begin() + (size_t)nd * N, H.end(), 0.0);
     auto Fv = [&](int a, int b, int c) { return B.F[a + r * (b + (size_t)r * c)]; };
     auto M = [&](int x, int b, int c) { return B.B100[x + (size_t)A1 * (b + (size_t)r * c)]; };
-    auto B110 = [&](int x, int y, int c) { return B.B110[x + (size_t)A1 * (y + (size_t)A1 * c)]; };
     auto B001 = [&](int a, int b, int z) { return B.B001[a + r * (b + (size_t)r * z)]; };
-    auto B101 = [&](int x, int b, int z) { return B.B101[x + (size_t)A1 * (b + (size_t)r * z)]; };
     std::vector<double> S1((size_t)r * r, 0.0), S3((size_t)r3 * r3, 0.0);
     for (int a = 0; a < r; ++a)
         for (int b = 0; b < r; ++b) {
@@ -223,52 +275,96 @@ void newton_matrix(const Blocks &B, std::vector<double> &H) {
                 for (int b = 0; b < r; ++b) s += Fv(a, b, c) * Fv(a, b, d);
             S3[(size_t)c * r3 + d] = s;
         }
-    // <M_x, M_y>
-    std::vector<double> MM((size_t)A1 * A1, 0.0);
+    // Delta-Delta: Gx[(x,b),(y,a)] = sum_c M(x,b,c) M(y,a,c); K[(x,y),(a,b)] =
+    // sum_c B110(x,y,c) F(a,b,c)
+    // thread-local workspaces: reused across calls (large cores need ~60 MB,
+    // whose first touch would otherwise dominate)
+    // (the lambdas below run on pool threads: they must see the caller's
+    // instances, hence the local references)
+    struct Work {
+        std::vector<double> Mt, B110t, Ft, Gx, K, MM, Mxc, B001t, B101t, Fb, T1, T2;
+    };
+    static thread_local Work tl_work;
+    Work &w_ = tl_work;
+    auto &Mt = w_.Mt, &B110t = w_.B110t, &Ft = w_.Ft, &Gx = w_.Gx, &K = w_.K, &MM = w_.MM;
+    auto &Mxc = w_.Mxc, &B001t = w_.B001t, &B101t = w_.B101t, &Fb = w_.Fb, &T1 = w_.T1,
+         &T2 = w_.T2;
+    Mt.resize((size_t)nd * r3);
+    B110t.resize((size_t)A1 * A1 * r3);
+    Ft.resize((size_t)r3 * rr);
     for (int x = 0; x < A1; ++x)
-        for (int y = 0; y <= x; ++y) {
-            double s = 0.0;
-            for (int c = 0; c < r3; ++c)
-                for (int b = 0; b < r; ++b) s += M(x, b, c) * M(y, b, c);
-            MM[(size_t)x * A1 + y] = MM[(size_t)y * A1 + x] = s;
-        }
-    std::vector<double> A((size_t)N * N, 0.0);
-    // Delta-Delta block
+        for (int b = 0; b < r; ++b)
+            for (int c = 0; c < r3; ++c) Mt[((size_t)x * r + b) * r3 + c] = M(x, b, c);
+    for (int c = 0; c < r3; ++c)
+        for (int y = 0; y < A1; ++y)
+            for (int x = 0; x < A1; ++x)
+                B110t[((size_t)x * A1 + y) * r3 + c] = B.B110[x + (size_t)A1 * (y + (size_t)A1 * c)];
+    for (int c = 0; c < r3; ++c)
+        for (int a = 0; a < r; ++a)
+            for (int b = 0; b < r; ++b) Ft[(size_t)c * rr + a * r + b] = Fv(a, b, c);
+    Gx.resize((size_t)nd * nd);
+    K.resize((size_t)A1 * A1 * rr);
+    la::dgemm(false, true, nd, nd, r3, 1.0, Mt.data(), r3, Mt.data(), r3, 0.0, Gx.data(), nd, true);
+    la::dgemm(false, false, A1 * A1, rr, r3, 1.0, B110t.data(), r3, Ft.data(), rr, 0.0, K.data(), rr,
+              true);
+    // MM = <M_x, M_y> = Mflat Mflat^T, Mflat(x, (b,c)) = M(x,b,c) (contiguous: Mt)
+    MM.resize((size_t)A1 * A1);
+    la::dgemm(false, true, A1, A1, r * r3, 1.0, Mt.data(), r * r3, Mt.data(), r * r3, 0.0,
+              MM.data(), A1, true);
+    // Delta-Theta: T1[(x,c),(a,z)] = sum_b M(x,b,c) B001(a,b,z);
+    // T2[(x,z),(a,c)] = sum_b B101(x,b,z) F(a,b,c)
+    Mxc.resize((size_t)A1 * r3 * r);
+    B001t.resize((size_t)r * r * C1);
+    B101t.resize((size_t)A1 * C1 * r);
+    Fb.resize((size_t)r * r * r3);
+    for (int x = 0; x < A1; ++x)
+        for (int c = 0; c < r3; ++c)
+            for (int b = 0; b < r; ++b) Mxc[((size_t)x * r3 + c) * r + b] = M(x, b, c);
+    for (int b = 0; b < r; ++b)
+        for (int a = 0; a < r; ++a)
+            for (int z = 0; z < C1; ++z) B001t[(size_t)b * (r * C1) + a * C1 + z] = B001(a, b, z);
+    for (int x = 0; x < A1; ++x)
+        for (int z = 0; z < C1; ++z)
+            for (int b = 0; b < r; ++b)
+                B101t[((size_t)x * C1 + z) * r + b] = B.B101[x + (size_t)A1 * (b + (size_t)r * z)];
+    for (int b = 0; b < r; ++b)
+        for (int a = 0; a < r; ++a)
+            for (int c = 0; c < r3; ++c) Fb[(size_t)b * (r * r3) + a * r3 + c] = Fv(a, b, c);
+    T1.resize((size_t)A1 * r3 * r * C1);
+    T2.resize((size_t)A1 * C1 * r * r3);
+    if (C1 > 0) {
+        la::dgemm(false, false, A1 * r3, r * C1, r, 1.0, Mxc.data(), r, B001t.data(), r * C1, 0.0,
+                  T1.data(), r * C1, true);
+        la::dgemm(false, false, A1 * C1, r * r3, r, 1.0, B101t.data(), r, Fb.data(), r * r3, 0.0,
+                  T2.data(), r * r3, true);
+    }
+    // assemble H = -2A (rows of the Delta part; Theta rows by symmetry below)
     la::parallel_for(A1, [&](int x) {
         for (int a = 0; a < r; ++a) {
-            const int row = x * r + a;
-            for (int y = 0; y < A1; ++y)
+            double *h = &H[((size_t)x * r + a) * N];
+            for (int y = 0; y < A1; ++y) {
+                const double *k = &K[((size_t)x * A1 + y) * rr + (size_t)a * r];
+                // Gx[(x,b),(y,a)] = Gx[(y,a),(x,b)] (exactly symmetric): contiguous in b
+                const double *g = &Gx[((size_t)y * r + a) * nd + (size_t)x * r];
                 for (int b = 0; b < r; ++b) {
-                    const int col = y * r + b;
-                    double v = 0.0;
+                    double v = 2.0 * g[b] + 2.0 * k[b];
                     if (a == b) v += 2.0 * MM[(size_t)x * A1 + y];
-                    double cross = 0.0, kf = 0.0;
-                    for (int c = 0; c < r3; ++c) {
-                        cross += M(x, b, c) * M(y, a, c);
-                        kf += Fv(a, b, c) * B110(x, y, c);
-                    }
-                    v += 2.0 * cross + 2.0 * kf;
                     if (x == y) v -= 2.0 * S1[(size_t)a * r + b];
-                    A[(size_t)row * N + col] = v;
+                    h[y * r + b] = -2.0 * v;
                 }
+            }
+            // two passes, each reading its product contiguously
+            for (int c = 0; c < r3; ++c) {
+                const double *t1 = &T1[((size_t)x * r3 + c) * (r * C1) + (size_t)a * C1];
+                for (int z = 0; z < C1; ++z) h[nd + z * r3 + c] = -4.0 * t1[z];
+            }
+            for (int z = 0; z < C1; ++z) {
+                const double *t2 = &T2[((size_t)x * C1 + z) * (r * r3) + (size_t)a * r3];
+                for (int c = 0; c < r3; ++c) h[nd + z * r3 + c] -= 4.0 * t2[c];
+            }
         }
     });
-    // Delta-Theta blocks
-    la::parallel_for(A1, [&](int x) {
-        for (int a = 0; a < r; ++a) {
-            const int row = x * r + a;
-            for (int z = 0; z < C1; ++z)
-                for (int c = 0; c < r3; ++c) {
-                    const int col = nd + z * r3 + c;
-                    double s = 0.0;
-                    for (int b = 0; b < r; ++b)
-                        s += M(x, b, c) * B001(a, b, z) + Fv(a, b, c) * B101(x, b, z);
-                    A[(size_t)row * N + col] = 2.0 * s;
-                    A[(size_t)col * N + row] = 2.0 * s;
-                }
-        }
-    });
-    // Theta-Theta block
+    // Theta-Theta
     for (int z = 0; z < C1; ++z)
         for (int w = 0; w <= z; ++w) {
             double s = 0.0;
@@ -276,21 +372,29 @@ void newton_matrix(const Blocks &B, std::vector<double> &H) {
                 for (int a = 0; a < r; ++a) s += B001(a, b, z) * B001(a, b, w);
             for (int c = 0; c < r3; ++c) {
                 const int i1 = nd + z * r3 + c, j1 = nd + w * r3 + c;
-                A[(size_t)i1 * N + j1] += s;
-                if (w != z) A[(size_t)j1 * N + i1] += s;
+                H[(size_t)i1 * N + j1] += -2.0 * s;
+                if (w != z) H[(size_t)j1 * N + i1] += -2.0 * s;
             }
         }
     for (int z = 0; z < C1; ++z)
         for (int c = 0; c < r3; ++c)
             for (int d = 0; d < r3; ++d)
-                A[(size_t)(nd + z * r3 + c) * N + nd + z * r3 + d] -= S3[(size_t)c * r3 + d];
-    for (size_t i = 0; i < (size_t)N * N; ++i) H[i] = -2.0 * A[i];
-    // exact symmetry
-    for (int i = 0; i < N; ++i)
-        for (int j = i + 1; j < N; ++j) {
-            const double s = 0.5 * (H[(size_t)i * N + j] + H[(size_t)j * N + i]);
-            H[(size_t)i * N + j] = H[(size_t)j * N + i] = s;
-        }
+                H[(size_t)(nd + z * r3 + c) * N + nd + z * r3 + d] -= -2.0 * S3[(size_t)c * r3 + d];
+    // exact symmetry, in 32 x 32 tiles (tile row ti owns the tiles (ti, tj >= ti));
+    // the Theta rows' Delta columns are only filled here, by copy
+    const int TS = 32, nt_ = (N + TS - 1) / TS;
+    la::parallel_for(nt_, [&](int ti) {
+        for (int tj = ti; tj < nt_; ++tj)
+            for (int i = ti * TS; i < std::min(N, ti * TS + TS); ++i)
+                for (int j = std::max(i + 1, tj * TS); j < std::min(N, tj * TS + TS); ++j) {
+                    if (i < nd && j >= nd) {
+                        H[(size_t)j * N + i] = H[(size_t)i * N + j];
+                        continue;
+                    }
+                    const double s = 0.5 * (H[(size_t)i * N + j] + H[(size_t)j * N + i]);
+                    H[(size_t)i * N + j] = H[(size_t)j * N + i] = s;
+                }
+    });
 }
 
 // g(P, S) = ||C.(P, P, S)||^2
@@ -329,15 +433,20 @@ void retract(int k, int r, const std::vector<double> &Q, const double *D, std::v
 }  // namespace
 
 double inner_objective(const std::vector<double> &C, int k1, int k3, const std::vector<double> &P,
-                       const std::vector<double> &S, int r, int r3) {
-    View V{C.data(), k1, k3};
+                       const std::vector<double> &S, int r, int r3, InnerDevice *dev) {
+    View V{C.data(), k1, k3, dev};
     return objective(V, P, S, r, r3);
 }
 
 void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, double tol,
                  int hooi_warm, int ng_max, bool warm, std::vector<double> &P,
-                 std::vector<double> &S, InnerInfo &info, const BigSolve &big) {
-    View V{C.data(), k1, k3};
+                 std::vector<double> &S, InnerInfo &info, const BigSolve &big,
+                 InnerDevice *dev, double dev_min) {
+    View V{C.data(), k1, k3, nullptr};
+    if (dev && (double)k1 * k1 * k3 >= dev_min) {
+        dev->set_core(C.data(), k1, k3);
+        V.dev = dev;
+    }
     info = InnerInfo{};
     auto clk = [] {
         return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
@@ -350,7 +459,10 @@ void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, do
     }
     info.t_start = clk() - t0;
     Blocks B;
-    std::vector<double> G1, G3, H, Hs, d, Pn, Sn;
+    std::vector<double> G1, G3, d, Pn, Sn;
+    // the Newton matrices (60 MB at rank (10,10,10)) are reused across calls
+    static thread_local std::vector<double> tl_H, tl_Hs;
+    std::vector<double> &H = tl_H, &Hs = tl_Hs;
     double mu = 0.0;
     double prev = INFINITY;
     int stall = 0;
@@ -389,14 +501,17 @@ void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, do
         const bool deep_floor = info.rel < 1e-10;
         const int max_attempts = deep_floor ? 4 : 12;
         for (int attempt = 0; attempt < max_attempts && !accepted; ++attempt) {
-            Hs = H;
-            for (int i = 0; i < N; ++i) Hs[(size_t)i * N + i] += mu;
+            const bool on_device = big && N >= kDeviceSolveMin;
+            if (!on_device) {
+                Hs = H;
+                for (int i = 0; i < N; ++i) Hs[(size_t)i * N + i] += mu;
+            }
             d.assign(N, 0.0);
             for (int i = 0; i < nd; ++i) d[i] = 4.0 * G1[i];
             for (int i = 0; i < N - nd; ++i) d[nd + i] = 2.0 * G3[i];
             t0 = clk();
-            if (big && N >= kDeviceSolveMin) {
-                const bool pd = big(N, Hs.data(), d.data());
+            if (on_device) {
+                const bool pd = big(N, H.data(), mu, attempt == 0, d.data());
                 info.t_chol += clk() - t0;
                 if (!pd) {
                     // no pivot from the device factorisation: escalate by 10

@@ -7,10 +7,37 @@
 
 namespace bks {
 
-// Optional solver for large Newton systems: solve H x = b in place of b
-// (H N x N symmetric row-major); returns false if H is not positive definite.
-using BigSolve = std::function<bool(int N, const double *H, double *b)>;
+// Optional solver for large Newton systems: solve (H + mu I) x = b in place
+// of b (H N x N symmetric row-major); returns false if H + mu I is not
+// positive definite.  `new_matrix` is false when H is the same as in the
+// previous call (only mu changed).
+using BigSolve = std::function<bool(int N, const double *H, double mu, bool new_matrix, double *b)>;
 constexpr int kDeviceSolveMin = 512;
+
+// Optional device for the dense products of large cores.  After set_core
+// (C uploaded, layout as below) every call is synchronous and returns host
+// results:
+//   gram1:  G1 = C_(1) C_(1)^T (k1 x k1)          gram3: G3 = C_(3) C_(3)^T (k3 x k3)
+//   mode3:  out(a + k1*(b + k1*l)) = sum_c C(a,b,c) Sv(c, l0 + l), l < nl
+//           (Sv k3 x ldS row-major)
+//   hooi3:  M3(c, i + r*j) = sum_{a,b} C(a,b,c) P(a,i) P(b,j) (P k1 x r row-major)
+//   rotate: with Qp (k1 x k1) and Qs (k3 x k3) row-major orthogonal,
+//           X_l = C.(I, I, Qs(:,l)); Y(x, y, l) = (Qp^T X_l Qp)(x, y) for l < r3
+//           at x + k1*(y + k1*l), Y2(x, j, z) = (Qp^T X_{r3+z} Qp(:, :r))(x, j)
+//           at x + k1*(j + r*z), z < k3 - r3
+// Results equal the host products up to rounding order.
+struct InnerDevice {
+    virtual ~InnerDevice() = default;
+    virtual void set_core(const double *C, int k1, int k3) = 0;
+    virtual void gram1(double *G1) = 0;
+    virtual void gram3(double *G3) = 0;
+    virtual void mode3(const double *Sv, int ldS, int l0, int nl, double *out) = 0;
+    virtual void hooi3(const double *P, int r, double *M3) = 0;
+    virtual void rotate(const double *Qp, const double *Qs, int r, int r3, double *Y,
+                        double *Y2) = 0;
+};
+// Cores with at least this many entries (k1^2 k3) use the device when given.
+constexpr double kDeviceCoreMin = 1.0e6;
 
 struct InnerInfo {
     int iters = 0;        // Newton-Grassmann iterations (incl. HOOI fallbacks)
@@ -24,10 +51,11 @@ struct InnerInfo {
 // also the start (else HOSVD + hooi_warm HOOI steps, Section 5.2).
 // g(P, S) = ||C.(P, P, S)||^2 (P k1 x r, S k3 x r3, row-major)
 double inner_objective(const std::vector<double> &C, int k1, int k3, const std::vector<double> &P,
-                       const std::vector<double> &S, int r, int r3);
+                       const std::vector<double> &S, int r, int r3, InnerDevice *dev = nullptr);
 
 void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, double tol,
                  int hooi_warm, int ng_max, bool warm, std::vector<double> &P,
-                 std::vector<double> &S, InnerInfo &info, const BigSolve &big = BigSolve());
+                 std::vector<double> &S, InnerInfo &info, const BigSolve &big = BigSolve(),
+                 InnerDevice *dev = nullptr, double dev_min = kDeviceCoreMin);
 
 }  // namespace bks

@@ -97,8 +97,9 @@ void tridiagonalize(int n, std::vector<double> &Z, std::vector<double> &d,
 }
 
 // Implicitly shifted QL on the tridiagonal (d, e); rotations accumulated
-// into the columns of Z.
-void tridiag_ql(int n, std::vector<double> &d, std::vector<double> &e, std::vector<double> &Z) {
+// into the rows of Zt = Z^T (row i of Zt is column i of Z, so each rotation
+// updates two contiguous rows).
+void tridiag_ql(int n, std::vector<double> &d, std::vector<double> &e, std::vector<double> &Zt) {
     const double eps = std::numeric_limits<double>::epsilon();
     double anorm = 0.0;
     for (int i = 0; i < n; ++i) anorm = std::max(anorm, std::fabs(d[i]) + std::fabs(e[i]));
@@ -140,11 +141,11 @@ void tridiag_ql(int n, std::vector<double> &d, std::vector<double> &e, std::vect
                     p = s * r;
                     d[i + 1] = g + p;
                     g = c * r - b;
+                    double *zi = &Zt[(size_t)i * n], *zi1 = &Zt[(size_t)(i + 1) * n];
                     for (int k = 0; k < n; ++k) {
-                        double *zr = &Z[(size_t)k * n];
-                        f = zr[i + 1];
-                        zr[i + 1] = s * zr[i] + c * f;
-                        zr[i] = c * zr[i] - s * f;
+                        const double a0 = zi[k], a1 = zi1[k];
+                        zi1[k] = s * a0 + c * a1;
+                        zi[k] = c * a0 - s * a1;
                     }
                 }
                 if (early) continue;
@@ -174,13 +175,17 @@ void sym_eig(int n, const double *A, double *w, double *V) {
         }
     std::vector<double> d, e;
     tridiagonalize(n, Z, d, e);
-    tridiag_ql(n, d, e, Z);
+    std::vector<double> Zt((size_t)n * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Zt[(size_t)j * n + i] = Z[(size_t)i * n + j];
+    tridiag_ql(n, d, e, Zt);
     std::vector<int> ord(n);
     std::iota(ord.begin(), ord.end(), 0);
     std::sort(ord.begin(), ord.end(), [&](int a, int b) { return d[a] > d[b]; });
     for (int j = 0; j < n; ++j) {
         w[j] = d[ord[j]];
-        for (int i = 0; i < n; ++i) V[(size_t)i * n + j] = Z[(size_t)i * n + ord[j]];
+        const double *zc = &Zt[(size_t)ord[j] * n];
+        for (int i = 0; i < n; ++i) V[(size_t)i * n + j] = zc[i];
     }
 }
 
@@ -519,27 +524,50 @@ void dgemm(bool ta, bool tb, int m, int n, int k, double alpha, const double *A,
         bp[jp] = dst;
         bs[jp] = NR;
     }
-    auto tile = [&](int t) {
-        const int ip = t / np, jp = t - (t / np) * np;
+    auto tile = [&](int ip, int jp) {
         alignas(32) double acc[MR * NR];
         micro_4x8(k, ap[ip], as[ip], bp[jp], bs[jp], acc);
+        const int i0 = ip * MR, j0 = jp * NR;
+        if (i0 + MR <= m && j0 + NR <= n) {
+            for (int r = 0; r < MR; ++r) {
+                double *ci = C + (size_t)(i0 + r) * ldc + j0;
+                const double *ar = acc + r * NR;
+                if (beta == 0.0)
+                    for (int c = 0; c < NR; ++c) ci[c] = alpha * ar[c];
+                else
+                    for (int c = 0; c < NR; ++c) ci[c] = beta * ci[c] + alpha * ar[c];
+            }
+            return;
+        }
         for (int r = 0; r < MR; ++r) {
-            const int i = ip * MR + r;
+            const int i = i0 + r;
             if (i >= m) break;
             double *ci = C + (size_t)i * ldc;
             for (int c = 0; c < NR; ++c) {
-                const int j = jp * NR + c;
+                const int j = j0 + c;
                 if (j >= n) break;
                 const double v = alpha * acc[r * NR + c];
                 ci[j] = beta == 0.0 ? v : beta * ci[j] + v;
             }
         }
     };
-    const int ntile = mp * np;
-    if (parallel && (double)m * n * k > 2e5)
-        parallel_for(ntile, tile);
-    else
-        for (int t = 0; t < ntile; ++t) tile(t);
+    // parallel tasks: groups of row panels (at most ~4 tasks per thread), or
+    // single tiles when there are few row panels
+    if (parallel && (double)m * n * k > 2e5 && threads() > 1) {
+        const int want = 4 * threads();
+        if (mp >= want / 2) {
+            const int per = (mp + want - 1) / want;
+            parallel_for((mp + per - 1) / per, [&](int t) {
+                for (int ip = t * per; ip < std::min(mp, t * per + per); ++ip)
+                    for (int jp = 0; jp < np; ++jp) tile(ip, jp);
+            });
+        } else {
+            parallel_for(mp * np, [&](int t) { tile(t / np, t % np); });
+        }
+        return;
+    }
+    for (int ip = 0; ip < mp; ++ip)
+        for (int jp = 0; jp < np; ++jp) tile(ip, jp);
 }
 
 }  // namespace la

@@ -4,7 +4,8 @@
 // problems on the host in FP64.
 //
 // Precision modes
-//   FP64:  every tensor product in FP64.
+//   FP64:  every tensor product in FP64; the gradient-defining slices of the
+//          core are taken from the step-(iii) products as below.
 //   MIXED: block-Krylov expansion products and the core product A.(X, X)_{1,2}
 //          in FP32; the step-(iii) products T1 = A.(U0, W0)_{2,3} and
 //          T3 = A.(U0, U0)_{1,2} with FP32 values, FP64 factors and FP64
@@ -291,6 +292,14 @@ struct Solver {
 
     // Orthonormalise B (rows x q, ld) against the basis and append the kept
     // columns; B is left projected off the old basis.  Returns kept count.
+    // hi and lo parts of a q x q double-double Gram at Gd, Gd + 64*64: one copy
+    void gram_dd_download(int q, std::vector<double> &hi, std::vector<double> &lo) {
+        std::vector<double> both((size_t)64 * 64 + (size_t)q * q);
+        d2h(both.data(), Gd.ptr, both.size());
+        hi.assign(both.begin(), both.begin() + (size_t)q * q);
+        lo.assign(both.begin() + 64 * 64, both.end());
+    }
+
     int orth_append(bool isU, double *B, int64_t ldb, int q, double tau) {
         const int64_t rows = isU ? m : n;
         int &k = isU ? k1 : k3;
@@ -311,10 +320,9 @@ struct Solver {
                 gemm_tn_f64(Bas.as<double>(), ldbas, Bc, ldb, rows, k, qc, H, qc, c, s);
                 gemm_nn_f64(Bas.as<double>(), ldbas, H, qc, rows, k, qc, -1.0, 1.0, Bc, ldb, s);
             }
-            std::vector<double> Ghi((size_t)qc * qc), Glo((size_t)qc * qc);
+            std::vector<double> Ghi, Glo;
             gram_dd(Bc, ldb, rows, qc, Gd.as<double>(), Gd.as<double>() + 64 * 64, c, s);
-            d2h(Ghi.data(), Gd.ptr, (size_t)qc * qc);
-            d2h(Glo.data(), Gd.as<double>() + 64 * 64, (size_t)qc * qc);
+            gram_dd_download(qc, Ghi, Glo);
             std::vector<int> kept;
             std::vector<double> T;
             chol_drop(qc, Ghi, Glo, before2, tau, room, kept, T);
@@ -329,10 +337,9 @@ struct Solver {
                 gemm_tn_f64(Bas.as<double>(), ldbas, Q1, qk, rows, k, qk, H, qk, c, s);
                 gemm_nn_f64(Bas.as<double>(), ldbas, H, qk, rows, k, qk, -1.0, 1.0, Q1, qk, s);
             }
-            std::vector<double> G2h((size_t)qk * qk), G2l((size_t)qk * qk);
+            std::vector<double> G2h, G2l;
             gram_dd(Q1, qk, rows, qk, Gd.as<double>(), Gd.as<double>() + 64 * 64, c, s);
-            d2h(G2h.data(), Gd.ptr, (size_t)qk * qk);
-            d2h(G2l.data(), Gd.as<double>() + 64 * 64, (size_t)qk * qk);
+            gram_dd_download(qk, G2h, G2l);
             std::vector<double> ones(qk, 1.0);
             std::vector<int> kept2;
             std::vector<double> T2;
@@ -600,8 +607,12 @@ struct Solver {
                     C[a + (size_t)k1 * (b + (size_t)k1 * cc)] = v;
                     C[b + (size_t)k1 * (a + (size_t)k1 * cc)] = v;
                 }
-        if (mixed) {
-            // FP64-accurate gradient-defining slices from the step-(iii) products
+        {
+            // Gradient-defining slices from the step-(iii) products (FP64
+            // accumulation in both modes): the gradient is evaluated from
+            // these same products, so a stationary point of the full problem
+            // is an exact fixed point of the iteration (in mixed mode they
+            // also replace FP32-formed values)
             const int q1 = r * r3, q3 = r * (r + 1) / 2;
             std::vector<double> XT1((size_t)k1 * q1), ZT3((size_t)k3 * q3);
             gemm_tn_f64(Xcol(0), k1cap, T1.as<double>(), q1, m, k1, q1, Hd.as<double>(), q1, c, s);
@@ -777,10 +788,13 @@ int run_bks(Ctx &c, Tensor &t, const bks_params &prm, double *U, double *W, doub
         }
         if (c.host_acquire) c.host_acquire();
         try {
-            const BigSolve big = [&](int N, const double *H, double *b) {
-                return c.devsolve.solve(s, N, H, b);
+            const BigSolve big = [&](int N, const double *H, double mu, bool fresh, double *b) {
+                return c.devsolve.solve(s, N, H, mu, fresh, b);
             };
-            inner_solve(C, S.k1, S.k3, r, r3, itol, hooi_warm, ng_max, warm, P, Sm, ii, big);
+            c.devinner.ds = &c.devsolve;
+            c.devinner.s = s;
+            InnerDevice *dev = &c.devinner;
+            inner_solve(C, S.k1, S.k3, r, r3, itol, hooi_warm, ng_max, warm, P, Sm, ii, big, dev);
             if (!warm) {
                 // keep the outer objective non-decreasing (eq. Fnon-decr): if
                 // the HOSVD-started solve ends below the current point E0,
@@ -788,12 +802,15 @@ int run_bks(Ctx &c, Tensor &t, const bks_params &prm, double *U, double *W, doub
                 std::vector<double> P0((size_t)S.k1 * r, 0.0), S0((size_t)S.k3 * r3, 0.0);
                 for (int j = 0; j < r; ++j) P0[(size_t)j * r + j] = 1.0;
                 for (int j = 0; j < r3; ++j) S0[(size_t)j * r3 + j] = 1.0;
-                const double g_new = inner_objective(C, S.k1, S.k3, P, Sm, r, r3);
-                const double g_cur = inner_objective(C, S.k1, S.k3, P0, S0, r, r3);
+                // (the device holds this C when the inner solve used it)
+                InnerDevice *gdev =
+                    (double)S.k1 * S.k1 * S.k3 >= kDeviceCoreMin ? dev : nullptr;
+                const double g_new = inner_objective(C, S.k1, S.k3, P, Sm, r, r3, gdev);
+                const double g_cur = inner_objective(C, S.k1, S.k3, P0, S0, r, r3, gdev);
                 if (g_new < g_cur * (1.0 - 1e-14)) {
                     InnerInfo i2;
                     inner_solve(C, S.k1, S.k3, r, r3, itol, hooi_warm, ng_max, true, P0, S0, i2,
-                                big);
+                                big, dev);
                     P.swap(P0);
                     Sm.swap(S0);
                     ii.newton += i2.newton;
@@ -824,6 +841,18 @@ int run_bks(Ctx &c, Tensor &t, const bks_params &prm, double *U, double *W, doub
             break;
         }
         if (it >= max_outer) break;
+        // stagnation at the rounding floor above tol: once below 1e-10, 30
+        // outer iterations without halving the best gradient end the solve
+        // (not converged; the iterate is returned).  Slow linear convergence
+        // halves it far more often.
+        constexpr int kWin = 30;
+        if (it > kWin) {
+            const double best_recent =
+                *std::min_element(rel_hist.end() - kWin, rel_hist.end());
+            const double best_before =
+                *std::min_element(rel_hist.begin(), rel_hist.end() - kWin);
+            if (best_before < 1e-10 && best_recent > 0.5 * best_before) break;
+        }
         a = now_s();
         S.expand(2);
         te += now_s() - a;

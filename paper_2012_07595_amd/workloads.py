@@ -268,6 +268,19 @@ def c3(seed: int = 1002) -> SymCOO:
     return sparse_sym(200_000, 10_000, 50_000_000, zipf=1.5, values="abs", seed=seed)
 
 
+def c3_planted(seed: int = 1002) -> SymCOO:
+    """The C3 law (200000 x 200000 x 10000, 5e7 stored, Zipf(1.5) modes 1-2,
+    uniform mode 3, |N(0,1)| FP32) with a planted rank-(10,10,10) part
+    (superdiagonal core 8000, 7500, ..., 3500; each factor column on 40 rows
+    and 20 slices, ~82k stored entries).  Like the plain C2 law, the plain C3
+    law has no separated rank-10 structure for BKS to converge to."""
+    plant = planted(200_000, 10_000, tuple(8000.0 - 500.0 * x for x in range(10)), 40, 20,
+                    seed + 7)
+    noise = sparse_sym(200_000, 10_000, 50_000_000 - plant.nnz, zipf=1.5, values="abs",
+                       seed=seed)
+    return merge(noise.astype(np.float64), plant).astype(np.float32)
+
+
 def c5(seed: int = 1004) -> SymCOO:
     """1e6 x 1e6 x 500, 2e8 stored, Zipf(1.6) modes 1-2, |N(0,1)| FP32."""
     return sparse_sym(1_000_000, 500, 200_000_000, zipf=1.6, values="abs", seed=seed)

@@ -1,0 +1,398 @@
+// Host-logic checks of libbks (no GPU): work schedules and the partial-row
+// reduction tree, and the host dense kernels used by the inner solve.
+// Prints one "ok <check>" line per passed check; exits 1 on the first failure.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <random>
+#include <vector>
+
+#include "inner.h"
+#include "linalg.h"
+#include "schedule.h"
+
+using namespace bks;
+
+static void require(bool c, const char *what) {
+    if (!c) {
+        std::printf("FAIL %s\n", what);
+        std::exit(1);
+    }
+}
+
+static std::vector<int64_t> random_segptr(std::mt19937_64 &g, int nseg) {
+    std::vector<int64_t> sp(nseg + 1, 0);
+    std::uniform_real_distribution<double> u(0.0, 1.0);
+    for (int s = 0; s < nseg; ++s) {
+        const double x = u(g);
+        int64_t len = x < 0.15 ? 0 : x < 0.7 ? (int64_t)(u(g) * 48) : x < 0.95 ? (int64_t)(u(g) * 5000)
+                                                                            : (int64_t)(u(g) * 300000);
+        sp[s + 1] = sp[s] + len;
+    }
+    return sp;
+}
+
+static void check_schedule() {
+    std::mt19937_64 g(7);
+    for (int E : {1, 3, 12, 21, 64}) {
+        const auto sp = random_segptr(g, 3000);
+        const int64_t nseg = (int64_t)sp.size() - 1;
+        std::vector<Item> items;
+        std::vector<Fixup> fix;
+        int64_t nslots = 0;
+        build_schedule(sp, E, items, fix, nslots);
+        std::vector<int> covered(sp.back(), 0);
+        std::vector<int> seg_done(nseg, 0);
+        std::vector<int> slot_seen(nslots, 0);
+        const int64_t CH = std::max<int64_t>((int64_t)E * kHeavySteps, 2048);
+        for (const Item &it : items) {
+            if (it.seg_end < 0) {
+                require(it.beg < it.end && it.end - it.beg <= CH, "heavy chunk size");
+                require(it.beg >= sp[it.seg] && it.end <= sp[it.seg + 1], "heavy chunk in segment");
+                for (int64_t e = it.beg; e < it.end; ++e) covered[e]++;
+                if (it.slot >= 0) {
+                    require(it.slot < nslots && !slot_seen[it.slot], "slot unique");
+                    slot_seen[it.slot] = 1;
+                } else {
+                    require(it.beg == sp[it.seg] && it.end == sp[it.seg + 1], "unsplit heavy whole");
+                    seg_done[it.seg]++;
+                }
+            } else {
+                require(it.seg_end > it.seg && it.seg_end - it.seg <= E, "light run size");
+                for (int64_t s = it.seg; s < it.seg_end; ++s) {
+                    require(sp[s + 1] - sp[s] <= kLightMax, "light segment short");
+                    for (int64_t e = sp[s]; e < sp[s + 1]; ++e) covered[e]++;
+                    seg_done[s]++;
+                }
+            }
+        }
+        for (const Fixup &f : fix) {
+            int64_t n = 0;
+            for (int32_t x = 0; x < f.nslots; ++x) {
+                require(slot_seen[f.first_slot + x] == 1, "fixup slots are chunk slots");
+                slot_seen[f.first_slot + x] = 2;
+                ++n;
+            }
+            require(n >= 2, "split segments have several chunks");
+            seg_done[f.seg]++;
+        }
+        for (int64_t e = 0; e < sp.back(); ++e) require(covered[e] == 1, "every entry exactly once");
+        for (int64_t s = 0; s < nseg; ++s)
+            require(seg_done[s] == 1 || sp[s + 1] == sp[s], "every nonempty segment written once");
+        for (int64_t x = 0; x < nslots; ++x) require(slot_seen[x] == 2, "every slot summed");
+    }
+    std::printf("ok schedule\n");
+}
+
+static void check_wide_schedule() {
+    std::mt19937_64 g(9);
+    const auto sp = random_segptr(g, 500);
+    for (int CW : {2048, 10000}) {
+        std::vector<Item> items;
+        std::vector<Fixup> fix;
+        int64_t nslots = 0;
+        build_wide_schedule(sp, CW, items, fix, nslots);
+        require((int64_t)fix.size() == (int64_t)sp.size() - 1, "one fix per slice");
+        require(nslots == (int64_t)items.size(), "slot per item");
+        std::vector<int> covered(sp.back(), 0);
+        for (size_t q = 0; q < items.size(); ++q) {
+            const Item &it = items[q];
+            require(it.slot == (int32_t)q && it.end - it.beg <= CW && it.beg < it.end, "wide item");
+            for (int64_t e = it.beg; e < it.end; ++e) covered[e]++;
+        }
+        for (const Fixup &f : fix)
+            for (int32_t x = 0; x < f.nslots; ++x)
+                require(items[f.first_slot + x].seg == f.seg, "fix lists the slice's items");
+        for (int64_t e = 0; e < sp.back(); ++e) require(covered[e] == 1, "wide: every entry once");
+    }
+    std::printf("ok wide_schedule\n");
+}
+
+static void check_fix_tree() {
+    std::mt19937_64 g(11);
+    std::uniform_real_distribution<double> u(-1.0, 1.0);
+    std::vector<Fixup> fix;
+    int64_t nslots = 0;
+    const int counts[] = {2, 64, 65, 127, 4096, 4097, 300000, 5};
+    for (int s = 0; s < 8; ++s) {
+        fix.push_back({s, (int32_t)nslots, counts[s], 0});
+        nslots += counts[s];
+    }
+    const int64_t base = nslots;
+    std::vector<double> val(nslots);
+    for (double &v : val) v = u(g);
+    std::vector<double> direct(8, 0.0);
+    for (const Fixup &f : fix)
+        for (int32_t x = 0; x < f.nslots; ++x) direct[f.seg] += val[f.first_slot + x];
+    std::vector<std::vector<Fixup>> levels;
+    build_fix_tree(fix, nslots, levels);
+    require(nslots > base, "tree adds slots");
+    val.resize(nslots, NAN);
+    for (const auto &lv : levels) {
+        for (const Fixup &f : lv) {
+            require(f.nslots <= kFixFan && f.seg >= base && f.seg < nslots, "level fixup");
+            double s = 0.0;
+            for (int32_t x = 0; x < f.nslots; ++x) {
+                require(f.first_slot + x < f.seg, "reads precede the slot written");
+                s += val[f.first_slot + x];
+            }
+            val[f.seg] = s;
+        }
+    }
+    for (const Fixup &f : fix) {
+        require(f.nslots <= kFixFan, "final fixups are shallow");
+        double s = 0.0;
+        for (int32_t x = 0; x < f.nslots; ++x) s += val[f.first_slot + x];
+        require(std::isfinite(s) && std::fabs(s - direct[f.seg]) <= 1e-9 * (1 + std::fabs(direct[f.seg])),
+                "tree sum equals direct sum");
+    }
+    std::printf("ok fix_tree levels=%zu\n", levels.size());
+}
+
+static void check_dgemm() {
+    std::mt19937_64 g(13);
+    std::normal_distribution<double> nd;
+    const int sizes[] = {1, 3, 4, 5, 8, 9, 33, 70};
+    for (int m : sizes)
+        for (int n : sizes)
+            for (int k : {1, 2, 7, 40})
+                for (int ta = 0; ta < 2; ++ta)
+                    for (int tb = 0; tb < 2; ++tb) {
+                        const int lda = (ta ? m : k) + 3, ldb = (tb ? k : n) + 1, ldc = n + 2;
+                        std::vector<double> A((size_t)(ta ? k : m) * lda), B((size_t)(tb ? n : k) * ldb),
+                            C((size_t)m * ldc), C0;
+                        for (double &x : A) x = nd(g);
+                        for (double &x : B) x = nd(g);
+                        for (double &x : C) x = nd(g);
+                        C0 = C;
+                        const double alpha = 0.75, beta = (m + n + k) % 2 ? 0.0 : -0.5;
+                        la::dgemm(ta, tb, m, n, k, alpha, A.data(), lda, B.data(), ldb, beta, C.data(),
+                                  ldc, (m * n * k) % 3 == 0);
+                        for (int i = 0; i < m; ++i)
+                            for (int j = 0; j < n; ++j) {
+                                double s = 0.0, sa = 0.0;
+                                for (int l = 0; l < k; ++l) {
+                                    const double a = ta ? A[(size_t)l * lda + i] : A[(size_t)i * lda + l];
+                                    const double b = tb ? B[(size_t)j * ldb + l] : B[(size_t)l * ldb + j];
+                                    s += a * b;
+                                    sa += std::fabs(a * b);
+                                }
+                                const double want = alpha * s + (beta == 0.0 ? 0.0 : beta * C0[(size_t)i * ldc + j]);
+                                require(std::fabs(C[(size_t)i * ldc + j] - want) <= 1e-13 * (sa + 1.0),
+                                        "dgemm matches the triple loop");
+                            }
+                        for (int i = 0; i < m; ++i)
+                            for (int j = n; j < ldc; ++j)
+                                require(C[(size_t)i * ldc + j] == C0[(size_t)i * ldc + j],
+                                        "dgemm leaves the padding alone");
+                    }
+    std::printf("ok dgemm\n");
+}
+
+static void check_cholesky_and_threads() {
+    std::mt19937_64 g(17);
+    std::normal_distribution<double> nd;
+    for (int n : {1, 5, 47, 48, 49, 100, 130}) {
+        std::vector<double> G((size_t)n * (n + 3)), A((size_t)n * n);
+        for (double &x : G) x = nd(g);
+        la::dgemm(false, true, n, n, n + 3, 1.0, G.data(), n + 3, G.data(), n + 3, 0.0, A.data(), n);
+        std::vector<double> L = A;
+        double piv = 0.0;
+        require(la::cholesky(n, L.data(), &piv), "SPD factorises");
+        double anorm = 0.0;
+        for (double x : A) anorm = std::max(anorm, std::fabs(x));
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double s = 0.0;
+                for (int l = 0; l < n; ++l) s += L[(size_t)i * n + l] * L[(size_t)j * n + l];
+                require(std::fabs(s - A[(size_t)i * n + j]) <= 1e-12 * anorm * n, "L L^T = A");
+                if (j > i) require(L[(size_t)i * n + j] == 0.0, "L lower");
+            }
+        // thread count does not change a bit
+        std::vector<double> L1 = A, L4 = A;
+        la::set_threads(1);
+        la::cholesky(n, L1.data());
+        la::set_threads(4);
+        la::cholesky(n, L4.data());
+        la::set_threads(0);
+        for (size_t x = 0; x < L1.size(); ++x) require(L1[x] == L4[x], "cholesky bitwise across threads");
+        // an indefinite matrix is refused with a nonpositive pivot
+        std::vector<double> Bm = A;
+        for (int i = 0; i < n; ++i) Bm[(size_t)i * n + i] -= 2.0 * anorm * n;
+        piv = 1.0;
+        require(!la::cholesky(n, Bm.data(), &piv) && piv <= 0.0, "indefinite refused");
+    }
+    // dgemm across thread counts
+    const int m = 90, n = 75, k = 300;
+    std::vector<double> A((size_t)m * k), B((size_t)k * n), C1((size_t)m * n), C4((size_t)m * n);
+    for (double &x : A) x = nd(g);
+    for (double &x : B) x = nd(g);
+    la::set_threads(1);
+    la::dgemm(false, false, m, n, k, 1.0, A.data(), k, B.data(), n, 0.0, C1.data(), n, true);
+    la::set_threads(4);
+    la::dgemm(false, false, m, n, k, 1.0, A.data(), k, B.data(), n, 0.0, C4.data(), n, true);
+    la::set_threads(0);
+    for (size_t x = 0; x < C1.size(); ++x) require(C1[x] == C4[x], "dgemm bitwise across threads");
+    std::printf("ok cholesky_threads\n");
+}
+
+static void check_eig() {
+    std::mt19937_64 g(19);
+    std::normal_distribution<double> nd;
+    for (int n : {1, 2, 7, 40, 70}) {
+        std::vector<double> A((size_t)n * n), w(n), V((size_t)n * n);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j <= i; ++j) A[(size_t)i * n + j] = A[(size_t)j * n + i] = nd(g);
+        la::sym_eig(n, A.data(), w.data(), V.data());
+        for (int i = 1; i < n; ++i) require(w[i - 1] >= w[i], "descending eigenvalues");
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double s = 0.0, o = 0.0;
+                for (int l = 0; l < n; ++l) {
+                    s += V[(size_t)i * n + l] * w[l] * V[(size_t)j * n + l];
+                    o += V[(size_t)l * n + i] * V[(size_t)l * n + j];
+                }
+                require(std::fabs(s - A[(size_t)i * n + j]) <= 1e-12 * n, "V W V^T = A");
+                require(std::fabs(o - (i == j ? 1.0 : 0.0)) <= 1e-12 * n, "V orthogonal");
+            }
+    }
+    std::printf("ok sym_eig\n");
+}
+
+// The device interface of the inner solve, implemented with plain loops from
+// its contract (inner.h): the inner solve must reach the same point through
+// it as through its own host products.
+struct LoopDevice : InnerDevice {
+    std::vector<double> C;
+    int k1 = 0, k3 = 0;
+    int calls = 0;
+    double at(int a, int b, int c) const { return C[a + (size_t)k1 * (b + (size_t)k1 * c)]; }
+    void set_core(const double *Cp, int k1_, int k3_) override {
+        k1 = k1_;
+        k3 = k3_;
+        C.assign(Cp, Cp + (size_t)k1 * k1 * k3);
+    }
+    void gram1(double *G1) override {
+        ++calls;
+        for (int a = 0; a < k1; ++a)
+            for (int b = 0; b < k1; ++b) {
+                double s = 0.0;
+                for (int c = 0; c < k3; ++c)
+                    for (int x = 0; x < k1; ++x) s += at(a, x, c) * at(b, x, c);
+                G1[(size_t)a * k1 + b] = s;
+            }
+    }
+    void gram3(double *G3) override {
+        ++calls;
+        for (int c = 0; c < k3; ++c)
+            for (int d = 0; d < k3; ++d) {
+                double s = 0.0;
+                for (int b = 0; b < k1; ++b)
+                    for (int a = 0; a < k1; ++a) s += at(a, b, c) * at(a, b, d);
+                G3[(size_t)c * k3 + d] = s;
+            }
+    }
+    void mode3(const double *Sv, int ldS, int l0, int nl, double *out) override {
+        ++calls;
+        for (int l = 0; l < nl; ++l)
+            for (int b = 0; b < k1; ++b)
+                for (int a = 0; a < k1; ++a) {
+                    double s = 0.0;
+                    for (int c = 0; c < k3; ++c) s += at(a, b, c) * Sv[(size_t)c * ldS + l0 + l];
+                    out[a + (size_t)k1 * (b + (size_t)k1 * l)] = s;
+                }
+    }
+    void hooi3(const double *P, int r, double *M3) override {
+        ++calls;
+        for (int c = 0; c < k3; ++c)
+            for (int i = 0; i < r; ++i)
+                for (int j = 0; j < r; ++j) {
+                    double s = 0.0;
+                    for (int b = 0; b < k1; ++b)
+                        for (int a = 0; a < k1; ++a) s += at(a, b, c) * P[(size_t)a * r + i] * P[(size_t)b * r + j];
+                    M3[(size_t)c * r * r + i + r * j] = s;
+                }
+    }
+    void rotate(const double *Qp, const double *Qs, int r, int r3, double *Y, double *Y2) override {
+        ++calls;
+        std::vector<double> X((size_t)k1 * k1), T((size_t)k1 * k1);
+        for (int l = 0; l < k3; ++l) {
+            for (int b = 0; b < k1; ++b)
+                for (int a = 0; a < k1; ++a) {
+                    double s = 0.0;
+                    for (int c = 0; c < k3; ++c) s += at(a, b, c) * Qs[(size_t)c * k3 + l];
+                    X[(size_t)a * k1 + b] = s;
+                }
+            const int ncol = l < r3 ? k1 : r;
+            for (int a = 0; a < k1; ++a)  // T = X Qp(:, :ncol)
+                for (int y = 0; y < ncol; ++y) {
+                    double s = 0.0;
+                    for (int b = 0; b < k1; ++b) s += X[(size_t)a * k1 + b] * Qp[(size_t)b * k1 + y];
+                    T[(size_t)a * k1 + y] = s;
+                }
+            for (int x = 0; x < k1; ++x)  // Qp^T T
+                for (int y = 0; y < ncol; ++y) {
+                    double s = 0.0;
+                    for (int a = 0; a < k1; ++a) s += Qp[(size_t)a * k1 + x] * T[(size_t)a * k1 + y];
+                    if (l < r3) Y[x + (size_t)k1 * (y + (size_t)k1 * l)] = s;
+                    else Y2[x + (size_t)k1 * (y + (size_t)r * (l - r3))] = s;
+                }
+        }
+    }
+};
+
+static void check_inner_device() {
+    // planted core: C = sum_t f_t u_t o u_t o w_t + small symmetric noise
+    const int k1 = 30, k3 = 20, r = 3, r3 = 3;
+    std::mt19937_64 g(23);
+    std::normal_distribution<double> nd;
+    std::vector<double> U((size_t)k1 * r), W((size_t)k3 * r3);
+    for (double &x : U) x = nd(g);
+    for (double &x : W) x = nd(g);
+    la::orthonormalize(k1, r, U.data());
+    la::orthonormalize(k3, r3, W.data());
+    std::vector<double> C((size_t)k1 * k1 * k3);
+    for (int c = 0; c < k3; ++c)
+        for (int b = 0; b < k1; ++b)
+            for (int a = 0; a <= b; ++a) {
+                double v = 1e-2 * nd(g);
+                for (int t = 0; t < r; ++t)
+                    v += (10.0 - 2.0 * t) * U[(size_t)a * r + t] * U[(size_t)b * r + t] * W[(size_t)c * r3 + t];
+                C[a + (size_t)k1 * (b + (size_t)k1 * c)] = C[b + (size_t)k1 * (a + (size_t)k1 * c)] = v;
+            }
+    std::vector<double> P0, S0, P1, S1;
+    InnerInfo i0, i1;
+    inner_solve(C, k1, k3, r, r3, 1e-13, 5, 50, false, P0, S0, i0);
+    LoopDevice dev;
+    inner_solve(C, k1, k3, r, r3, 1e-13, 5, 50, false, P1, S1, i1, BigSolve(), &dev, 0.0);
+    require(dev.calls > 0, "device path taken");
+    require(i0.rel <= 1e-12 && i1.rel <= 1e-12, "both paths converge");
+    const double g0 = inner_objective(C, k1, k3, P0, S0, r, r3);
+    const double g1 = inner_objective(C, k1, k3, P1, S1, r, r3);
+    require(std::fabs(g0 - g1) <= 1e-12 * g0, "same objective through the device interface");
+    // same subspace: ||(I - P0 P0^T) P1||_F
+    double d2 = 0.0;
+    for (int j = 0; j < r; ++j)
+        for (int i = 0; i < k1; ++i) {
+            double s = P1[(size_t)i * r + j];
+            for (int t = 0; t < r; ++t) {
+                double pt = 0.0;
+                for (int x = 0; x < k1; ++x) pt += P0[(size_t)x * r + t] * P1[(size_t)x * r + j];
+                s -= P0[(size_t)i * r + t] * pt;
+            }
+            d2 += s * s;
+        }
+    require(std::sqrt(d2) <= 1e-10, "same subspace through the device interface");
+    std::printf("ok inner_device calls=%d\n", dev.calls);
+}
+
+int main() {
+    check_schedule();
+    check_wide_schedule();
+    check_fix_tree();
+    check_dgemm();
+    check_cholesky_and_threads();
+    check_eig();
+    check_inner_device();
+    return 0;
+}
