@@ -718,7 +718,8 @@ size_t solve_footprint(int64_t m, int64_t n, const bks_params &prm) {
     // wide core product keeps one k1 x k1 partial per slice chunk and a
     // block-packed copy of X
     const size_t cts = mixed ? 4 : 8;
-    b += (size_t)n * k1 * k1 * cts + (size_t)m * (k1 + 16) * cts;
+    b += std::min<size_t>((size_t)(n + 4096) * k1 * k1 * cts, (size_t)1 << 29) +
+         (size_t)m * (k1 + 16) * cts;
     b += (size_t)n * Q * 8 / 4 + rows * 64 * 8 + (size_t)(1 << 20) * 8;
     return b;
 }

@@ -565,6 +565,7 @@ __global__ __launch_bounds__(256) void ttmc_sym_wide(
 // and writes it to its partial slot; `sym_gram_reduce` sums a slice's
 // chunks in order and writes the upper triangle of M + M^T.
 constexpr int kGramChunk = 16;
+constexpr int64_t kGramItems = 4096;  // target number of slice chunks per product
 
 template <typename VT, typename CT, int R>
 __global__ __launch_bounds__(256) void ttmc_sym_gram(const Item *__restrict__ items,
@@ -651,23 +652,47 @@ __global__ __launch_bounds__(256) void ttmc_sym_gram(const Item *__restrict__ it
 
 // out(k, beta(beta+1)/2 + alpha) = sum over slice k's chunks c, in order, of
 // M_c(alpha, beta) + M_c(beta, alpha), alpha <= beta (zero for an empty slice).
+// One workgroup per slice walks the 32 x 32 tile pairs (I <= J): tiles
+// M_c(I, J) and M_c(J, I) are read row by row (coalesced) into LDS and the
+// transpose is taken there.
 template <typename CT>
 __global__ __launch_bounds__(256) void sym_gram_reduce(const Fixup *__restrict__ fix,
                                                        const CT *__restrict__ part, int p,
                                                        CT *__restrict__ out, int64_t ldo) {
+    __shared__ CT tA[32][33], tB[32][33];
     const Fixup f = fix[blockIdx.x];
     const int64_t pp = (int64_t)p * p;
-    for (int x = threadIdx.x; x < p * p; x += 256) {
-        const int alpha = x / p, beta = x - (x / p) * p;
-        if (alpha > beta) continue;
-        CT s = CT(0);
-        for (int c = 0; c < f.nslots; ++c) {
-            const CT *m = part + (int64_t)(f.first_slot + c) * pp;
-            s += m[(int64_t)alpha * p + beta];
-            s += m[(int64_t)beta * p + alpha];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    const int nt = (p + 31) / 32;
+    for (int I = 0; I < nt; ++I)
+        for (int J = I; J < nt; ++J) {
+            CT acc[4] = {CT(0), CT(0), CT(0), CT(0)};
+            for (int c = 0; c < f.nslots; ++c) {
+                const CT *m = part + (int64_t)(f.first_slot + c) * pp;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int r = ty + 8 * k;
+                    const int ra = I * 32 + r, ca = J * 32 + tx;
+                    const int rb = J * 32 + r, cb = I * 32 + tx;
+                    tA[r][tx] = (ra < p && ca < p) ? m[(int64_t)ra * p + ca] : CT(0);
+                    tB[r][tx] = (rb < p && cb < p) ? m[(int64_t)rb * p + cb] : CT(0);
+                }
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int r = ty + 8 * k;
+                    acc[k] += tA[r][tx];
+                    acc[k] += tB[tx][r];
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int alpha = I * 32 + ty + 8 * k, beta = J * 32 + tx;
+                if (alpha <= beta && beta < p)
+                    out[(int64_t)f.seg * ldo + beta * (beta + 1) / 2 + alpha] = acc[k];
+            }
         }
-        out[(int64_t)f.seg * ldo + beta * (beta + 1) / 2 + alpha] = s;
-    }
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -957,10 +982,13 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
         if (choose_gram(px, dbl, R, T)) {
             const int V = dbl ? 2 : 4;
             const int RP = pad_to(R, V), W = T * RP;
-            // chunk width: at most ~512 MB of partial matrices
+            // chunk width: about kGramItems chunks in all (enough waves to hide
+            // the staging latency), 256..2048 entries, and at most ~512 MB
+            // of partial matrices
             const double per_item = (double)px * px * cts;
             const int64_t max_items = std::max<int64_t>(o.nseg + 1, (int64_t)(536870912.0 / per_item));
-            const int64_t cw64 = std::max<int64_t>(2048, t.nnz / std::max<int64_t>(1, max_items - o.nseg) + 1);
+            int64_t cw64 = std::min<int64_t>(2048, std::max<int64_t>(256, t.nnz / kGramItems));
+            cw64 = std::max<int64_t>(cw64, t.nnz / std::max<int64_t>(1, max_items - o.nseg) + 1);
             const int CW = (int)std::min<int64_t>(cw64, 1 << 30);
             const Schedule &sc = t.schedule(kWideOrder, CW);
             c.ws_fac1.ensure((size_t)std::max<int64_t>(t.m, 1) * W * cts);
