@@ -93,9 +93,12 @@ def roofline_of(stats, workload=None):
     traffic = load_traffic(name, workload) if workload else None
     avg_s = ms / calls / 1e3
     if name.startswith("free3_sym_wide"):
+        # FP32: a dense contraction on the matrix cores (FP32 MFMA peak);
+        # FP64: vector FMA (FP64 peak)
         peak = FP32_PEAK_TFLOPS if name.endswith("_f32") else FP64_PEAK_TFLOPS
+        bound = "mfma" if name.endswith("_f32") else "alu"
         ach = fl / calls / avg_s / 1e12
-        return {"kernel": "ttmc_" + name, "bound": "alu", "achieved": round(ach, 3), "peak": peak,
+        return {"kernel": "ttmc_" + name, "bound": bound, "achieved": round(ach, 3), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": traffic,
                 "launches": calls, "avg_launch_us": round(avg_s * 1e6, 2),
                 "algorithmic_flops_per_launch": fl / calls, **extra}

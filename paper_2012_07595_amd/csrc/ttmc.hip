@@ -695,6 +695,101 @@ __global__ __launch_bounds__(256) void sym_gram_reduce(const Fixup *__restrict__
         }
 }
 
+// ---------------------------------------------------------------- wide sym, matrix cores
+// The same per-chunk matrix M = sum v' X(i,:)^T X(j,:) on the FP32 matrix
+// cores (V_MFMA_F32_16X16X4_F32, 157 TFLOP/s on MI355X against 79 for
+// unpacked FP32 FMA).  k1 is padded to T tiles of 16; wave w of the
+// workgroup owns tile rows w*ROWS .. w*ROWS+ROWS-1 and every tile column.
+// Entries are staged kMfmaChunk at a time (rows of v'-scaled X(i,:) and of
+// X(j,:) in LDS, row stride Wl staggered over the banks); one K-step takes
+// 4 entries: lane l feeds A(r, k) = xi'(k, 16 I + r) and B(k, c) =
+// xj(k, 16 J + c) with r = c = l % 16, k = l / 16, and holds
+// D(4 (l / 16) + i, l % 16) of each 16 x 16 output tile.
+constexpr int kMfmaChunk = 32;
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+
+template <typename VT, int T, int ROWS>
+__global__ __launch_bounds__(512) void ttmc_sym_gram_mfma(const Item *__restrict__ items,
+                                                          const int2 *__restrict__ c12,
+                                                          const VT *__restrict__ val,
+                                                          const float *__restrict__ Xp, int Wl,
+                                                          int p, float *__restrict__ part) {
+    constexpr int W = 16 * T;  // packed row width of X
+    constexpr int U = W / 4;   // 16-byte units per row
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    float *s_xi = reinterpret_cast<float *>(lds_raw);  // [kMfmaChunk][Wl]
+    float *s_xj = s_xi + kMfmaChunk * Wl;
+    float *s_v = s_xj + kMfmaChunk * Wl;  // [kMfmaChunk]
+    i32x2 *s_ij = reinterpret_cast<i32x2 *>(s_v + kMfmaChunk);
+    const i32x2 *__restrict__ cp = reinterpret_cast<const i32x2 *>(c12);
+
+    const Item it = items[blockIdx.x];
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int kq = lane >> 4, rc = lane & 15;
+    f32x4v acc[ROWS][T];
+#pragma unroll
+    for (int a = 0; a < ROWS; ++a)
+#pragma unroll
+        for (int J = 0; J < T; ++J) acc[a][J] = f32x4v{0.f, 0.f, 0.f, 0.f};
+
+    for (int64_t b0 = it.beg; b0 < it.end; b0 += kMfmaChunk) {
+        const int cnt = (int)min<int64_t>(kMfmaChunk, it.end - b0);
+        for (int x = tid; x < kMfmaChunk; x += nth) {
+            i32x2 c = i32x2{0, 0};
+            float v = 0.f;
+            if (x < cnt) {
+                c = cp[b0 + x];
+                v = static_cast<float>(val[b0 + x]);
+                if (c.x == c.y) v *= 0.5f;
+            }
+            s_ij[x] = c;
+            s_v[x] = v;  // padding entries: v' = 0, no contribution
+        }
+        __syncthreads();
+        for (int x = tid; x < kMfmaChunk * 2 * U; x += nth) {
+            const int e = x / (2 * U), rem = x - e * (2 * U);
+            const int w = rem >= U ? 1 : 0, u = rem - w * U;
+            const i32x2 c = s_ij[e];
+            f32x4v d = reinterpret_cast<const f32x4v *>(Xp + (int64_t)(w ? c.y : c.x) * W)[u];
+            if (!w) d = d * s_v[e];
+            reinterpret_cast<f32x4v *>((w ? s_xj : s_xi) + e * Wl)[u] = d;
+        }
+        __syncthreads();
+        const int nk = (cnt + 3) >> 2;
+        for (int kk = 0; kk < nk; ++kk) {
+            const int e = kk * 4 + kq;
+            float a[ROWS], b[T];
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const int I = wave * ROWS + r;
+                a[r] = I < T ? s_xi[e * Wl + I * 16 + rc] : 0.f;
+            }
+#pragma unroll
+            for (int J = 0; J < T; ++J) b[J] = s_xj[e * Wl + J * 16 + rc];
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+                for (int J = 0; J < T; ++J)
+                    acc[r][J] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r], b[J], acc[r][J], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    float *o = part + (int64_t)it.slot * p * p;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int I = wave * ROWS + r;
+        if (I >= T) break;
+#pragma unroll
+        for (int J = 0; J < T; ++J)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = I * 16 + 4 * kq + i, col = J * 16 + rc;
+                if (row < p && col < p) o[(int64_t)row * p + col] = acc[r][J][i];
+            }
+    }
+}
+
 // ---------------------------------------------------------------- dispatch
 template <typename VT, typename CT, int PA, int PB, int MODE>
 void launch_wave(dim3 grid, size_t lds, hipStream_t s, const Item *items,
@@ -797,6 +892,35 @@ bool launch_gram_r(int R, dim3 grid, dim3 block, size_t lds, hipStream_t s, cons
         }
     }
     return false;
+}
+
+template <int T>
+void launch_mfma_t(dim3 grid, size_t lds, hipStream_t s, const Item *items, const int2 *c12,
+                   const float *val, const float *Xp, int Wl, int p, float *part) {
+    constexpr int ROWS = T <= 8 ? 1 : 2;
+    constexpr int NW = (T + ROWS - 1) / ROWS;
+    hipLaunchKernelGGL((ttmc_sym_gram_mfma<float, T, ROWS>), grid, dim3(64 * NW), lds, s, items,
+                       c12, val, Xp, Wl, p, part);
+}
+
+// FP32 Gram product on the matrix cores for 2 <= T = ceil(p / 16) <= 12.
+bool launch_gram_mfma(int T, dim3 grid, size_t lds, hipStream_t s, const Item *items,
+                      const int2 *c12, const float *val, const float *Xp, int Wl, int p,
+                      float *part) {
+    switch (T) {
+    case 2: launch_mfma_t<2>(grid, lds, s, items, c12, val, Xp, Wl, p, part); return true;
+    case 3: launch_mfma_t<3>(grid, lds, s, items, c12, val, Xp, Wl, p, part); return true;
+    case 4: launch_mfma_t<4>(grid, lds, s, items, c12, val, Xp, Wl, p, part); return true;
+    case 5: launch_mfma_t<5>(grid, lds, s, items, c12, val, Xp, Wl, p, part); return true;
+    case 6: launch_mfma_t<6>(grid, lds, s, items, c12, val, Xp, Wl, p, part); return true;
+    case 7: launch_mfma_t<7>(grid, lds, s, items, c12, val, Xp, Wl, p, part); return true;
+    case 8: launch_mfma_t<8>(grid, lds, s, items, c12, val, Xp, Wl, p, part); return true;
+    case 9: launch_mfma_t<9>(grid, lds, s, items, c12, val, Xp, Wl, p, part); return true;
+    case 10: launch_mfma_t<10>(grid, lds, s, items, c12, val, Xp, Wl, p, part); return true;
+    case 11: launch_mfma_t<11>(grid, lds, s, items, c12, val, Xp, Wl, p, part); return true;
+    case 12: launch_mfma_t<12>(grid, lds, s, items, c12, val, Xp, Wl, p, part); return true;
+    default: return false;
+    }
 }
 
 // Register tile R and thread grid T x T for width p: the fewest lane-FMAs
@@ -979,9 +1103,16 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
 
     if (op == BKS_FREE3 && outmode == OUT_SYM && px > kWideThreshold) {
         int R, T;
-        if (choose_gram(px, dbl, R, T)) {
+        // FP32: the matrix-core kernel (tiles of 16) for widths up to 192
+        const int T16 = (px + 15) / 16;
+        const bool mfma = prec == BKS_F32 && T16 >= 2 && T16 <= 12;
+        if (mfma) {
+            R = 16;
+            T = T16;
+        }
+        if (mfma || choose_gram(px, dbl, R, T)) {
             const int V = dbl ? 2 : 4;
-            const int RP = pad_to(R, V), W = T * RP;
+            const int RP = mfma ? 16 : pad_to(R, V), W = T * RP;
             // chunk width: about kGramItems chunks in all (enough waves to hide
             // the staging latency), 256..2048 entries, and at most ~512 MB
             // of partial matrices
@@ -1007,6 +1138,29 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
                 HIPCHECK(hipGetLastError());
             }
             if (sc.nitems > 0) c.ws_partial.ensure((size_t)sc.nitems * px * px * cts);
+            if (mfma) {
+                // row stride with (Wl * 4) % 256 == 64: the four 16-float rows a
+                // K-step reads fall in different banks
+                const int Wl = W + ((16 - W % 64) + 64) % 64;
+                const size_t lds_m = (size_t)(2 * kMfmaChunk * Wl + kMfmaChunk) * 4 +
+                                     (size_t)kMfmaChunk * 8;
+                mark(0);
+                if (sc.nitems > 0) {
+                    if (!launch_gram_mfma(T, dim3((unsigned)sc.nitems), lds_m, s, sc.items.as<Item>(),
+                                          o.c1.as<int2>(), o.v32.as<float>(), c.ws_fac1.as<float>(),
+                                          Wl, px, c.ws_partial.as<float>()))
+                        fail(BKS_EINVAL, "no matrix-core kernel for this width");
+                    HIPCHECK(hipGetLastError());
+                }
+                mark(1);
+                if (sc.nfix > 0) {
+                    hipLaunchKernelGGL(sym_gram_reduce<float>, dim3((unsigned)sc.nfix), dim3(256), 0,
+                                       s, sc.fix.as<Fixup>(), c.ws_partial.as<float>(), px,
+                                       static_cast<float *>(out), ldo);
+                    HIPCHECK(hipGetLastError());
+                }
+                return;
+            }
             const dim3 block((unsigned)((T * T + 63) / 64 * 64));
             const size_t lds = (size_t)(2 * kGramChunk * W + pad_to(kGramChunk, V)) * cts +
                                (size_t)kGramChunk * 8;
