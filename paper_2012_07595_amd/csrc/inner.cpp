@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 
 #include "linalg.h"
 
@@ -432,6 +433,22 @@ void retract(int k, int r, const std::vector<double> &Q, const double *D, std::v
 
 }  // namespace
 
+double device_core_min() {
+    static const double v = [] {
+        const char *e = std::getenv("BKS_DEVICE_CORE_MIN");
+        return e ? std::atof(e) : kDeviceCoreMin;
+    }();
+    return v;
+}
+
+int device_solve_min() {
+    static const int v = [] {
+        const char *e = std::getenv("BKS_DEVICE_SOLVE_MIN");
+        return e ? std::atoi(e) : kDeviceSolveMin;
+    }();
+    return v;
+}
+
 double inner_objective(const std::vector<double> &C, int k1, int k3, const std::vector<double> &P,
                        const std::vector<double> &S, int r, int r3, InnerDevice *dev) {
     View V{C.data(), k1, k3, dev};
@@ -501,7 +518,7 @@ void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, do
         const bool deep_floor = info.rel < 1e-10;
         const int max_attempts = deep_floor ? 4 : 12;
         for (int attempt = 0; attempt < max_attempts && !accepted; ++attempt) {
-            const bool on_device = big && N >= kDeviceSolveMin;
+            const bool on_device = big && N >= device_solve_min();
             if (!on_device) {
                 Hs = H;
                 for (int i = 0; i < N; ++i) Hs[(size_t)i * N + i] += mu;

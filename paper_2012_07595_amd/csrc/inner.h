@@ -36,8 +36,13 @@ struct InnerDevice {
     virtual void rotate(const double *Qp, const double *Qs, int r, int r3, double *Y,
                         double *Y2) = 0;
 };
-// Cores with at least this many entries (k1^2 k3) use the device when given.
-constexpr double kDeviceCoreMin = 1.0e6;
+// Cores with at least this many entries (k1^2 k3) use the device when given
+// (BKS_DEVICE_CORE_MIN overrides); Newton systems of at least
+// device_solve_min() unknowns are factorised on the device
+// (BKS_DEVICE_SOLVE_MIN overrides).
+constexpr double kDeviceCoreMin = 1.0e5;
+double device_core_min();
+int device_solve_min();
 
 struct InnerInfo {
     int iters = 0;        // Newton-Grassmann iterations (incl. HOOI fallbacks)

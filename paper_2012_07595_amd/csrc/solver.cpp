@@ -795,7 +795,8 @@ int run_bks(Ctx &c, Tensor &t, const bks_params &prm, double *U, double *W, doub
             c.devinner.ds = &c.devsolve;
             c.devinner.s = s;
             InnerDevice *dev = &c.devinner;
-            inner_solve(C, S.k1, S.k3, r, r3, itol, hooi_warm, ng_max, warm, P, Sm, ii, big, dev);
+            inner_solve(C, S.k1, S.k3, r, r3, itol, hooi_warm, ng_max, warm, P, Sm, ii, big, dev,
+                        device_core_min());
             if (!warm) {
                 // keep the outer objective non-decreasing (eq. Fnon-decr): if
                 // the HOSVD-started solve ends below the current point E0,
@@ -805,13 +806,13 @@ int run_bks(Ctx &c, Tensor &t, const bks_params &prm, double *U, double *W, doub
                 for (int j = 0; j < r3; ++j) S0[(size_t)j * r3 + j] = 1.0;
                 // (the device holds this C when the inner solve used it)
                 InnerDevice *gdev =
-                    (double)S.k1 * S.k1 * S.k3 >= kDeviceCoreMin ? dev : nullptr;
+                    (double)S.k1 * S.k1 * S.k3 >= device_core_min() ? dev : nullptr;
                 const double g_new = inner_objective(C, S.k1, S.k3, P, Sm, r, r3, gdev);
                 const double g_cur = inner_objective(C, S.k1, S.k3, P0, S0, r, r3, gdev);
                 if (g_new < g_cur * (1.0 - 1e-14)) {
                     InnerInfo i2;
                     inner_solve(C, S.k1, S.k3, r, r3, itol, hooi_warm, ng_max, true, P0, S0, i2,
-                                big, dev);
+                                big, dev, device_core_min());
                     P.swap(P0);
                     Sm.swap(S0);
                     ii.newton += i2.newton;
