@@ -94,7 +94,9 @@ struct DevInner : InnerDevice {
     DevSolver *ds = nullptr;
     hipStream_t s = nullptr;
     int k1 = 0, k3 = 0;
-    DevBuf dC, dA, dB, dOut, dT, dY;
+    DevBuf dC, dA, dB, dOut, dT, dY, dOnes;
+    // out_host(0:len) = sum of the nparts device vectors parts(:, q) (ld len)
+    void sum_parts(const double *parts, int len, int nparts, double *out_host);
     void set_core(const double *C, int k1, int k3) override;
     void gram1(double *G1) override;
     void gram3(double *G3) override;

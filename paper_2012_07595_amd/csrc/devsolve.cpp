@@ -24,6 +24,9 @@ void *DevSolver::get_handle(hipStream_t s) {
     if (!handle) {
         rocblas_handle h = nullptr;
         if (rocblas_create_handle(&h) != rocblas_status_success) fail(BKS_EDEVICE, "rocblas handle");
+        // no atomics: every product sums in a fixed order, run to run
+        if (rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed) != rocblas_status_success)
+            fail(BKS_EDEVICE, "rocblas atomics mode");
         handle = h;
     }
     rocblas_handle h = static_cast<rocblas_handle>(handle);
@@ -95,25 +98,47 @@ void DevInner::set_core(const double *C, int k1_, int k3_) {
     HIPCHECK(hipStreamSynchronize(s));
 }
 
+// A single GEMM with a k1 x k1 (or k3 x k3) result and an inner dimension
+// of k1 k3 (k1^2) runs on one or two workgroups; the Grams are formed as
+// batched partial products over the core's slices instead, summed in a fixed
+// order by a matrix-vector product with ones.
+void DevInner::sum_parts(const double *parts, int len, int nparts, double *out_host) {
+    rocblas_handle h = static_cast<rocblas_handle>(ds->get_handle(s));
+    if (dOnes.bytes < (size_t)nparts * 8) {
+        std::vector<double> ones(nparts, 1.0);
+        dOnes.ensure((size_t)nparts * 8);
+        HIPCHECK(hipMemcpyAsync(dOnes.ptr, ones.data(), (size_t)nparts * 8, hipMemcpyHostToDevice, s));
+        HIPCHECK(hipStreamSynchronize(s));
+    }
+    dOut.ensure((size_t)len * 8);
+    const double one = 1.0, zero = 0.0;
+    check_rb(rocblas_dgemv(h, rocblas_operation_none, len, nparts, &one, parts, len,
+                           dOnes.as<double>(), 1, &zero, dOut.as<double>(), 1),
+             "rocblas_dgemv");
+    HIPCHECK(hipMemcpyAsync(out_host, dOut.ptr, (size_t)len * 8, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+}
+
 void DevInner::gram1(double *G1) {
     rocblas_handle h = static_cast<rocblas_handle>(ds->get_handle(s));
-    dOut.ensure((size_t)k1 * k1 * 8);
-    // C is the column-major k1 x (k1 k3) matrix C_(1)
-    dgemm_sb(h, rocblas_operation_none, rocblas_operation_transpose, k1, k1, k1 * k3, dC.as<double>(),
-             k1, 0, dC.as<double>(), k1, 0, dOut.as<double>(), k1, 0, 1);
-    HIPCHECK(hipMemcpyAsync(G1, dOut.ptr, (size_t)k1 * k1 * 8, hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipStreamSynchronize(s));
+    const int64_t sl = (int64_t)k1 * k1;
+    dT.ensure((size_t)sl * k3 * 8);
+    // part c = X_c X_c^T with X_c = C(:, :, c) (column-major k1 x k1)
+    dgemm_sb(h, rocblas_operation_none, rocblas_operation_transpose, k1, k1, k1, dC.as<double>(),
+             k1, sl, dC.as<double>(), k1, sl, dT.as<double>(), k1, sl, k3);
+    sum_parts(dT.as<double>(), (int)sl, k3, G1);
 }
 
 void DevInner::gram3(double *G3) {
     rocblas_handle h = static_cast<rocblas_handle>(ds->get_handle(s));
     const int sl = k1 * k1;
-    dOut.ensure((size_t)k3 * k3 * 8);
-    // C is the column-major (k1^2) x k3 matrix C_(3)^T
-    dgemm_sb(h, rocblas_operation_transpose, rocblas_operation_none, k3, k3, sl, dC.as<double>(), sl,
-             0, dC.as<double>(), sl, 0, dOut.as<double>(), k3, 0, 1);
-    HIPCHECK(hipMemcpyAsync(G3, dOut.ptr, (size_t)k3 * k3 * 8, hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipStreamSynchronize(s));
+    const int64_t g = (int64_t)k3 * k3;
+    dT.ensure((size_t)g * k1 * 8);
+    // C is the column-major (k1^2) x k3 matrix C_(3)^T; part b is the product
+    // of its rows b k1 .. b k1 + k1 - 1 (the fibres C(:, b, c)) with themselves
+    dgemm_sb(h, rocblas_operation_transpose, rocblas_operation_none, k3, k3, k1, dC.as<double>(), sl,
+             k1, dC.as<double>(), sl, k1, dT.as<double>(), k3, g, k1);
+    sum_parts(dT.as<double>(), (int)g, k1, G3);
 }
 
 void DevInner::mode3(const double *Sv, int ldS, int l0, int nl, double *out) {
