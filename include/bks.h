@@ -183,6 +183,9 @@ typedef struct {
  * Requires 1 <= r <= m, 1 <= r3 <= n, r3 <= r(r+1)/2 (else W0 cannot be
  * spanned by the first products).  k1 > m or k3 > n is capped (Section
  * 3.3.4).  Returns BKS_ENOTCONV if max_outer is reached.  `info` may be NULL.
+ * Runs on the ctx's stream with the ctx's workspaces (device buffers, a
+ * 1 MiB pinned host staging buffer, the rocBLAS handle): solves on one ctx
+ * must not overlap; concurrent solves use one ctx each (or a server).
  * Errors: BKS_EINVAL, BKS_ENOMEM, BKS_EDEVICE. */
 int bks_solve(bks_ctx ctx, bks_tensor t, const bks_params *prm, double *U, double *W,
               double *F, bks_info *info);

@@ -47,6 +47,25 @@ void DevBuf::release() {
     bytes = 0;
 }
 
+PinnedBuf::~PinnedBuf() {
+    if (ptr) (void)hipHostFree(ptr);
+}
+
+void PinnedBuf::ensure(size_t b) {
+    if (b <= bytes) return;
+    if (ptr) (void)hipHostFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+    void *q = nullptr;
+    hipError_t e = hipHostMalloc(&q, b);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(BKS_ENOMEM, "hipHostMalloc of " + std::to_string(b) + " bytes failed");
+    }
+    ptr = static_cast<char *>(q);
+    bytes = b;
+}
+
 }  // namespace bks
 
 using namespace bks;

@@ -41,6 +41,18 @@ struct DevBuf {
     template <class T> T *as() const { return static_cast<T *>(ptr); }
 };
 
+// Page-locked host staging memory owned by the library (freed with its
+// owner; the owner synchronises its stream first).
+struct PinnedBuf {
+    char *ptr = nullptr;
+    size_t bytes = 0;
+    PinnedBuf() = default;
+    PinnedBuf(const PinnedBuf &) = delete;
+    PinnedBuf &operator=(const PinnedBuf &) = delete;
+    ~PinnedBuf();
+    void ensure(size_t b);  // grow-only; contents are not kept
+};
+
 // ---------------------------------------------------------------- formats
 // A segmented entry stream: segments (slices, rows or pairs) own contiguous
 // runs of entries; entry e carries two indices c1[e], c2[e] and a value.
@@ -122,6 +134,7 @@ struct Ctx {
     DevBuf ws_partial;              // TTMc partial rows
     DevBuf ws_pack1, ws_pack2;      // dense-kernel partials
     DevBuf ws_fac1, ws_fac2;        // block-packed factor copies for TTMc
+    PinnedBuf pin;                  // staging of the solver's small copies
     std::mutex mu;
     std::mutex tensors_mu;
     std::vector<Tensor *> tensors;  // live tensors uploaded through this ctx

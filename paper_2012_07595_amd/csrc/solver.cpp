@@ -166,17 +166,52 @@ struct Solver {
         : c(c_), t(t_), s(s_), m(t_.m), n(t_.n), r(r_), r3(r3_), p(p_), stages(st),
           variant(var), mixed(mx) {}
 
-    void sync() { HIPCHECK(hipStreamSynchronize(s)); }
+    // Pinned staging for the small host <-> device copies of the
+    // orthogonalisation: uploads are queued without a wait (their staging
+    // bytes stay untouched until the next synchronisation), downloads land
+    // in pinned memory first.
+    // (the ctx's staging buffer: solves on one ctx do not overlap)
+    static constexpr size_t kPinBytes = (size_t)1 << 20;
+    size_t pin_used = 0;
+    void sync() {
+        HIPCHECK(hipStreamSynchronize(s));
+        pin_used = 0;
+    }
+    char *pin_take(size_t bytes) {
+        if (c.pin.bytes < kPinBytes) {
+            sync();
+            c.pin.ensure(kPinBytes);
+        }
+        if (pin_used + bytes > kPinBytes) sync();
+        char *q = c.pin.ptr + pin_used;
+        pin_used += (bytes + 255) & ~(size_t)255;
+        return q;
+    }
 
     template <class T_>
     void d2h(T_ *h, const void *d, size_t count) {
-        HIPCHECK(hipMemcpyAsync(h, d, count * sizeof(T_), hipMemcpyDeviceToHost, s));
+        const size_t bytes = count * sizeof(T_);
+        if (bytes > kPinBytes / 2) {
+            HIPCHECK(hipMemcpyAsync(h, d, bytes, hipMemcpyDeviceToHost, s));
+            sync();
+            return;
+        }
+        char *q = pin_take(bytes);
+        HIPCHECK(hipMemcpyAsync(q, d, bytes, hipMemcpyDeviceToHost, s));
         sync();
+        std::memcpy(h, q, bytes);
     }
     template <class T_>
     void h2d(void *d, const T_ *h, size_t count) {
-        HIPCHECK(hipMemcpyAsync(d, h, count * sizeof(T_), hipMemcpyHostToDevice, s));
-        sync();
+        const size_t bytes = count * sizeof(T_);
+        if (bytes > kPinBytes / 2) {
+            HIPCHECK(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s));
+            sync();
+            return;
+        }
+        char *q = pin_take(bytes);
+        std::memcpy(q, h, bytes);
+        HIPCHECK(hipMemcpyAsync(d, q, bytes, hipMemcpyHostToDevice, s));
     }
 
     // -------------------------------------------------------- capacities
@@ -292,12 +327,16 @@ struct Solver {
 
     // Orthonormalise B (rows x q, ld) against the basis and append the kept
     // columns; B is left projected off the old basis.  Returns kept count.
-    // hi and lo parts of a q x q double-double Gram at Gd, Gd + 64*64: one copy
-    void gram_dd_download(int q, std::vector<double> &hi, std::vector<double> &lo) {
-        std::vector<double> both((size_t)64 * 64 + (size_t)q * q);
-        d2h(both.data(), Gd.ptr, both.size());
-        hi.assign(both.begin(), both.begin() + (size_t)q * q);
-        lo.assign(both.begin() + 64 * 64, both.end());
+    // hi and lo parts of a q x q double-double Gram at Gd, Gd + 64*64 (and,
+    // with `norms`, nn column norms at Gd + 2*64*64): one copy
+    void gram_dd_download(int q, std::vector<double> &hi, std::vector<double> &lo,
+                          std::vector<double> *norms = nullptr, int nn = 0) {
+        const size_t len = norms ? (size_t)2 * 64 * 64 + nn : (size_t)64 * 64 + (size_t)q * q;
+        std::vector<double> all(len);
+        d2h(all.data(), Gd.ptr, all.size());
+        hi.assign(all.begin(), all.begin() + (size_t)q * q);
+        lo.assign(all.begin() + 64 * 64, all.begin() + 64 * 64 + (size_t)q * q);
+        if (norms) norms->assign(all.begin() + 2 * 64 * 64, all.begin() + 2 * 64 * 64 + nn);
     }
 
     int orth_append(bool isU, double *B, int64_t ldb, int q, double tau) {
@@ -312,9 +351,9 @@ struct Solver {
             double *Bc = B + c0;
             const int room = cap - k;
             if (room <= 0) break;
-            std::vector<double> before2(qc);
-            colnorm2(Bc, ldb, rows, qc, Gd.as<double>(), c, s);
-            d2h(before2.data(), Gd.ptr, qc);
+            // squared column norms before the projection (downloaded with the Gram)
+            std::vector<double> before2;
+            colnorm2(Bc, ldb, rows, qc, Gd.as<double>() + 2 * 64 * 64, c, s);
             double *H = Hd.as<double>();
             for (int pass = 0; pass < 2 && k > 0; ++pass) {
                 gemm_tn_f64(Bas.as<double>(), ldbas, Bc, ldb, rows, k, qc, H, qc, c, s);
@@ -322,7 +361,7 @@ struct Solver {
             }
             std::vector<double> Ghi, Glo;
             gram_dd(Bc, ldb, rows, qc, Gd.as<double>(), Gd.as<double>() + 64 * 64, c, s);
-            gram_dd_download(qc, Ghi, Glo);
+            gram_dd_download(qc, Ghi, Glo, &before2, qc);
             std::vector<int> kept;
             std::vector<double> T;
             chol_drop(qc, Ghi, Glo, before2, tau, room, kept, T);
@@ -425,8 +464,7 @@ struct Solver {
             copy2d_f64(Bas.as<double>(), ld, W, w, rows, w, s);
             std::vector<double> Gh((size_t)w * w), Gl((size_t)w * w);
             gram_dd(W, w, rows, w, Gd.as<double>(), Gd.as<double>() + 64 * 64, c, s);
-            d2h(Gh.data(), Gd.ptr, (size_t)w * w);
-            d2h(Gl.data(), Gd.as<double>() + 64 * 64, (size_t)w * w);
+            gram_dd_download(w, Gh, Gl);
             std::vector<double> ones(w, 1.0), T;
             std::vector<int> kept;
             chol_drop(w, Gh, Gl, ones, 0.0, w, kept, T);
