@@ -43,10 +43,11 @@ void build_wide_schedule(const std::vector<int64_t> &segptr, int CW, std::vector
     fix.clear();
     for (int64_t s = 0; s < nseg; ++s) {
         const int64_t len = segptr[s + 1] - segptr[s];
-        const int64_t nch = (len + CW - 1) / CW;
+        // equal chunks: no short remainder chunk that costs a whole partial
+        const int64_t nch = len == 0 ? 0 : std::max<int64_t>(1, (len + CW / 2) / CW);
         fix.push_back({(int32_t)s, (int32_t)items.size(), (int32_t)nch, 0});
         for (int64_t c = 0; c < nch; ++c) {
-            const int64_t b = segptr[s] + c * CW, e = std::min(segptr[s + 1], b + CW);
+            const int64_t b = segptr[s] + len * c / nch, e = segptr[s] + len * (c + 1) / nch;
             items.push_back({(int32_t)s, -1, b, e, (int32_t)items.size(), 0});
         }
     }

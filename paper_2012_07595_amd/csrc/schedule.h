@@ -32,9 +32,11 @@ constexpr int kHeavySteps = 32;
 constexpr int kLightMax = 48;
 void build_schedule(const std::vector<int64_t> &segptr, int E, std::vector<Item> &items,
                     std::vector<Fixup> &fix, int64_t &nslots);
-// Wide symmetric products: every slice is cut into chunks of at most CW
-// entries, one item each (slot = item index); fix[s] lists slice s's items
-// (every slice, empty ones with nslots = 0).  Cached as order kWideOrder.
+// Wide symmetric products: every nonempty slice of len entries is cut into
+// max(1, round(len / CW)) chunks of equal size (+-1 entry), one item each
+// (slot = item index), so chunks hold between CW / 2 and 1.5 CW entries
+// unless the slice is shorter; fix[s] lists slice s's items (every slice,
+// empty ones with nslots = 0).  Cached as order kWideOrder.
 constexpr int kWideOrder = 3;
 void build_wide_schedule(const std::vector<int64_t> &segptr, int CW, std::vector<Item> &items,
                          std::vector<Fixup> &fix, int64_t &nslots);

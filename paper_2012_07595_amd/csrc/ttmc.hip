@@ -700,11 +700,15 @@ __global__ __launch_bounds__(256) void sym_gram_reduce(const Fixup *__restrict__
 // cores (V_MFMA_F32_16X16X4_F32, 157 TFLOP/s on MI355X against 79 for
 // unpacked FP32 FMA).  k1 is padded to T tiles of 16; wave w of the
 // workgroup owns tile rows w*ROWS .. w*ROWS+ROWS-1 and every tile column.
-// Entries are staged kMfmaChunk at a time (rows of v'-scaled X(i,:) and of
-// X(j,:) in LDS, row stride Wl staggered over the banks); one K-step takes
-// 4 entries: lane l feeds A(r, k) = xi'(k, 16 I + r) and B(k, c) =
-// xj(k, 16 J + c) with r = c = l % 16, k = l / 16, and holds
-// D(4 (l / 16) + i, l % 16) of each 16 x 16 output tile.
+// Entries are staged kMfmaChunk at a time (rows X(i,:) and X(j,:) in LDS,
+// row stride Wl staggered over the banks); one K-step takes 4 entries: lane
+// l feeds A(r, k) = v'(k) xi(k, 16 I + r) and B(k, c) = xj(k, 16 J + c) with
+// r = c = l % 16, k = l / 16, and holds D(4 (l / 16) + i, l % 16) of each
+// 16 x 16 output tile.
+// Software pipeline over the chunks of an item: while the matrix cores work
+// on chunk c from LDS, the row gathers of chunk c + 1 (into registers) and
+// the index loads of chunk c + 3 are in flight; chunk c + 1's and c + 2's
+// index pairs wait in two small LDS buffers.
 constexpr int kMfmaChunk = 32;
 typedef float f32x4v __attribute__((ext_vector_type(4)));
 
@@ -716,15 +720,21 @@ __global__ __launch_bounds__(512) void ttmc_sym_gram_mfma(const Item *__restrict
                                                           int p, float *__restrict__ part) {
     constexpr int W = 16 * T;  // packed row width of X
     constexpr int U = W / 4;   // 16-byte units per row
+    constexpr int NW = (T + ROWS - 1) / ROWS;
+    constexpr int NTH = 64 * NW;                // threads of the workgroup
+    constexpr int NG = kMfmaChunk * 2 * U;      // 16-byte row gathers per chunk
+    constexpr int NQ = (NG + NTH - 1) / NTH;    // per thread
     extern __shared__ __align__(16) unsigned char lds_raw[];
     float *s_xi = reinterpret_cast<float *>(lds_raw);  // [kMfmaChunk][Wl]
     float *s_xj = s_xi + kMfmaChunk * Wl;
-    float *s_v = s_xj + kMfmaChunk * Wl;  // [kMfmaChunk]
-    i32x2 *s_ij = reinterpret_cast<i32x2 *>(s_v + kMfmaChunk);
+    float *s_v = s_xj + kMfmaChunk * Wl;                      // [2][kMfmaChunk]
+    i32x2 *s_ij = reinterpret_cast<i32x2 *>(s_v + 2 * kMfmaChunk);  // [2][kMfmaChunk]
     const i32x2 *__restrict__ cp = reinterpret_cast<const i32x2 *>(c12);
 
     const Item it = items[blockIdx.x];
-    const int tid = threadIdx.x, nth = blockDim.x;
+    const int64_t beg = it.beg, end = it.end;
+    const int nchunk = (int)((end - beg + kMfmaChunk - 1) / kMfmaChunk);
+    const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int kq = lane >> 4, rc = lane & 15;
     f32x4v acc[ROWS][T];
@@ -733,37 +743,75 @@ __global__ __launch_bounds__(512) void ttmc_sym_gram_mfma(const Item *__restrict
 #pragma unroll
         for (int J = 0; J < T; ++J) acc[a][J] = f32x4v{0.f, 0.f, 0.f, 0.f};
 
-    for (int64_t b0 = it.beg; b0 < it.end; b0 += kMfmaChunk) {
-        const int cnt = (int)min<int64_t>(kMfmaChunk, it.end - b0);
-        for (int x = tid; x < kMfmaChunk; x += nth) {
-            i32x2 c = i32x2{0, 0};
-            float v = 0.f;
-            if (x < cnt) {
-                c = cp[b0 + x];
-                v = static_cast<float>(val[b0 + x]);
-                if (c.x == c.y) v *= 0.5f;
-            }
-            s_ij[x] = c;
-            s_v[x] = v;  // padding entries: v' = 0, no contribution
+    // index pair and value of entry tid of a chunk (threads tid < kMfmaChunk);
+    // positions past the item read its last entry (in bounds) with v' = 0
+    i32x2 nidx = i32x2{0, 0};
+    float nv = 0.f;
+    bool nin = false;
+    auto fetch_idx = [&](int ch) {
+        if (tid < kMfmaChunk) {
+            const int64_t e = beg + (int64_t)ch * kMfmaChunk + tid;
+            nin = e < end;
+            const int64_t ec = nin ? e : end - 1;
+            nidx = cp[ec];
+            nv = static_cast<float>(val[ec]);
         }
-        __syncthreads();
-        for (int x = tid; x < kMfmaChunk * 2 * U; x += nth) {
+    };
+    auto commit_idx = [&](int buf) {
+        if (tid < kMfmaChunk) {
+            float v = nin ? nv : 0.f;
+            if (nidx.x == nidx.y) v *= 0.5f;
+            s_ij[buf * kMfmaChunk + tid] = nidx;
+            s_v[buf * kMfmaChunk + tid] = v;
+        }
+    };
+    // row gathers of the chunk whose indices are in buffer `buf`: gather x
+    // is unit u of row w (0: X(i,:), 1: X(j,:)) of entry e
+    f32x4v g[NQ];
+    int lo[NQ];  // LDS destination (floats from s_xi) of gather q
+    auto fetch_rows = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int x = min(tid + q * NTH, NG - 1);
             const int e = x / (2 * U), rem = x - e * (2 * U);
             const int w = rem >= U ? 1 : 0, u = rem - w * U;
-            const i32x2 c = s_ij[e];
-            f32x4v d = reinterpret_cast<const f32x4v *>(Xp + (int64_t)(w ? c.y : c.x) * W)[u];
-            if (!w) d = d * s_v[e];
-            reinterpret_cast<f32x4v *>((w ? s_xj : s_xi) + e * Wl)[u] = d;
+            const i32x2 c = s_ij[buf * kMfmaChunk + e];
+            g[q] = reinterpret_cast<const f32x4v *>(Xp + (int64_t)(w ? c.y : c.x) * W)[u];
+            lo[q] = w * kMfmaChunk * Wl + e * Wl + 4 * u;
         }
-        __syncthreads();
+    };
+    auto commit_rows = [&]() {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (NG % NTH == 0 || tid + q * NTH < NG)
+                *reinterpret_cast<f32x4v *>(s_xi + lo[q]) = g[q];
+    };
+
+    // prologue: indices of chunks 0 and 1 in LDS, rows of chunk 0 in LDS,
+    // indices of chunk 2 in registers
+    fetch_idx(0);
+    commit_idx(0);
+    fetch_idx(1);
+    commit_idx(1);
+    __syncthreads();
+    fetch_rows(0);
+    fetch_idx(2);
+    commit_rows();
+    __syncthreads();
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const bool more = ch + 1 < nchunk;
+        if (more) fetch_rows((ch + 1) & 1);
+        const int cnt = (int)min<int64_t>(kMfmaChunk, end - beg - (int64_t)ch * kMfmaChunk);
         const int nk = (cnt + 3) >> 2;
+        const float *sv = s_v + (ch & 1) * kMfmaChunk;
         for (int kk = 0; kk < nk; ++kk) {
             const int e = kk * 4 + kq;
+            const float ve = sv[e];  // v' of the entry (0 past the item)
             float a[ROWS], b[T];
 #pragma unroll
             for (int r = 0; r < ROWS; ++r) {
                 const int I = wave * ROWS + r;
-                a[r] = I < T ? s_xi[e * Wl + I * 16 + rc] : 0.f;
+                a[r] = I < T ? s_xi[e * Wl + I * 16 + rc] * ve : 0.f;
             }
 #pragma unroll
             for (int J = 0; J < T; ++J) b[J] = s_xj[e * Wl + J * 16 + rc];
@@ -773,6 +821,10 @@ __global__ __launch_bounds__(512) void ttmc_sym_gram_mfma(const Item *__restrict
                 for (int J = 0; J < T; ++J)
                     acc[r][J] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r], b[J], acc[r][J], 0, 0, 0);
         }
+        __syncthreads();  // chunk ch's rows and indices, chunk ch + 1's indices are consumed
+        if (more) commit_rows();
+        commit_idx(ch & 1);  // chunk ch + 2
+        fetch_idx(ch + 3);
         __syncthreads();
     }
     float *o = part + (int64_t)it.slot * p * p;
@@ -1142,8 +1194,8 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
                 // row stride with (Wl * 4) % 256 == 64: the four 16-float rows a
                 // K-step reads fall in different banks
                 const int Wl = W + ((16 - W % 64) + 64) % 64;
-                const size_t lds_m = (size_t)(2 * kMfmaChunk * Wl + kMfmaChunk) * 4 +
-                                     (size_t)kMfmaChunk * 8;
+                const size_t lds_m = (size_t)(2 * kMfmaChunk * Wl + 2 * kMfmaChunk) * 4 +
+                                     (size_t)2 * kMfmaChunk * 8;
                 mark(0);
                 if (sc.nitems > 0) {
                     if (!launch_gram_mfma(T, dim3((unsigned)sc.nitems), lds_m, s, sc.items.as<Item>(),

@@ -87,7 +87,7 @@ static void check_schedule() {
 static void check_wide_schedule() {
     std::mt19937_64 g(9);
     const auto sp = random_segptr(g, 500);
-    for (int CW : {2048, 10000}) {
+    for (int CW : {300, 2048, 10000}) {
         std::vector<Item> items;
         std::vector<Fixup> fix;
         int64_t nslots = 0;
@@ -97,12 +97,23 @@ static void check_wide_schedule() {
         std::vector<int> covered(sp.back(), 0);
         for (size_t q = 0; q < items.size(); ++q) {
             const Item &it = items[q];
-            require(it.slot == (int32_t)q && it.end - it.beg <= CW && it.beg < it.end, "wide item");
+            require(it.slot == (int32_t)q && it.end - it.beg <= CW + CW / 2 + 1 && it.beg < it.end,
+                    "wide item");
             for (int64_t e = it.beg; e < it.end; ++e) covered[e]++;
         }
-        for (const Fixup &f : fix)
-            for (int32_t x = 0; x < f.nslots; ++x)
-                require(items[f.first_slot + x].seg == f.seg, "fix lists the slice's items");
+        for (const Fixup &f : fix) {
+            const int64_t len = sp[f.seg + 1] - sp[f.seg];
+            require(f.nslots == (len == 0 ? 0 : std::max<int64_t>(1, (len + CW / 2) / CW)),
+                    "wide: round(len / CW) chunks");
+            int64_t lo = len, hi = 0;
+            for (int32_t x = 0; x < f.nslots; ++x) {
+                const Item &it = items[f.first_slot + x];
+                require(it.seg == f.seg, "fix lists the slice's items");
+                lo = std::min(lo, it.end - it.beg);
+                hi = std::max(hi, it.end - it.beg);
+            }
+            require(f.nslots < 2 || (hi - lo <= 1 && lo >= CW / 2), "wide: equal chunks");
+        }
         for (int64_t e = 0; e < sp.back(); ++e) require(covered[e] == 1, "wide: every entry once");
     }
     std::printf("ok wide_schedule\n");
