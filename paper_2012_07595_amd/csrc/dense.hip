@@ -334,7 +334,11 @@ void gram_dd(const double *B, int64_t ldb, int64_t rows, int q, double *Ghi, dou
     if (q <= 0) return;
     if (q > DD_MAXQ) fail(BKS_EINVAL, "gram_dd: block wider than 64 columns");
     const int npair = q * (q + 1) / 2;
-    int64_t nblk = std::min<int64_t>(1024, std::max<int64_t>(1, (rows + 255) / 256));
+    // ~64 rows per block: a block's threads own up to 9 column pairs each, so
+    // the kernel is bound by its double-double arithmetic, not by HBM, and
+    // needs many blocks (m = 2e4 rows: 313 blocks; 256 rows per block kept
+    // 3/4 of the chip idle)
+    int64_t nblk = std::min<int64_t>(1024, std::max<int64_t>(1, (rows + 63) / 64));
     int64_t rpb = std::max<int64_t>(1, (rows + nblk - 1) / nblk);
     nblk = std::max<int64_t>(1, (rows + rpb - 1) / rpb);
     c.ws_pack2.ensure((size_t)nblk * npair * 2 * sizeof(double));
