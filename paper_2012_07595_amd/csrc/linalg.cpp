@@ -201,8 +201,8 @@ void top_eigvecs(int n, const double *A, int r, double *Vr, double *wr) {
 bool cholesky(int n, double *A, double *fail_pivot) {
     // Blocked right-looking A = U^T U on the upper triangle (row j of U
     // contiguous): factor the rows of one diagonal block (row AXPYs inside
-    // the block), update the trailing upper triangle with dgemm, then copy
-    // L = U^T into the lower triangle.
+    // the block), update the trailing upper triangle with dgemm; the lower
+    // triangle is cleared.  Both triangular solves then read rows of U.
     constexpr int NB = 48, RB = 64;
     for (int j0 = 0; j0 < n; j0 += NB) {
         const int r0 = std::min(n, j0 + NB), jb = r0 - j0;
@@ -234,24 +234,23 @@ bool cholesky(int n, double *A, double *fail_pivot) {
             });
         }
     }
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < i; ++j) A[(size_t)i * n + j] = A[(size_t)j * n + i];
-    for (int i = 0; i < n; ++i)
-        for (int j = i + 1; j < n; ++j) A[(size_t)i * n + j] = 0.0;
+    for (int i = 0; i < n; ++i) std::fill(A + (size_t)i * n, A + (size_t)i * n + i, 0.0);
     return true;
 }
 
-void chol_solve(int n, const double *L, double *b) {
-    for (int i = 0; i < n; ++i) {
-        double s = b[i];
-        const double *ri = &L[(size_t)i * n];
-        for (int k = 0; k < i; ++k) s -= ri[k] * b[k];
-        b[i] = s / ri[i];
+void chol_solve(int n, const double *U, double *b) {
+    // U^T y = b by columns of U^T (rows of U), then U x = y by rows of U
+    for (int k = 0; k < n; ++k) {
+        const double *uk = &U[(size_t)k * n];
+        const double yk = b[k] / uk[k];
+        b[k] = yk;
+        for (int i = k + 1; i < n; ++i) b[i] -= yk * uk[i];
     }
     for (int i = n - 1; i >= 0; --i) {
+        const double *ui = &U[(size_t)i * n];
         double s = b[i];
-        for (int k = i + 1; k < n; ++k) s -= L[(size_t)k * n + i] * b[k];
-        b[i] = s / L[(size_t)i * n + i];
+        for (int k = i + 1; k < n; ++k) s -= ui[k] * b[k];
+        b[i] = s / ui[i];
     }
 }
 

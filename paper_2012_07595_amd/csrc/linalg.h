@@ -20,12 +20,13 @@ void sym_eig(int n, const double *A, double *w, double *V);
 // Leading r eigenvectors (descending eigenvalues) as an n x r row-major matrix.
 void top_eigvecs(int n, const double *A, int r, double *Vr, double *wr = nullptr);
 
-// Cholesky A = L L^T in place (lower triangle, row-major).  false if A is
+// Cholesky A = U^T U in place (row-major: U in the upper triangle, the
+// strict lower triangle set to zero; U^T = L of A = L L^T).  false if A is
 // not numerically positive definite (then *fail_pivot, if given, is the
 // offending Schur-complement diagonal).
 bool cholesky(int n, double *A, double *fail_pivot = nullptr);
-// Solve L L^T x = b in place.
-void chol_solve(int n, const double *L, double *b);
+// Solve U^T U x = b in place (U from cholesky).
+void chol_solve(int n, const double *U, double *b);
 
 // Householder QR of an m x n (m >= n) row-major matrix: returns the full
 // m x m orthogonal Q (row-major) whose first n columns span the columns.

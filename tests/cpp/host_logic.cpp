@@ -207,18 +207,30 @@ static void check_cholesky_and_threads() {
         std::vector<double> G((size_t)n * (n + 3)), A((size_t)n * n);
         for (double &x : G) x = nd(g);
         la::dgemm(false, true, n, n, n + 3, 1.0, G.data(), n + 3, G.data(), n + 3, 0.0, A.data(), n);
-        std::vector<double> L = A;
+        std::vector<double> U = A;
         double piv = 0.0;
-        require(la::cholesky(n, L.data(), &piv), "SPD factorises");
+        require(la::cholesky(n, U.data(), &piv), "SPD factorises");
         double anorm = 0.0;
         for (double x : A) anorm = std::max(anorm, std::fabs(x));
         for (int i = 0; i < n; ++i)
             for (int j = 0; j < n; ++j) {
                 double s = 0.0;
-                for (int l = 0; l < n; ++l) s += L[(size_t)i * n + l] * L[(size_t)j * n + l];
-                require(std::fabs(s - A[(size_t)i * n + j]) <= 1e-12 * anorm * n, "L L^T = A");
-                if (j > i) require(L[(size_t)i * n + j] == 0.0, "L lower");
+                for (int l = 0; l < n; ++l) s += U[(size_t)l * n + i] * U[(size_t)l * n + j];
+                require(std::fabs(s - A[(size_t)i * n + j]) <= 1e-12 * anorm * n, "U^T U = A");
+                if (j < i) require(U[(size_t)i * n + j] == 0.0, "U upper");
             }
+        // chol_solve against a known solution
+        std::vector<double> x0(n), bb(n, 0.0);
+        for (double &x : x0) x = nd(g);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) bb[i] += A[(size_t)i * n + j] * x0[j];
+        la::chol_solve(n, U.data(), bb.data());
+        double xerr = 0.0, xn = 0.0;
+        for (int i = 0; i < n; ++i) {
+            xerr = std::max(xerr, std::fabs(bb[i] - x0[i]));
+            xn = std::max(xn, std::fabs(x0[i]));
+        }
+        require(xerr <= 1e-8 * xn, "chol_solve recovers x");
         // thread count does not change a bit
         std::vector<double> L1 = A, L4 = A;
         la::set_threads(1);
