@@ -113,6 +113,8 @@ struct DevInner : InnerDevice {
     void gram1(double *G1) override;
     void gram3(double *G3) override;
     void mode3(const double *Sv, int ldS, int l0, int nl, double *out) override;
+    void mode3p(const double *Sv, int ldS, int l0, int nl, const double *P, int r,
+                double *out) override;
     void hooi3(const double *P, int r, double *M3) override;
     void rotate(const double *Qp, const double *Qs, int r, int r3, double *Y,
                 double *Y2) override;

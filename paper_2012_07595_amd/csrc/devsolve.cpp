@@ -156,6 +156,29 @@ void DevInner::mode3(const double *Sv, int ldS, int l0, int nl, double *out) {
     HIPCHECK(hipStreamSynchronize(s));
 }
 
+void DevInner::mode3p(const double *Sv, int ldS, int l0, int nl, const double *P, int r,
+                      double *out) {
+    rocblas_handle h = static_cast<rocblas_handle>(ds->get_handle(s));
+    const int sl = k1 * k1;
+    std::vector<double> Sc((size_t)k3 * nl);  // column-major k3 x nl
+    for (int c = 0; c < k3; ++c)
+        for (int l = 0; l < nl; ++l) Sc[c + (size_t)k3 * l] = Sv[(size_t)c * ldS + l0 + l];
+    dA.ensure(Sc.size() * 8);
+    dB.ensure((size_t)k1 * r * 8);
+    dT.ensure((size_t)sl * nl * 8);
+    dOut.ensure((size_t)k1 * r * nl * 8);
+    HIPCHECK(hipMemcpyAsync(dA.ptr, Sc.data(), Sc.size() * 8, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(dB.ptr, P, (size_t)k1 * r * 8, hipMemcpyHostToDevice, s));
+    // CS = C_(3)^T Sc (k1^2 x nl), then M_l = CS_l P with CS_l the k1 x k1
+    // slice l; P row-major k1 x r reads as the column-major r x k1 matrix P^T
+    dgemm_sb(h, rocblas_operation_none, rocblas_operation_none, sl, nl, k3, dC.as<double>(), sl, 0,
+             dA.as<double>(), k3, 0, dT.as<double>(), sl, 0, 1);
+    dgemm_sb(h, rocblas_operation_none, rocblas_operation_transpose, k1, r, k1, dT.as<double>(), k1,
+             sl, dB.as<double>(), r, 0, dOut.as<double>(), k1, (int64_t)k1 * r, nl);
+    HIPCHECK(hipMemcpyAsync(out, dOut.ptr, (size_t)k1 * r * nl * 8, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+}
+
 void DevInner::hooi3(const double *P, int r, double *M3) {
     rocblas_handle h = static_cast<rocblas_handle>(ds->get_handle(s));
     const int64_t sl = (int64_t)k1 * k1;

@@ -102,15 +102,22 @@ void lead_left(const std::vector<double> &M, int rows, int cols, int w, std::vec
 void hooi_step(const View &V, int r, int r3, std::vector<double> &P, std::vector<double> &S) {
     const int k1 = V.k1, k3 = V.k3;
     const size_t sl = (size_t)k1 * k1;
-    std::vector<double> CS;
-    mode3_product(V, S.data(), r3, 0, r3, CS);  // k1 x k1 x r3
-    // M1(a, j + r*l) = sum_b CS(a, b, l) P(b, j)
+    // M1(a, j + r*l) = sum_b CS(a, b, l) P(b, j), CS = C x_3 S (k1 x k1 x r3)
     const int w1 = r * r3;
     std::vector<double> M1((size_t)k1 * w1);
-    la::parallel_for(r3, [&](int l) {
-        la::dgemm(false, false, k1, r, k1, 1.0, &CS[sl * l], k1, P.data(), r, 0.0, &M1[(size_t)r * l],
-                  w1);
-    });
+    if (V.dev) {
+        std::vector<double> out((size_t)k1 * w1);
+        V.dev->mode3p(S.data(), r3, 0, r3, P.data(), r, out.data());
+        for (int a = 0; a < k1; ++a)
+            for (int x = 0; x < w1; ++x) M1[(size_t)a * w1 + x] = out[a + (size_t)k1 * x];
+    } else {
+        std::vector<double> CS;
+        mode3_product(V, S.data(), r3, 0, r3, CS);
+        la::parallel_for(r3, [&](int l) {
+            la::dgemm(false, false, k1, r, k1, 1.0, &CS[sl * l], k1, P.data(), r, 0.0,
+                      &M1[(size_t)r * l], w1);
+        });
+    }
     lead_left(M1, k1, w1, r, P);
     // M3(c, i + r*j) = sum_{a,b} C(a,b,c) P(a,i) P(b,j)
     const int w3 = r * r;
@@ -403,9 +410,25 @@ double objective(const View &V, const std::vector<double> &P, const std::vector<
                  int r3) {
     const int k1 = V.k1;
     const size_t sl = (size_t)k1 * k1;
+    std::vector<double> gl(r3, 0.0);
+    if (V.dev) {
+        // M_l = CS_l P on the device; g = sum_l ||P^T M_l||^2
+        std::vector<double> M((size_t)k1 * r * r3);
+        V.dev->mode3p(S.data(), r3, 0, r3, P.data(), r, M.data());
+        for (int l = 0; l < r3; ++l)
+            for (int i = 0; i < r; ++i)
+                for (int j = 0; j < r; ++j) {
+                    double t = 0.0;
+                    for (int a = 0; a < k1; ++a)
+                        t += P[(size_t)a * r + i] * M[a + (size_t)k1 * (j + (size_t)r * l)];
+                    gl[l] += t * t;
+                }
+        double g = 0.0;
+        for (double v : gl) g += v;
+        return g;
+    }
     std::vector<double> CS;
     mode3_product(V, S.data(), r3, 0, r3, CS);
-    std::vector<double> gl(r3, 0.0);
     la::parallel_for(r3, [&](int l) {
         std::vector<double> t((size_t)k1 * r), T((size_t)r * r);
         la::dgemm(false, false, k1, r, k1, 1.0, &CS[sl * l], k1, P.data(), r, 0.0, t.data(), r);

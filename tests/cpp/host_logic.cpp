@@ -325,6 +325,21 @@ struct LoopDevice : InnerDevice {
                     out[a + (size_t)k1 * (b + (size_t)k1 * l)] = s;
                 }
     }
+    void mode3p(const double *Sv, int ldS, int l0, int nl, const double *P, int r,
+                double *out) override {
+        ++calls;
+        for (int l = 0; l < nl; ++l)
+            for (int j = 0; j < r; ++j)
+                for (int a = 0; a < k1; ++a) {
+                    double s = 0.0;
+                    for (int b = 0; b < k1; ++b) {
+                        double cs = 0.0;
+                        for (int c = 0; c < k3; ++c) cs += at(a, b, c) * Sv[(size_t)c * ldS + l0 + l];
+                        s += cs * P[(size_t)b * r + j];
+                    }
+                    out[a + (size_t)k1 * (j + (size_t)r * l)] = s;
+                }
+    }
     void hooi3(const double *P, int r, double *M3) override {
         ++calls;
         for (int c = 0; c < k3; ++c)
