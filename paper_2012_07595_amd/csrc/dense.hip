@@ -93,6 +93,73 @@ __global__ __launch_bounds__(256) void reduce_splits_wide(const double *__restri
     if (threadIdx.x == 0) out[(int64_t)kk * ldo + qq] = red[0];
 }
 
+// A^T B for k <= 256 and q <= 64 (the basis against a block of at most 64
+// columns): one block holds the whole k x q product of its row range, so
+// every row of A and B is read once (the 32 x 32 tiling above reads A once
+// per column tile of B and B once per row tile of A).  Thread (ty, tx) owns
+// outputs (ty + 16 i, tx + 16 j), i < KI, j < 4; rows are staged 16 at a
+// time.
+constexpr int TR_ROWS = 16;
+constexpr int TR_KMAX = 256, TR_QMAX = 64;
+
+template <typename TB, int KI>
+__global__ __launch_bounds__(256) void gemm_tn_rows_kernel(const double *__restrict__ A,
+                                                           int64_t lda, const TB *__restrict__ B,
+                                                           int64_t ldb, int64_t rows, int k,
+                                                           int q, int64_t rows_per_split,
+                                                           double *__restrict__ part) {
+    __shared__ double As[TR_ROWS][16 * KI + 1];
+    __shared__ double Bs[TR_ROWS][TR_QMAX + 1];
+    const int split = blockIdx.x;
+    const int64_t r0 = (int64_t)split * rows_per_split;
+    const int64_t r1 = min(rows, r0 + rows_per_split);
+    const int tid = threadIdx.x;
+    const int ty = tid / 16, tx = tid % 16;
+    double acc[KI][4];
+#pragma unroll
+    for (int i = 0; i < KI; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int64_t rb = r0; rb < r1; rb += TR_ROWS) {
+        const int nr = (int)min<int64_t>(TR_ROWS, r1 - rb);
+        for (int x = tid; x < TR_ROWS * k; x += 256) {
+            const int rr = x / k, cc = x - (x / k) * k;
+            As[rr][cc] = rr < nr ? A[(rb + rr) * lda + cc] : 0.0;
+        }
+        for (int x = tid; x < TR_ROWS * q; x += 256) {
+            const int rr = x / q, cc = x - (x / q) * q;
+            Bs[rr][cc] = rr < nr ? (double)B[(rb + rr) * ldb + cc] : 0.0;
+        }
+        __syncthreads();
+        for (int rr = 0; rr < nr; ++rr) {
+            double a[KI], b[4];
+#pragma unroll
+            for (int i = 0; i < KI; ++i) a[i] = ty + 16 * i < k ? As[rr][ty + 16 * i] : 0.0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = tx + 16 * j < q ? Bs[rr][tx + 16 * j] : 0.0;
+#pragma unroll
+            for (int i = 0; i < KI; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < KI; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int kk = ty + 16 * i, qq = tx + 16 * j;
+            if (kk < k && qq < q) part[((int64_t)split * k + kk) * q + qq] = acc[i][j];
+        }
+}
+
+template <typename TB, int KI>
+void launch_tn_rows(int64_t nsplit, const double *A, int64_t lda, const TB *B, int64_t ldb,
+                    int64_t rows, int k, int q, int64_t rps, double *part, hipStream_t s) {
+    hipLaunchKernelGGL((gemm_tn_rows_kernel<TB, KI>), dim3((unsigned)nsplit), dim3(256), 0, s, A,
+                       lda, B, ldb, rows, k, q, rps, part);
+}
+
 void launch_reduce(const double *part, int nsplit, int k, int q, double *out, int64_t ldo,
                    hipStream_t s) {
     const int64_t n = (int64_t)k * q;
@@ -108,6 +175,25 @@ template <typename TB>
 void gemm_tn_impl(const double *A, int64_t lda, const TB *B, int64_t ldb, int64_t rows, int k,
                   int q, double *out, int64_t ldo, Ctx &c, hipStream_t s) {
     if (k <= 0 || q <= 0) return;
+    if (rows > 0 && k <= TR_KMAX && q <= TR_QMAX) {
+        // ~64 rows per block (fewer blocks only for short operands)
+        int64_t nsplit = std::min<int64_t>(1024, std::max<int64_t>(1, rows / 64));
+        const int64_t rps = (rows + nsplit - 1) / nsplit;
+        nsplit = (rows + rps - 1) / rps;
+        c.ws_pack2.ensure((size_t)nsplit * k * q * sizeof(double));
+        double *part = c.ws_pack2.as<double>();
+        if (k <= 32)
+            launch_tn_rows<TB, 2>(nsplit, A, lda, B, ldb, rows, k, q, rps, part, s);
+        else if (k <= 64)
+            launch_tn_rows<TB, 4>(nsplit, A, lda, B, ldb, rows, k, q, rps, part, s);
+        else if (k <= 128)
+            launch_tn_rows<TB, 8>(nsplit, A, lda, B, ldb, rows, k, q, rps, part, s);
+        else
+            launch_tn_rows<TB, 16>(nsplit, A, lda, B, ldb, rows, k, q, rps, part, s);
+        launch_reduce(part, (int)nsplit, k, q, out, ldo, s);
+        HIPCHECK(hipGetLastError());
+        return;
+    }
     const int ntk = (k + TN_T - 1) / TN_T, ntq = (q + TN_T - 1) / TN_T;
     const int tiles = ntk * ntq;
     int64_t nsplit = std::max<int64_t>(1, 2048 / tiles);
