@@ -13,7 +13,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbks.so")
 ARCH = os.environ.get("BKS_OFFLOAD_ARCH", "gfx950")
 
-HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+HIPCC = os.environ.get("HIPCC", os.path.join(ROCM, "bin", "hipcc"))
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wno-unused-result",
           "-I" + os.path.join(os.path.dirname(HERE), "include")]
 # packed FP32 instructions are kept out of the generated code
@@ -27,12 +28,13 @@ def sources():
 
 def compile_one(src: str) -> str:
     obj = os.path.join(BUILD, src + ".o")
-    cmd = [HIPCC, "-c", os.path.join(CSRC, src), "-o", obj] + COMMON
     if src.endswith(".hip"):
-        cmd += DEVICE
+        cmd = [HIPCC, "-c", os.path.join(CSRC, src), "-o", obj] + COMMON + DEVICE
     else:
-        # host code: AVX2 + FMA (every x86-64 host of an MI355X has them)
-        cmd += ["-x", "c++", "-mavx2", "-mfma"]
+        # host code (plain C++: `-x` applies to the inputs after it), with
+        # AVX2 + FMA (every x86-64 host of an MI355X has them)
+        cmd = [HIPCC, "-x", "c++", "-c", os.path.join(CSRC, src), "-o", obj] + COMMON + [
+            "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROCM, "include"), "-mavx2", "-mfma"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -46,8 +48,8 @@ def build(verbose: bool = True) -> str:
         objs = list(ex.map(compile_one, srcs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-o", tmp] + objs + ["--offload-arch=" + ARCH, "-lpthread",
-                                                 "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas",
-                                                 "-Wl,-rpath,/opt/rocm/lib"]
+                                                 "-L" + os.path.join(ROCM, "lib"), "-lrocsolver", "-lrocblas",
+                                                 "-Wl,-rpath," + os.path.join(ROCM, "lib")]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

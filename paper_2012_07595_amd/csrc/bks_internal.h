@@ -106,7 +106,9 @@ struct DevInner : InnerDevice {
     DevSolver *ds = nullptr;
     hipStream_t s = nullptr;
     int k1 = 0, k3 = 0;
-    DevBuf dC, dA, dB, dOut, dT, dY, dOnes;
+    DevBuf dC, dA, dOut, dT, dY, dOnes;
+    PinnedBuf pin;                  // staging of the small transfers
+    double *stage(size_t count);    // pinned host space for `count` doubles
     // out_host(0:len) = sum of the nparts device vectors parts(:, q) (ld len)
     void sum_parts(const double *parts, int len, int nparts, double *out_host);
     void set_core(const double *C, int k1, int k3) override;

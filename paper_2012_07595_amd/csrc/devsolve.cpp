@@ -7,6 +7,8 @@
 //    rotation into [P P_perp], [S S_perp] coordinates) as rocBLAS FP64
 //    GEMMs.  Device matrices are column-major; a row-major host matrix
 //    uploaded as is reads as its transpose.
+#include <algorithm>
+#include <cstring>
 #include <vector>
 
 #include <rocblas/rocblas.h>
@@ -89,6 +91,14 @@ void dgemm_sb(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int 
 }
 }  // namespace
 
+// Small transfers of the inner solve go through a pinned staging buffer
+// (one copy per call for several operands; every DevInner call ends with a
+// stream synchronisation, so the buffer is free again on return).
+double *DevInner::stage(size_t count) {
+    pin.ensure(count * 8);
+    return reinterpret_cast<double *>(pin.ptr);
+}
+
 void DevInner::set_core(const double *C, int k1_, int k3_) {
     k1 = k1_;
     k3 = k3_;
@@ -115,8 +125,10 @@ void DevInner::sum_parts(const double *parts, int len, int nparts, double *out_h
     check_rb(rocblas_dgemv(h, rocblas_operation_none, len, nparts, &one, parts, len,
                            dOnes.as<double>(), 1, &zero, dOut.as<double>(), 1),
              "rocblas_dgemv");
-    HIPCHECK(hipMemcpyAsync(out_host, dOut.ptr, (size_t)len * 8, hipMemcpyDeviceToHost, s));
+    double *hs = stage(len);
+    HIPCHECK(hipMemcpyAsync(hs, dOut.ptr, (size_t)len * 8, hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
+    std::memcpy(out_host, hs, (size_t)len * 8);
 }
 
 void DevInner::gram1(double *G1) {
@@ -160,23 +172,26 @@ void DevInner::mode3p(const double *Sv, int ldS, int l0, int nl, const double *P
                       double *out) {
     rocblas_handle h = static_cast<rocblas_handle>(ds->get_handle(s));
     const int sl = k1 * k1;
-    std::vector<double> Sc((size_t)k3 * nl);  // column-major k3 x nl
+    const size_t ns = (size_t)k3 * nl, np = (size_t)k1 * r, no = (size_t)k1 * r * nl;
+    // staging: [Sc (column-major k3 x nl) | P], then the result
+    double *hs = stage(ns + np + no);
     for (int c = 0; c < k3; ++c)
-        for (int l = 0; l < nl; ++l) Sc[c + (size_t)k3 * l] = Sv[(size_t)c * ldS + l0 + l];
-    dA.ensure(Sc.size() * 8);
-    dB.ensure((size_t)k1 * r * 8);
+        for (int l = 0; l < nl; ++l) hs[c + (size_t)k3 * l] = Sv[(size_t)c * ldS + l0 + l];
+    std::memcpy(hs + ns, P, np * 8);
+    dA.ensure((ns + np) * 8);
     dT.ensure((size_t)sl * nl * 8);
-    dOut.ensure((size_t)k1 * r * nl * 8);
-    HIPCHECK(hipMemcpyAsync(dA.ptr, Sc.data(), Sc.size() * 8, hipMemcpyHostToDevice, s));
-    HIPCHECK(hipMemcpyAsync(dB.ptr, P, (size_t)k1 * r * 8, hipMemcpyHostToDevice, s));
+    dOut.ensure(no * 8);
+    HIPCHECK(hipMemcpyAsync(dA.ptr, hs, (ns + np) * 8, hipMemcpyHostToDevice, s));
+    const double *dS = dA.as<double>(), *dP = dA.as<double>() + ns;
     // CS = C_(3)^T Sc (k1^2 x nl), then M_l = CS_l P with CS_l the k1 x k1
     // slice l; P row-major k1 x r reads as the column-major r x k1 matrix P^T
     dgemm_sb(h, rocblas_operation_none, rocblas_operation_none, sl, nl, k3, dC.as<double>(), sl, 0,
-             dA.as<double>(), k3, 0, dT.as<double>(), sl, 0, 1);
+             dS, k3, 0, dT.as<double>(), sl, 0, 1);
     dgemm_sb(h, rocblas_operation_none, rocblas_operation_transpose, k1, r, k1, dT.as<double>(), k1,
-             sl, dB.as<double>(), r, 0, dOut.as<double>(), k1, (int64_t)k1 * r, nl);
-    HIPCHECK(hipMemcpyAsync(out, dOut.ptr, (size_t)k1 * r * nl * 8, hipMemcpyDeviceToHost, s));
+             sl, dP, r, 0, dOut.as<double>(), k1, (int64_t)k1 * r, nl);
+    HIPCHECK(hipMemcpyAsync(hs + ns + np, dOut.ptr, no * 8, hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
+    std::memcpy(out, hs + ns + np, no * 8);
 }
 
 void DevInner::hooi3(const double *P, int r, double *M3) {
@@ -186,32 +201,40 @@ void DevInner::hooi3(const double *P, int r, double *M3) {
     dA.ensure((size_t)k1 * r * 8);
     dT.ensure((size_t)k1 * r * k3 * 8);
     dOut.ensure((size_t)r * r * k3 * 8);
-    HIPCHECK(hipMemcpyAsync(dA.ptr, P, (size_t)k1 * r * 8, hipMemcpyHostToDevice, s));
+    const size_t np = (size_t)k1 * r, no = (size_t)r * r * k3;
+    double *hs = stage(np + no);
+    std::memcpy(hs, P, np * 8);
+    HIPCHECK(hipMemcpyAsync(dA.ptr, hs, np * 8, hipMemcpyHostToDevice, s));
     // CP_c = C_c P (k1 x r), then M_c = P^T CP_c (r x r, M_c(i, j) at i + r j)
     dgemm_sb(h, rocblas_operation_none, rocblas_operation_transpose, k1, r, k1, dC.as<double>(), k1,
              sl, dA.as<double>(), r, 0, dT.as<double>(), k1, (int64_t)k1 * r, k3);
     dgemm_sb(h, rocblas_operation_none, rocblas_operation_none, r, r, k1, dA.as<double>(), r, 0,
              dT.as<double>(), k1, (int64_t)k1 * r, dOut.as<double>(), r, (int64_t)r * r, k3);
-    HIPCHECK(hipMemcpyAsync(M3, dOut.ptr, (size_t)r * r * k3 * 8, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(hs + np, dOut.ptr, no * 8, hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
+    std::memcpy(M3, hs + np, no * 8);
 }
 
 void DevInner::rotate(const double *Qp, const double *Qs, int r, int r3, double *Y, double *Y2) {
     rocblas_handle h = static_cast<rocblas_handle>(ds->get_handle(s));
     const int64_t sl = (int64_t)k1 * k1;
     const int C1 = k3 - r3;
-    // row-major Qp, Qs read as Qp^T, Qs^T
-    dA.ensure((size_t)k1 * k1 * 8);
-    dB.ensure((size_t)k3 * k3 * 8);
+    // row-major Qp, Qs read as Qp^T, Qs^T; one upload [Qp | Qs], one
+    // download [Y | Y2] through the pinned staging buffer
+    const size_t nqp = (size_t)k1 * k1, nqs = (size_t)k3 * k3;
+    const size_t ny = (size_t)sl * r3, ny2 = (size_t)k1 * r * C1;
+    double *hs = stage(std::max(nqp + nqs, ny + ny2));
+    std::memcpy(hs, Qp, nqp * 8);
+    std::memcpy(hs + nqp, Qs, nqs * 8);
+    dA.ensure((nqp + nqs) * 8);
     dOut.ensure((size_t)sl * k3 * 8);
     dT.ensure((size_t)std::max<int64_t>(sl * r3, (int64_t)k1 * r * C1) * 8);
-    dY.ensure((size_t)(sl * r3 + (int64_t)k1 * r * C1) * 8);
-    HIPCHECK(hipMemcpyAsync(dA.ptr, Qp, (size_t)k1 * k1 * 8, hipMemcpyHostToDevice, s));
-    HIPCHECK(hipMemcpyAsync(dB.ptr, Qs, (size_t)k3 * k3 * 8, hipMemcpyHostToDevice, s));
+    dY.ensure((ny + ny2) * 8);
+    HIPCHECK(hipMemcpyAsync(dA.ptr, hs, (nqp + nqs) * 8, hipMemcpyHostToDevice, s));
+    const double *dQs = dA.as<double>() + nqp;
     // X_l = C.(I, I, Qs(:, l)) for every l: (k1^2 x k3) times Qs
     dgemm_sb(h, rocblas_operation_none, rocblas_operation_transpose, (int)sl, k3, k3,
-             dC.as<double>(), (int)sl, 0, dB.as<double>(), k3, 0, dOut.as<double>(), (int)sl, 0,
-             1);
+             dC.as<double>(), (int)sl, 0, dQs, k3, 0, dOut.as<double>(), (int)sl, 0, 1);
     double *dYl = dY.as<double>(), *dY2 = dY.as<double>() + sl * r3;
     // Y_l = Qp^T (X_l Qp), l < r3
     dgemm_sb(h, rocblas_operation_none, rocblas_operation_transpose, k1, k1, k1, dOut.as<double>(),
@@ -226,10 +249,11 @@ void DevInner::rotate(const double *Qp, const double *Qs, int r, int r3, double 
         dgemm_sb(h, rocblas_operation_none, rocblas_operation_none, k1, r, k1, dA.as<double>(), k1, 0,
                  dT.as<double>(), k1, (int64_t)k1 * r, dY2, k1, (int64_t)k1 * r, C1);
     }
-    HIPCHECK(hipMemcpyAsync(Y, dYl, (size_t)sl * r3 * 8, hipMemcpyDeviceToHost, s));
-    if (C1 > 0)
-        HIPCHECK(hipMemcpyAsync(Y2, dY2, (size_t)k1 * r * C1 * 8, hipMemcpyDeviceToHost, s));
+    // (the upload has been consumed before the download lands: same stream)
+    HIPCHECK(hipMemcpyAsync(hs, dYl, (ny + ny2) * 8, hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
+    std::memcpy(Y, hs, ny * 8);
+    if (C1 > 0) std::memcpy(Y2, hs + ny, ny2 * 8);
 }
 
 }  // namespace bks
