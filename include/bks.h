@@ -26,6 +26,20 @@
  *     is used by one host thread at a time.
  *   - Streams: `stream` arguments are hipStream_t values passed as void*;
  *     NULL means the null stream.
+ *
+ * Environment (the first four are read once per process; results do not
+ * depend on them unless stated)
+ *   BKS_HOST_THREADS      host threads of the inner solve (default: hardware
+ *                         concurrency, at most 8)
+ *   BKS_DEVICE_CORE_MIN   cores with at least this many entries (k1^2 k3) form
+ *                         their dense products on the device (default 1e5;
+ *                         results change only by rounding order)
+ *   BKS_DEVICE_SOLVE_MIN  Newton systems of at least this order are factorised
+ *                         on the device (default 512; rounding order only)
+ *   BKS_DEBUG_INNER=1     one line per inner solve on stderr
+ *   BKS_FAIL_NEXT_ALLOC=1 checked at every device allocation: the next one
+ *                         fails with BKS_ENOMEM and the variable is cleared
+ *                         (tests of the error paths)
  */
 #ifndef BKS_H
 #define BKS_H

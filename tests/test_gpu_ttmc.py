@@ -205,3 +205,20 @@ def test_upload_errors(ctx):
     t = ctx.upload(5, 2, [0, 1, 3], [1, 0, 3], [0, 0, 1], np.array([1.0, 1.0, 2.0]),
                    flags=bks.FULL_SYMMETRIC)
     assert t.nnz == 2
+
+
+def test_allocation_failure_is_reported(ctx, monkeypatch):
+    # a device allocation forced to fail (BKS_FAIL_NEXT_ALLOC) comes back as
+    # BKS_ENOMEM with a message, leaves nothing behind, and the ctx stays usable
+    coo = workloads.sparse_sym(300, 20, 3000, seed=5, dtype=np.float32)
+    monkeypatch.setenv("BKS_FAIL_NEXT_ALLOC", "1")
+    with pytest.raises(bks.BksError) as e:
+        ctx.upload_coo(coo)
+    assert e.value.code == bks.ENOMEM
+    assert "allocation" in str(e.value)
+    monkeypatch.delenv("BKS_FAIL_NEXT_ALLOC", raising=False)
+    t = ctx.upload_coo(coo)
+    o = oracle_tensor(coo)
+    X = factors(coo.m, 3, 7, bks.F32)
+    check(run(ctx, t, bks.FREE3, X, None, coo.n, 6, bks.F32, sym=True),
+          ref.free3(o, X, sym_half=True), bks.F32)
