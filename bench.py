@@ -48,7 +48,16 @@ WORKLOAD_TEXT = {
           "uniform mode 3, |N(0,1)| FP32",
     "c3p": "C3-shaped (1,2)-symmetric 200000x200000x10000, 5e7 stored, Zipf(1.5) modes 1-2, "
            "uniform mode 3, |N(0,1)| FP32 + planted rank-(10,10,10)",
+    "p_princeton": "Princeton-shaped stand-in 6593x6593x29: Zipf(1.0) friendship pairs in their "
+                   "endpoints' flag slices, 6.1e5 stored (1.2e6 full), values 1",
+    "p_reuters": "Reuters-shaped stand-in 13332x13332x66: 2.4e5 stored (4.9e5 full), Zipf(1.0) "
+                 "indices, Zipf(2) integer weights",
+    "p_darpa": "DARPA-shaped stand-in 8891x8891x371: 1e6 stored, Zipf(1.2) indices, binary, "
+               "slices scaled to Frobenius norm 1",
 }
+# the paper's ranks for its data sets (Section 5.2)
+DEFAULT_RANK = {"c2p": 5, "c2": 5, "c3": 10, "c3p": 10, "p_princeton": 3, "p_reuters": 2,
+                "p_darpa": 2}
 
 
 def load_traffic(kernel_class, workload):
@@ -144,10 +153,11 @@ def cpu_baseline(coo, r, U0, W0, gpu_iters, outer=3):
 
 def run_bks(args):
     import torch
-    rank = args.rank if args.rank else (10 if args.workload.startswith("c3") else 5)
+    rank = args.rank if args.rank else DEFAULT_RANK[args.workload]
     t_gen = time.perf_counter()
     coo = {"c2p": workloads.c2_planted, "c2": workloads.c2, "c3": workloads.c3,
-           "c3p": workloads.c3_planted}[args.workload]()
+           "c3p": workloads.c3_planted, "p_princeton": workloads.p_princeton,
+           "p_reuters": workloads.p_reuters, "p_darpa": workloads.p_darpa}[args.workload]()
     U0, W0 = workloads.random_start(coo.m, coo.n, rank, rank, 2024)
     t_gen = time.perf_counter() - t_gen
     assert torch.cuda.is_available(), "bench needs a GPU"
@@ -377,7 +387,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["c2p", "c2", "c3", "c3p"], default="c2p")
+    ap.add_argument("--workload", choices=sorted(WORKLOAD_TEXT), default="c2p")
     ap.add_argument("--rank", type=int, default=0)
     ap.add_argument("--max-outer", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")

@@ -297,6 +297,58 @@ class Request:
     seed: int
 
 
+def p_princeton(seed: int = 1010) -> SymCOO:
+    """Stand-in for the Princeton tensor (Section 5.2, Example 2; the data set
+    is not used): 6593 x 6593 x 29, entry (l, m, v) = 1 when l and m are
+    friends and one of them has flag v.  Friendships are 3.1e5 distinct
+    pairs l != m drawn from a Zipf(1.0) law on the (permuted) node labels;
+    every node gets one of the 29 flags uniformly.  An edge is stored once in
+    each of its endpoints' flag slices: about 6.1e5 stored entries, about
+    1.2e6 entries of the full tensor (the count the paper states)."""
+    m, n, edges = 6593, 29, 310_000
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(m).astype(np.int64)
+    keys = np.empty(0, np.int64)
+    while keys.shape[0] < edges:
+        a = _zipf_labels(rng, m, 2 * edges, 1.0, perm)
+        b = _zipf_labels(rng, m, 2 * edges, 1.0, perm)
+        ok = a != b
+        keys = np.unique(np.concatenate([keys, np.minimum(a, b)[ok] * m + np.maximum(a, b)[ok]]))
+    keys = np.sort(rng.choice(keys, size=edges, replace=False))
+    i, j = keys // m, keys % m
+    flag = rng.integers(0, n, size=m)
+    two = flag[i] != flag[j]
+    ii = np.concatenate([i, i[two]])
+    jj = np.concatenate([j, j[two]])
+    kk = np.concatenate([flag[i], flag[j][two]])
+    order = rng.permutation(ii.shape[0])
+    return SymCOO(m, n, ii[order].astype(np.int32), jj[order].astype(np.int32),
+                  kk[order].astype(np.int32), np.ones(ii.shape[0], np.float32))
+
+
+def p_reuters(seed: int = 1011) -> SymCOO:
+    """Stand-in for the Reuters tensor (Section 5.2, Example 3; the data set
+    is not used): 13332 x 13332 x 66 with 486,894 nonzeros of the full tensor
+    (read as 243,447 stored (i <= j, k) positions), indices from a Zipf(1.0)
+    law, positive integer weights from a Zipf(2) law."""
+    coo = sparse_sym(13332, 66, 243_447, zipf=1.0, values="ones", seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    return dataclasses.replace(coo, val=rng.zipf(2.0, size=coo.nnz).astype(np.float32))
+
+
+def p_darpa(seed: int = 1012) -> SymCOO:
+    """Stand-in for the 1998 DARPA tensor (Section 5.2, Example 4; the data
+    set is not used; its nonzero count is not stated and is read as 1e6
+    stored positions): 8891 x 8891 x 371, binary, indices from a Zipf(1.2)
+    law, then every slice scaled to Frobenius norm 1 as in the paper."""
+    coo = sparse_sym(8891, 371, 1_000_000, zipf=1.2, values="ones", seed=seed)
+    # full-tensor squared norm of slice k: off-diagonal stored entries count twice
+    w = np.where(coo.i == coo.j, 1.0, 2.0)
+    norm2 = np.bincount(coo.k, weights=w, minlength=coo.n)
+    scale = 1.0 / np.sqrt(np.maximum(norm2, 1.0))
+    return dataclasses.replace(coo, val=scale[coo.k].astype(np.float32))
+
+
 def c4_requests(count: int = 512, rate_per_s: float = 10.0, seed: int = 1003,
                 m_range=(1_000, 100_000), n_range=(100, 5_000),
                 nnz_range=(10_000, 5_000_000), ranks=(2, 3, 5, 8, 10)):

@@ -1,0 +1,62 @@
+"""BKS on seeded stand-ins for the paper's data sets (Section 5.2, Examples
+2-4; the data sets themselves are not used): Princeton-, Reuters- and
+DARPA-shaped tensors at the ranks the paper uses for them.
+
+On each, the plain FP64 GPU solve and the mixed-precision solve (BKS(2,4),
+same seeded start, tolerance 1e-10 on the relative G-gradient) both
+converge, agree within a 1e-8 subspace angle (the precision target) and in
+||F|| to 1e-9, and satisfy sum_i s_i^2 = ||F||^2 in both modes (Section 2.6)
+and ||F|| <= ||A||.  HOOI (Section 5.1) from the same start is run beside
+them and never ends above BKS (on the Reuters stand-in it stalls at a lower
+objective, the starting-point sensitivity the paper reports)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2012_07595_amd import bks, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def angle(Ua, Ub):
+    Qa = np.linalg.qr(Ua)[0]
+    Qb = np.linalg.qr(Ub)[0]
+    return float(np.linalg.norm(Qb - Qa @ (Qa.T @ Qb), 2))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = bks.Ctx(0)
+    yield c
+    c.close()
+
+
+CASES = [("p_princeton", 3, 3), ("p_princeton", 4, 3), ("p_reuters", 2, 2),
+         ("p_reuters", 6, 6), ("p_darpa", 2, 2)]
+
+
+@pytest.mark.parametrize("name,r,r3", CASES)
+def test_standin(ctx, name, r, r3):
+    coo = getattr(workloads, name)()
+    t = ctx.upload_coo(coo)
+    U0, W0 = workloads.random_start(coo.m, coo.n, r, r3, 2024)
+    kw = dict(U0=U0, W0=W0, p=4, s=2, max_outer=300, tol=1e-10)
+    U64, W64, F64, i64, rc64 = ctx.solve(t, r, r3, precision=bks.PREC_FP64, **kw)
+    U, W, F, info, rc = ctx.solve(t, r, r3, precision=bks.PREC_MIXED, **kw)
+    assert rc64 == 0 and i64.converged, (rc64, i64.rel_grad)
+    assert rc == 0 and info.converged, (rc, info.rel_grad)
+    a = max(angle(U64, U), angle(W64, W))
+    assert a <= 1e-8, a
+    nF = float(np.linalg.norm(F))
+    assert abs(nF - i64.normF) <= 1e-9 * nF
+    assert nF <= t.frob * (1 + 1e-12)
+    s1 = np.array(info.svals1[:r])
+    s3 = np.array(info.svals3[:r3])
+    assert abs(np.sum(s1 ** 2) - nF ** 2) <= 1e-10 * nF ** 2
+    assert abs(np.sum(s3 ** 2) - nF ** 2) <= 1e-10 * nF ** 2
+    Uh, Wh, Fh, ih, rch = ctx.hooi(t, r, r3, U0=U0, W0=W0, precision=bks.PREC_FP64, tol=1e-10,
+                                   max_iter=3000)
+    assert ih.normF <= i64.normF * (1 + 1e-10), (ih.normF, i64.normF)
+    print(f"[standin] {name} ({r},{r},{r3}) outer {i64.outer_iters}/{info.outer_iters} "
+          f"angle {a:.1e} normF {nF:.6e} HOOI {ih.normF:.6e} status {rch}", flush=True)
