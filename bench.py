@@ -12,6 +12,7 @@ workload and scaled by the GPU's outer-iteration count.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
     python bench.py --ttmc-sweep      # C3-shaped product sweep (one JSON line per product)
+    python bench.py --ablation        # block vs repeated one-column products
 """
 from __future__ import annotations
 
@@ -300,6 +301,65 @@ def ttmc_sweep(args):
         copy_reference(args.copy_ref_mb)
 
 
+def ablation(args):
+    """Block products against repeated single-vector products (the paper's
+    3-9x claim for 6 vectors, Section 3.3): on two tensors of the paper's
+    stated sizes, each block product and the equivalent sequence of
+    one-column products, timed with HIP events (one JSON line each)."""
+    import torch
+    dev = "cuda:0"
+    ctx = bks.Ctx(0)
+    shapes = [("500x500x500", 500, 500), ("3600x3600x60", 3600, 60)]
+    for label, m, n in shapes:
+        coo = workloads.sparse_sym(m, n, 1_000_000, zipf=0.0, values="abs", seed=1020 + n)
+        t = ctx.upload_coo(coo)
+        X = torch.randn(m, 6, device=dev)
+        Y = torch.randn(m, 2, device=dev)
+        Z = torch.randn(n, 6, device=dev)
+        o3 = torch.empty(n, 21, device=dev)
+        o3v = torch.empty(n, 1, device=dev)
+        o1 = torch.empty(m, 6, device=dev)
+        o1v = torch.empty(m, 1, device=dev)
+        om = torch.empty(t.npairs, 6, device=dev)
+        omv = torch.empty(t.npairs, 1, device=dev)
+        cols = [X[:, a:a + 1].contiguous() for a in range(6)]
+        ycols = [Y[:, a:a + 1].contiguous() for a in range(2)]
+        zcols = [Z[:, c:c + 1].contiguous() for c in range(6)]
+        cases = {
+            # A.(X, X)_{1,2}, 6 columns (21 distinct column pairs)
+            "free3_sym": (lambda: ctx.ttmc(t, bks.FREE3, X, None, o3, sym_half=True),
+                          lambda: [ctx.ttmc(t, bks.FREE3, cols[a], cols[b], o3v)
+                                   for b in range(6) for a in range(b + 1)]),
+            # A.(Y, Z)_{2,3}, 2 x 3 columns (6 column pairs)
+            "free1": (lambda: ctx.ttmc(t, bks.FREE1, Y, Z[:, :3], o1),
+                      lambda: [ctx.ttmc(t, bks.FREE1, ycols[b], zcols[c], o1v)
+                               for c in range(3) for b in range(2)]),
+            # A.(Z)_3, 6 columns
+            "mode3": (lambda: ctx.ttmc(t, bks.MODE3, None, Z, om),
+                      lambda: [ctx.ttmc(t, bks.MODE3, None, zcols[c], omv) for c in range(6)]),
+        }
+        for name, (blk, vec) in cases.items():
+            res = {}
+            for kind, fn in (("block", blk), ("vectors", vec)):
+                for _ in range(3):
+                    fn()
+                torch.cuda.synchronize()
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record()
+                for _ in range(args.steps):
+                    fn()
+                b.record()
+                torch.cuda.synchronize()
+                res[kind] = a.elapsed_time(b) * 1e3 / args.steps
+            print(json.dumps({"ablation": name, "tensor": label, "stored": coo.nnz,
+                              "block_us": round(res["block"], 1),
+                              "vectors_us": round(res["vectors"], 1),
+                              "ratio": round(res["vectors"] / res["block"], 2)}), flush=True)
+        t.free()
+    ctx.close()
+
+
 def serving(args):
     """C4-shaped serving trace (one JSON line): requests of different sizes and
     ranks, uploaded by the server after admission; closed-loop throughput, then
@@ -397,6 +457,8 @@ def main():
                     choices=["free3_sym", "free3", "free1", "mode3"])
     ap.add_argument("--copy-ref-mb", type=int, default=0)
     ap.add_argument("--serving", action="store_true")
+    ap.add_argument("--ablation", action="store_true",
+                    help="block products against repeated one-column products")
     ap.add_argument("--requests", type=int, default=64)
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--max-nnz", type=int, default=5_000_000)
@@ -407,6 +469,8 @@ def main():
         sys.exit(2)
     if args.serving:
         serving(args)
+    elif args.ablation:
+        ablation(args)
     elif args.ttmc_sweep:
         ttmc_sweep(args)
     else:
