@@ -114,7 +114,6 @@ struct DevInner : InnerDevice {
     void set_core(const double *C, int k1, int k3) override;
     void gram1(double *G1) override;
     void gram3(double *G3) override;
-    void mode3(const double *Sv, int ldS, int l0, int nl, double *out) override;
     void mode3p(const double *Sv, int ldS, int l0, int nl, const double *P, int r,
                 double *out) override;
     void hooi3(const double *P, int r, double *M3) override;

@@ -153,21 +153,6 @@ void DevInner::gram3(double *G3) {
     sum_parts(dT.as<double>(), (int)g, k1, G3);
 }
 
-void DevInner::mode3(const double *Sv, int ldS, int l0, int nl, double *out) {
-    rocblas_handle h = static_cast<rocblas_handle>(ds->get_handle(s));
-    const int sl = k1 * k1;
-    std::vector<double> Sc((size_t)k3 * nl);  // column-major k3 x nl
-    for (int c = 0; c < k3; ++c)
-        for (int l = 0; l < nl; ++l) Sc[c + (size_t)k3 * l] = Sv[(size_t)c * ldS + l0 + l];
-    dA.ensure(Sc.size() * 8);
-    dOut.ensure((size_t)sl * nl * 8);
-    HIPCHECK(hipMemcpyAsync(dA.ptr, Sc.data(), Sc.size() * 8, hipMemcpyHostToDevice, s));
-    dgemm_sb(h, rocblas_operation_none, rocblas_operation_none, sl, nl, k3, dC.as<double>(), sl, 0,
-             dA.as<double>(), k3, 0, dOut.as<double>(), sl, 0, 1);
-    HIPCHECK(hipMemcpyAsync(out, dOut.ptr, (size_t)sl * nl * 8, hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipStreamSynchronize(s));
-}
-
 void DevInner::mode3p(const double *Sv, int ldS, int l0, int nl, const double *P, int r,
                       double *out) {
     rocblas_handle h = static_cast<rocblas_handle>(ds->get_handle(s));

@@ -45,10 +45,6 @@ void mode3_product(const View &V, const double *Sv, int ldS, int l0, int nl,
     const int k1 = V.k1, k3 = V.k3;
     const int sl = k1 * k1;
     out.resize((size_t)sl * nl);
-    if (V.dev) {
-        V.dev->mode3(Sv, ldS, l0, nl, out.data());
-        return;
-    }
     la::dgemm(true, false, nl, sl, k3, 1.0, Sv + l0, ldS, V.C, sl, 0.0, out.data(), sl, true);
 }
 

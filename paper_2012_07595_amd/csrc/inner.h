@@ -18,10 +18,9 @@ constexpr int kDeviceSolveMin = 512;
 // (C uploaded, layout as below) every call is synchronous and returns host
 // results:
 //   gram1:  G1 = C_(1) C_(1)^T (k1 x k1)          gram3: G3 = C_(3) C_(3)^T (k3 x k3)
-//   mode3:  out(a + k1*(b + k1*l)) = sum_c C(a,b,c) Sv(c, l0 + l), l < nl
-//           (Sv k3 x ldS row-major)
 //   mode3p: out(a + k1*(j + r*l)) = sum_b [sum_c C(a,b,c) Sv(c, l0 + l)] P(b, j),
-//           l < nl (P k1 x r row-major): the mode-3 product times P in mode 2
+//           l < nl (Sv k3 x ldS, P k1 x r, row-major): the mode-3 product
+//           times P in mode 2
 //   hooi3:  M3(c, i + r*j) = sum_{a,b} C(a,b,c) P(a,i) P(b,j) (P k1 x r row-major)
 //   rotate: with Qp (k1 x k1) and Qs (k3 x k3) row-major orthogonal,
 //           X_l = C.(I, I, Qs(:,l)); Y(x, y, l) = (Qp^T X_l Qp)(x, y) for l < r3
@@ -33,7 +32,6 @@ struct InnerDevice {
     virtual void set_core(const double *C, int k1, int k3) = 0;
     virtual void gram1(double *G1) = 0;
     virtual void gram3(double *G3) = 0;
-    virtual void mode3(const double *Sv, int ldS, int l0, int nl, double *out) = 0;
     virtual void mode3p(const double *Sv, int ldS, int l0, int nl, const double *P, int r,
                         double *out) = 0;
     virtual void hooi3(const double *P, int r, double *M3) = 0;

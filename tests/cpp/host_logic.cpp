@@ -315,16 +315,6 @@ struct LoopDevice : InnerDevice {
                 G3[(size_t)c * k3 + d] = s;
             }
     }
-    void mode3(const double *Sv, int ldS, int l0, int nl, double *out) override {
-        ++calls;
-        for (int l = 0; l < nl; ++l)
-            for (int b = 0; b < k1; ++b)
-                for (int a = 0; a < k1; ++a) {
-                    double s = 0.0;
-                    for (int c = 0; c < k3; ++c) s += at(a, b, c) * Sv[(size_t)c * ldS + l0 + l];
-                    out[a + (size_t)k1 * (b + (size_t)k1 * l)] = s;
-                }
-    }
     void mode3p(const double *Sv, int ldS, int l0, int nl, const double *P, int r,
                 double *out) override {
         ++calls;
