@@ -240,7 +240,8 @@ def run_bks(args):
 def copy_reference(mb):
     """A plain device copy of `mb` MiB (outside any timed region): the
     reference that scales the FETCH_SIZE / WRITE_SIZE counters of a profiled
-    run to bytes."""
+    run to bytes, and the measured stream-copy bandwidth (bytes read plus
+    written per second, HIP events over 5 copies after 3)."""
     import torch
     nb = mb << 20
     a = torch.ones(nb // 4, device="cuda:0", dtype=torch.float32)
@@ -248,7 +249,17 @@ def copy_reference(mb):
     for _ in range(3):
         b.copy_(a)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_ref_bytes": nb}), file=sys.stderr, flush=True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nb * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    print(json.dumps({"copy_ref_bytes": nb, "copy_GBs": round(gbs, 1)}), file=sys.stderr,
+          flush=True)
+    return gbs
 
 
 def ttmc_sweep(args):
@@ -263,6 +274,8 @@ def ttmc_sweep(args):
     print(json.dumps({"stage": "uploaded", "seconds": round(time.perf_counter() - t0, 1),
                       "dev_bytes": t.dev_bytes, "pairs": t.npairs}), flush=True)
     del coo
+    # measured stream-copy bandwidth: the attainable HBM rate beside the 8 TB/s
+    copy_gbs = copy_reference(args.copy_ref_mb or 1024)
     dev = "cuda:0"
     cases = []
     for p in args.widths:
@@ -296,9 +309,10 @@ def ttmc_sweep(args):
         st = ctx.profile_read()
         ctx.profile(False)
         rl = roofline_of(st, workload=f"c3/{name}{p2}")
+        if rl.get("unit") == "GB/s":
+            rl["copy_GBs"] = round(copy_gbs, 1)
+            rl["frac_of_copy"] = round(rl["achieved"] / copy_gbs, 4)
         print(json.dumps({"op": name, "p": p2, "roofline": rl}), flush=True)
-    if args.copy_ref_mb:
-        copy_reference(args.copy_ref_mb)
 
 
 def ablation(args):
