@@ -31,7 +31,7 @@ namespace {
 
 constexpr int kMaxP = 5;
 constexpr int kStageBytes = 10240;  // LDS staging budget of one wave
-constexpr int kIdxRegs = 4;         // batch entries held in registers per lane
+constexpr int kIdxRegs = 2;         // batch entries held in registers per lane
 
 enum { MODE_TWO = 0, MODE_ONE = 1, MODE_M3 = 2 };
 enum { OUT_RECT = 0, OUT_SYM = 1 };
