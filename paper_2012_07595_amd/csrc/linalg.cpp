@@ -105,8 +105,10 @@ void tridiag_ql(int n, std::vector<double> &d, std::vector<double> &e, std::vect
     for (int i = 0; i < n; ++i) anorm = std::max(anorm, std::fabs(d[i]) + std::fabs(e[i]));
     if (!std::isfinite(anorm)) throw std::runtime_error("eigensolver: non-finite input");
     // an off-diagonal entry is negligible relative to its neighbours or, for
-    // clusters of (near-)zero eigenvalues, relative to the matrix norm
-    const double floor_ = eps * 1e-3 * anorm;
+    // clusters of (near-)zero eigenvalues, relative to the matrix norm (and
+    // always below the smallest normal number: a tiny matrix whose relative
+    // floor underflows must still converge)
+    const double floor_ = std::max(eps * 1e-3 * anorm, std::numeric_limits<double>::min());
     for (int l = 0; l < n; ++l) {
         int iter = 0;
         int m;
@@ -159,6 +161,77 @@ void tridiag_ql(int n, std::vector<double> &d, std::vector<double> &e, std::vect
 
 }  // namespace
 
+namespace {
+
+// Cyclic Jacobi on a symmetric row-major matrix (destroyed): eigenvalues in
+// w, eigenvectors as the columns of V (row-major).  Slow but unconditionally
+// convergent; the fallback when the QL iteration stalls.
+void jacobi_eig(int n, std::vector<double> &A, std::vector<double> &w, std::vector<double> &V) {
+    V.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+    auto a = [&](int i, int j) -> double & { return A[(size_t)i * n + j]; };
+    double tot = 0.0;
+    for (double x : A) tot += x * x;
+    const double eps = std::numeric_limits<double>::epsilon();
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) off += 2.0 * a(p, q) * a(p, q);
+        if (off <= eps * eps * tot || off == 0.0) {
+            w.resize(n);
+            for (int i = 0; i < n; ++i) w[i] = a(i, i);
+            return;
+        }
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = a(p, q);
+                if (apq == 0.0) continue;
+                // rotation in the (p, q) plane that zeroes A(p, q)
+                const double th = (a(q, q) - a(p, p)) / (2.0 * apq);
+                const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < n; ++k) {
+                    const double akp = a(k, p), akq = a(k, q);
+                    a(k, p) = c * akp - s * akq;
+                    a(k, q) = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double apk = a(p, k), aqk = a(q, k);
+                    a(p, k) = c * apk - s * aqk;
+                    a(q, k) = s * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+                    V[(size_t)k * n + p] = c * vkp - s * vkq;
+                    V[(size_t)k * n + q] = s * vkp + c * vkq;
+                }
+            }
+    }
+    throw std::runtime_error("eigensolver did not converge");
+}
+
+}  // namespace
+
+void sym_eig_jacobi(int n, const double *A, double *w, double *V) {
+    if (n == 0) return;
+    std::vector<double> Z(A, A + (size_t)n * n), wj, Vj;
+    for (double x : Z)
+        if (!std::isfinite(x)) throw std::runtime_error("eigensolver: non-finite input");
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            const double s = 0.5 * (Z[(size_t)i * n + j] + Z[(size_t)j * n + i]);
+            Z[(size_t)i * n + j] = Z[(size_t)j * n + i] = s;
+        }
+    jacobi_eig(n, Z, wj, Vj);
+    std::vector<int> ord(n);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::sort(ord.begin(), ord.end(), [&](int a, int b) { return wj[a] > wj[b]; });
+    for (int j = 0; j < n; ++j) {
+        w[j] = wj[ord[j]];
+        for (int i = 0; i < n; ++i) V[(size_t)i * n + j] = Vj[(size_t)i * n + ord[j]];
+    }
+}
+
 void sym_eig(int n, const double *A, double *w, double *V) {
     if (n == 0) return;
     if (n == 1) {
@@ -167,6 +240,8 @@ void sym_eig(int n, const double *A, double *w, double *V) {
         return;
     }
     std::vector<double> Z(A, A + (size_t)n * n);
+    for (double x : Z)
+        if (!std::isfinite(x)) throw std::runtime_error("eigensolver: non-finite input");
     // symmetrise (callers pass symmetric matrices up to rounding)
     for (int i = 0; i < n; ++i)
         for (int j = i + 1; j < n; ++j) {
@@ -174,11 +249,18 @@ void sym_eig(int n, const double *A, double *w, double *V) {
             Z[(size_t)i * n + j] = Z[(size_t)j * n + i] = s;
         }
     std::vector<double> d, e;
+    const std::vector<double> Asym = Z;
     tridiagonalize(n, Z, d, e);
     std::vector<double> Zt((size_t)n * n);
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) Zt[(size_t)j * n + i] = Z[(size_t)i * n + j];
-    tridiag_ql(n, d, e, Zt);
+    try {
+        tridiag_ql(n, d, e, Zt);
+    } catch (const std::runtime_error &) {
+        // QL stalled: cyclic Jacobi on the symmetrised input
+        sym_eig_jacobi(n, Asym.data(), w, V);
+        return;
+    }
     std::vector<int> ord(n);
     std::iota(ord.begin(), ord.end(), 0);
     std::sort(ord.begin(), ord.end(), [&](int a, int b) { return d[a] > d[b]; });

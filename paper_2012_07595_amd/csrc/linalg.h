@@ -16,6 +16,9 @@ using Mat = std::vector<double>;
 // read).  Eigenvalues in descending order; V(:, i) is column i of the
 // row-major V.  Householder tridiagonalisation + implicit QL.
 void sym_eig(int n, const double *A, double *w, double *V);
+// The same by cyclic Jacobi rotations: slower, unconditionally convergent;
+// sym_eig falls back to it if the QL iteration stalls.
+void sym_eig_jacobi(int n, const double *A, double *w, double *V);
 
 // Leading r eigenvectors (descending eigenvalues) as an n x r row-major matrix.
 void top_eigvecs(int n, const double *A, int r, double *Vr, double *wr = nullptr);

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <limits>
 #include <random>
 #include <vector>
 
@@ -268,6 +269,18 @@ static void check_eig() {
             for (int j = 0; j <= i; ++j) A[(size_t)i * n + j] = A[(size_t)j * n + i] = nd(g);
         la::sym_eig(n, A.data(), w.data(), V.data());
         for (int i = 1; i < n; ++i) require(w[i - 1] >= w[i], "descending eigenvalues");
+        // the Jacobi fallback gives the same spectrum and a valid basis
+        std::vector<double> wj(n), Vj((size_t)n * n);
+        la::sym_eig_jacobi(n, A.data(), wj.data(), Vj.data());
+        for (int i = 0; i < n; ++i) {
+            require(std::fabs(wj[i] - w[i]) <= 1e-12 * n * std::max(1.0, std::fabs(w[0])),
+                    "Jacobi eigenvalues");
+            for (int j = 0; j < n; ++j) {
+                double s = 0.0;
+                for (int l = 0; l < n; ++l) s += Vj[(size_t)i * n + l] * wj[l] * Vj[(size_t)j * n + l];
+                require(std::fabs(s - A[(size_t)i * n + j]) <= 1e-12 * n, "Jacobi V W V^T = A");
+            }
+        }
         for (int i = 0; i < n; ++i)
             for (int j = 0; j < n; ++j) {
                 double s = 0.0, o = 0.0;
@@ -277,6 +290,31 @@ static void check_eig() {
                 }
                 require(std::fabs(s - A[(size_t)i * n + j]) <= 1e-12 * n, "V W V^T = A");
                 require(std::fabs(o - (i == j ? 1.0 : 0.0)) <= 1e-12 * n, "V orthogonal");
+            }
+    }
+    // far-from-unit scales and matrices with many zero eigenvalues converge
+    // (squares stay normal: the Householder norms are plain sums of squares)
+    for (double scale : {1e-150, 1.0, 1e150}) {
+        const int n = 30;
+        std::vector<double> A((size_t)n * n), w(n), V((size_t)n * n);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j <= i; ++j)
+                A[(size_t)i * n + j] = A[(size_t)j * n + i] = scale * nd(g) * (i < 5 && j < 5);
+        la::sym_eig(n, A.data(), w.data(), V.data());
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double o = 0.0;
+                for (int l = 0; l < n; ++l) o += V[(size_t)l * n + i] * V[(size_t)l * n + j];
+                require(std::fabs(o - (i == j ? 1.0 : 0.0)) <= 1e-12 * n, "V orthogonal (scaled)");
+            }
+        double wmax = 0.0;
+        for (double x : w) wmax = std::max(wmax, std::fabs(x));
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double s = 0.0;
+                for (int l = 0; l < n; ++l) s += V[(size_t)i * n + l] * w[l] * V[(size_t)j * n + l];
+                require(std::fabs(s - A[(size_t)i * n + j]) <= 1e-12 * n * wmax,
+                        "V W V^T = A (scaled)");
             }
     }
     std::printf("ok sym_eig\n");
