@@ -57,7 +57,10 @@ void PinnedBuf::ensure(size_t b) {
     ptr = nullptr;
     bytes = 0;
     void *q = nullptr;
-    hipError_t e = hipHostMalloc(&q, b);
+    // coherent (fine-grained): the same staging bytes are written by the host
+    // and read by the copy engines or blit kernels over and over, so no
+    // device cache may keep an old copy of them
+    hipError_t e = hipHostMalloc(&q, b, hipHostMallocCoherent);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         fail(BKS_ENOMEM, "hipHostMalloc of " + std::to_string(b) + " bytes failed");

@@ -815,6 +815,11 @@ int run_bks(Ctx &c, Tensor &t, const bks_params &prm, double *U, double *W, doub
         a = now_s();
         S.form_core(C);
         tc += now_s() - a;
+        for (double v : C)
+            if (!std::isfinite(v))
+                fail(BKS_EDEVICE, "non-finite projected core at outer iteration " +
+                                      std::to_string(it) + " (k1 " + std::to_string(S.k1) +
+                                      ", k3 " + std::to_string(S.k3) + ")");
         a = now_s();
         InnerInfo ii;
         const bool warm = prm.inner_start == 1;
