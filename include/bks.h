@@ -198,7 +198,8 @@ typedef struct {
  * spanned by the first products).  k1 > m or k3 > n is capped (Section
  * 3.3.4).  Returns BKS_ENOTCONV if max_outer is reached.  `info` may be NULL.
  * Runs on the ctx's stream with the ctx's workspaces (device buffers, a
- * 1 MiB pinned host staging buffer, the rocBLAS handle): solves on one ctx
+ * coherent pinned host staging buffers, 1 MiB plus the size of the inner
+ * solve's transfers, the rocBLAS handle): solves on one ctx
  * must not overlap; concurrent solves use one ctx each (or a server).
  * Errors: BKS_EINVAL, BKS_ENOMEM, BKS_EDEVICE. */
 int bks_solve(bks_ctx ctx, bks_tensor t, const bks_params *prm, double *U, double *W,

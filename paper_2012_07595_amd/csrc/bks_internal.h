@@ -41,8 +41,8 @@ struct DevBuf {
     template <class T> T *as() const { return static_cast<T *>(ptr); }
 };
 
-// Page-locked host staging memory owned by the library (freed with its
-// owner; the owner synchronises its stream first).
+// Page-locked, coherent host staging memory owned by the library (freed
+// with its owner; the owner synchronises its stream first).
 struct PinnedBuf {
     char *ptr = nullptr;
     size_t bytes = 0;
