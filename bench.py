@@ -7,8 +7,9 @@ tolerance, from a fixed seeded start, with the tensor already resident in
 HBM.  `value` = solves/s over the K timed steps; p50/p99 are per-solve
 latencies.  The roofline object reports the dominant tensor-product kernel
 class, timed live with HIP events on the stream it runs on.  The CPU
-baseline is the FP64 NumPy oracle timed on one outer iteration of the same
-workload and scaled by the GPU's outer-iteration count.
+baseline is the FP64 NumPy oracle's own BKS solve of the same workload and
+start, stopped after 3 outer iterations and scaled by the GPU's
+outer-iteration count.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
     python bench.py --ttmc-sweep      # C3-shaped product sweep (one JSON line per product)
