@@ -120,6 +120,10 @@ int bks_ctx_profile_read(bks_ctx ctx, int idx, char *name, int name_len, int64_t
  * FP64 values are kept in FP64 as well as rounded to FP32.  The library
  * builds its device formats (slice-major and row-major sorted segments, the
  * stored-pair pattern) once here and owns them until bks_tensor_free.
+ * With BKS_DEVICE_PTRS the four arrays are device memory that the caller
+ * has finished writing (its stream synchronised); they are copied to the
+ * host and not kept.  The call returns once the device formats are
+ * resident.
  * Errors: BKS_EINVAL (m, n < 1, nnz < 0), BKS_EINDEX, BKS_EVALUE,
  * BKS_EASYM, BKS_EDUP, BKS_ENOMEM, BKS_EDEVICE. */
 int bks_tensor_upload(bks_ctx ctx, int64_t m, int64_t n, int64_t nnz, const int32_t *i,

@@ -50,9 +50,13 @@ bool DevSolver::solve(hipStream_t s, int N, const double *H, double mu, bool new
     if (mu != 0.0) {
         // A += mu I: an AXPY of a vector of ones onto the diagonal (stride N + 1)
         if (dones.bytes < (size_t)N * 8) {
-            std::vector<double> ones(N, 1.0);
+            // ones over the whole allocation (ensure adds slack): a later,
+            // larger order that fits finds them written.  The upload runs on
+            // the solve's own stream, which does not wait for the null stream.
             dones.ensure((size_t)N * 8);
-            HIPCHECK(hipMemcpy(dones.ptr, ones.data(), (size_t)N * 8, hipMemcpyHostToDevice));
+            std::vector<double> ones(dones.bytes / 8, 1.0);
+            HIPCHECK(hipMemcpyAsync(dones.ptr, ones.data(), ones.size() * 8, hipMemcpyHostToDevice, s));
+            HIPCHECK(hipStreamSynchronize(s));
         }
         if (rocblas_daxpy(h, N, &mu, dones.as<double>(), 1, dA.as<double>(), N + 1) !=
             rocblas_status_success)
@@ -115,9 +119,10 @@ void DevInner::set_core(const double *C, int k1_, int k3_) {
 void DevInner::sum_parts(const double *parts, int len, int nparts, double *out_host) {
     rocblas_handle h = static_cast<rocblas_handle>(ds->get_handle(s));
     if (dOnes.bytes < (size_t)nparts * 8) {
-        std::vector<double> ones(nparts, 1.0);
+        // ones over the whole allocation, slack included (see DevSolver::solve)
         dOnes.ensure((size_t)nparts * 8);
-        HIPCHECK(hipMemcpyAsync(dOnes.ptr, ones.data(), (size_t)nparts * 8, hipMemcpyHostToDevice, s));
+        std::vector<double> ones(dOnes.bytes / 8, 1.0);
+        HIPCHECK(hipMemcpyAsync(dOnes.ptr, ones.data(), ones.size() * 8, hipMemcpyHostToDevice, s));
         HIPCHECK(hipStreamSynchronize(s));
     }
     dOut.ensure((size_t)len * 8);

@@ -101,10 +101,18 @@ int bits_for(uint64_t maxv) {
     return b;
 }
 
+// A blocking copy from pageable memory may return before its DMA has landed,
+// and the kernels run on non-blocking streams that do not wait for the null
+// stream: wait for the null stream before the data is used.
+void h2d_blocking(void *d, const void *h, size_t bytes) {
+    HIPCHECK(hipMemcpy(d, h, bytes, hipMemcpyHostToDevice));
+    HIPCHECK(hipStreamSynchronize(nullptr));
+}
+
 void upload(DevBuf &d, const void *h, size_t bytes) {
     if (bytes == 0) return;
     d.alloc(bytes);
-    HIPCHECK(hipMemcpy(d.ptr, h, bytes, hipMemcpyHostToDevice));
+    h2d_blocking(d.ptr, h, bytes);
 }
 
 }  // namespace
@@ -331,8 +339,7 @@ const Schedule &Tensor::schedule(int order, int E) {
             auto L = std::make_unique<Schedule::Level>();
             L->nfix = (int64_t)l.size();
             L->fix.alloc(l.size() * sizeof(Fixup));
-            HIPCHECK(hipMemcpy(L->fix.ptr, l.data(), l.size() * sizeof(Fixup),
-                               hipMemcpyHostToDevice));
+            h2d_blocking(L->fix.ptr, l.data(), l.size() * sizeof(Fixup));
             sc->levels.push_back(std::move(L));
         }
     }
@@ -340,13 +347,11 @@ const Schedule &Tensor::schedule(int order, int E) {
     sc->nfix = (int64_t)fx.size();
     if (!items.empty()) {
         sc->items.alloc(items.size() * sizeof(Item));
-        HIPCHECK(hipMemcpy(sc->items.ptr, items.data(), items.size() * sizeof(Item),
-                           hipMemcpyHostToDevice));
+        h2d_blocking(sc->items.ptr, items.data(), items.size() * sizeof(Item));
     }
     if (!fx.empty()) {
         sc->fix.alloc(fx.size() * sizeof(Fixup));
-        HIPCHECK(hipMemcpy(sc->fix.ptr, fx.data(), fx.size() * sizeof(Fixup),
-                           hipMemcpyHostToDevice));
+        h2d_blocking(sc->fix.ptr, fx.data(), fx.size() * sizeof(Fixup));
     }
     auto &ref = *sc;
     sched[key] = std::move(sc);

@@ -149,14 +149,24 @@ def test_bks_mixed_vs_oracle_c2_shaped(ctx):
     compare(ref, U2, W2, F2, info2, 1e-9)
 
 
+_RANK8 = {}
+
+
+def rank8_case():
+    """Planted rank-(8,8,8) tensor with Zipf noise and the oracle's solve of it."""
+    if not _RANK8:
+        P = workloads.planted(3000, 300, tuple(200.0 - 15 * x for x in range(8)), 10, 6, seed=9)
+        noise = workloads.sparse_sym(3000, 300, 60_000, zipf=1.3, values="abs", seed=9)
+        c = workloads.merge(noise.astype(np.float64), P)
+        U0, W0 = workloads.random_start(c.m, c.n, 8, 8, 3)
+        _RANK8["case"] = (c, U0, W0, obks.bks_solve(otensor(c), 8, 8, U0, W0, max_outer=60))
+    return _RANK8["case"]
+
+
 def test_bks_rank8_device_newton(ctx):
     """Rank 8 gives Newton systems of order r(k1-r) + r3(k3-r3) > 512, which
     are factorised on the device."""
-    P = workloads.planted(3000, 300, tuple(200.0 - 15 * x for x in range(8)), 10, 6, seed=9)
-    noise = workloads.sparse_sym(3000, 300, 60_000, zipf=1.3, values="abs", seed=9)
-    c = workloads.merge(noise.astype(np.float64), P)
-    U0, W0 = workloads.random_start(c.m, c.n, 8, 8, 3)
-    ref = obks.bks_solve(otensor(c), 8, 8, U0, W0, max_outer=60)
+    c, U0, W0, ref = rank8_case()
     t = ctx.upload_coo(c)
     U, W, F, info, rc = ctx.solve(t, 8, 8, U0=U0, W0=W0, precision=bks.PREC_FP64, max_outer=60)
     assert info.k1 > 100
@@ -165,6 +175,31 @@ def test_bks_rank8_device_newton(ctx):
     assert min(info.rel_hist[:info.n_hist]) <= 1e-11
     assert min(ref["rel_hist"]) <= 1e-11
     compare(ref, U, W, F, info, 1e-8)
+
+
+def test_bks_rank8_device_newton_on_dirty_memory():
+    """The same solve in a new ctx after 4 GiB of device memory was filled
+    with NaN and handed back to the driver, so that fresh allocations are
+    likely to hold NaN: every device buffer the solve reads must have been
+    written by it first (a freshly mapped allocation reads as zeros and would
+    hide such a read).  The device-side ones vectors (the Newton shift and
+    the slice sums of the core's Grams) are the case in point: they are
+    allocated with slack and reused for larger orders."""
+    c, U0, W0, ref = rank8_case()
+    x = torch.full((1 << 29,), float("nan"), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    del x
+    torch.cuda.empty_cache()
+    ctx2 = bks.Ctx(0)
+    try:
+        t = ctx2.upload_coo(c)
+        U, W, F, info, rc = ctx2.solve(t, 8, 8, U0=U0, W0=W0, precision=bks.PREC_FP64,
+                                       max_outer=60)
+        assert min(info.rel_hist[:info.n_hist]) <= 1e-11
+        compare(ref, U, W, F, info, 1e-8)
+        t.free()
+    finally:
+        ctx2.close()
 
 
 def test_hooi_fp64_vs_oracle(ctx):
