@@ -177,8 +177,10 @@ def test_bks_rank8_device_newton(ctx):
     compare(ref, U, W, F, info, 1e-8)
 
 
-def test_bks_rank8_device_newton_on_dirty_memory():
-    """The same solve in a new ctx after 4 GiB of device memory was filled
+@pytest.mark.parametrize("precision", [bks.PREC_FP64, bks.PREC_MIXED])
+def test_bks_rank8_device_newton_on_dirty_memory(precision):
+    """The same solve (plain FP64, and mixed: FP32 products on the matrix
+    cores) in a new ctx after 4 GiB of device memory was filled
     with NaN and handed back to the driver, so that fresh allocations are
     likely to hold NaN: every device buffer the solve reads must have been
     written by it first (a freshly mapped allocation reads as zeros and would
@@ -193,9 +195,11 @@ def test_bks_rank8_device_newton_on_dirty_memory():
     ctx2 = bks.Ctx(0)
     try:
         t = ctx2.upload_coo(c)
-        U, W, F, info, rc = ctx2.solve(t, 8, 8, U0=U0, W0=W0, precision=bks.PREC_FP64,
+        U, W, F, info, rc = ctx2.solve(t, 8, 8, U0=U0, W0=W0, precision=precision,
                                        max_outer=60)
-        assert min(info.rel_hist[:info.n_hist]) <= 1e-11
+        assert np.all(np.isfinite(U)) and np.all(np.isfinite(W)) and np.all(np.isfinite(F))
+        if precision == bks.PREC_FP64:
+            assert min(info.rel_hist[:info.n_hist]) <= 1e-11
         compare(ref, U, W, F, info, 1e-8)
         t.free()
     finally:
