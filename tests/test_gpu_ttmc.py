@@ -132,6 +132,38 @@ def test_mode3(ctx, tensors, idx, prec, pz):
     check(got, want, prec)
 
 
+def test_products_on_dirty_memory():
+    """Every product kind in a new ctx after 4 GiB of device memory was
+    filled with NaN and handed back, so that the ctx's formats, schedules
+    and workspaces are likely to land on NaN: a read of a workspace entry
+    that the launch did not write shows up as a wrong or non-finite row (a
+    freshly mapped allocation reads as zeros and would hide it)."""
+    m, n, nnz, z, v = CASES[2]
+    coo = workloads.sparse_sym(m, n, nnz, zipf=z, values=v, seed=m + n, dtype=np.float64)
+    x = torch.full((1 << 29,), float("nan"), dtype=torch.float64, device=DEV)
+    torch.cuda.synchronize()
+    del x
+    torch.cuda.empty_cache()
+    c = bks.Ctx(0)
+    try:
+        for prec in PRECS:
+            cc = coo if prec == bks.F64 else coo.astype(np.float32)
+            t, o = c.upload_coo(cc), oracle_tensor(cc)
+            for p in (5, 70, 130):
+                X = factors(o.m, p, 13, prec)
+                got = run(c, t, bks.FREE3, X, None, o.n, p * (p + 1) // 2, prec, sym=True)
+                check(got, ref.free3(o, X, sym_half=True), prec)
+            X, Y = factors(o.m, 5, 11, prec), factors(o.m, 4, 12, prec)
+            check(run(c, t, bks.FREE3, X, Y, o.n, 20, prec), ref.free3(o, X, Y), prec)
+            Y, Z = factors(o.m, 4, 14, prec), factors(o.n, 5, 15, prec)
+            check(run(c, t, bks.FREE1, Y, Z, o.m, 20, prec), ref.free1(o, Y, Z), prec)
+            Z = factors(o.n, 5, 16, prec)
+            check(run(c, t, bks.MODE3, None, Z, t.npairs, 5, prec), ref.mode3(o, Z)[2], prec)
+            t.free()
+    finally:
+        c.close()
+
+
 def test_deterministic(ctx, tensors):
     t, o = pick(tensors, 1, bks.F32)
     X = factors(o.m, 5, 1, bks.F32)
