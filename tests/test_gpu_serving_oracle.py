@@ -49,3 +49,39 @@ def test_c4_small_requests_vs_oracle():
         worst = max(worst, a)
         assert a <= 1e-8, (q.rid, a)
     print(f"[serving-oracle] largest angle {worst:.1e}", flush=True)
+
+
+def test_served_solves_on_dirty_memory():
+    """Four of those requests served by a new ctx after 4 GiB of device memory
+    was filled with NaN and handed back: the sessions' buffers are likely to
+    land on NaN, and every result must still match the oracle."""
+    reqs = sorted((q for q in workloads.c4_requests(count=512, rate_per_s=1.0,
+                                                    nnz_range=(10_000, 5_000_000))
+                   if q.nnz <= 300_000), key=lambda q: q.nnz)[:4]
+    coos = [workloads.request_tensor(q) for q in reqs]
+    starts = [workloads.random_start(q.m, q.n, q.r, q.r, q.seed + 1) for q in reqs]
+    x = torch.full((1 << 29,), float("nan"), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    del x
+    torch.cuda.empty_cache()
+    ctx = bks.Ctx(0)
+    srv = bks.Server(ctx, max_active=4, host_workers=4)
+    try:
+        ids = [srv.submit(None, q.r, q.r, precision=bks.PREC_MIXED, U0=U0, W0=W0, coo=coo,
+                          tol=1e-11)
+               for q, coo, (U0, W0) in zip(reqs, coos, starts)]
+        got = []
+        for rid in ids:
+            U, W, F, res = srv.wait(rid)
+            assert res.done and res.status == 0 and res.info.converged, res.status
+            got.append((U, W))
+    finally:
+        srv.close()
+        ctx.close()
+    for q, coo, (U0, W0), (U, W) in zip(reqs, coos, starts, got):
+        assert np.all(np.isfinite(U)) and np.all(np.isfinite(W))
+        T = sptensor.from_coo(coo.m, coo.n, coo.i, coo.j, coo.k, coo.val.astype(np.float64))
+        ref = obks.bks_solve(T, q.r, q.r, U0, W0, p=4, s=2, tol=1e-11)
+        a = max(obks.subspace_distance(ref["U"], U), obks.subspace_distance(ref["W"], W))
+        print(f"[serving-dirty] request {q.rid} nnz={q.nnz} r={q.r} angle {a:.1e}", flush=True)
+        assert a <= 1e-8, (q.rid, a)
