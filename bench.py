@@ -206,7 +206,9 @@ def run_bks(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 products + f64 orthogonalisation/inner solve (mixed)",
+        "dtype": "f32+f64",
+        "dtype_detail": "f32 tensor-times-block products (the core product on FP32 MFMA); "
+                        "f64 orthogonalisation, gradient and inner solve",
         "data": "synthetic",
         "config": {
             "workload": WORKLOAD_TEXT[args.workload],
