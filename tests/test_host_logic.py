@@ -16,12 +16,23 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2012_07595_amd", "csrc")
 
 
-def test_host_logic(tmp_path):
+# host-only builds (g++, no device code): the plain optimised build, and one
+# with AddressSanitizer and UBSan that fails on any out-of-bounds access,
+# leak or undefined behaviour in the host sources
+BUILDS = {
+    "plain": ["-O2"],
+    "sanitized": ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=undefined"],
+}
+
+
+@pytest.mark.parametrize("build", sorted(BUILDS))
+def test_host_logic(tmp_path, build):
     cxx = shutil.which("g++") or shutil.which("c++")
     if cxx is None:
         pytest.skip("no host C++ compiler")
     exe = str(tmp_path / "host_logic")
-    cmd = [cxx, "-O2", "-std=c++17", "-mavx2", "-mfma", "-pthread", "-I", CSRC,
+    cmd = [cxx] + BUILDS[build] + ["-std=c++17", "-mavx2", "-mfma", "-pthread", "-I", CSRC,
            os.path.join(ROOT, "tests", "cpp", "host_logic.cpp"),
            os.path.join(CSRC, "schedule.cpp"), os.path.join(CSRC, "linalg.cpp"),
            os.path.join(CSRC, "inner.cpp"), "-o", exe]
