@@ -124,7 +124,8 @@ int bks_ctx_profile_read(bks_ctx ctx, int idx, char *name, int name_len, int64_t
  * has finished writing (its stream synchronised); they are copied to the
  * host and not kept.  The call returns once the device formats are
  * resident.
- * Errors: BKS_EINVAL (m, n < 1, nnz < 0), BKS_EINDEX, BKS_EVALUE,
+ * Errors: BKS_EINVAL (m, n < 1, nnz < 0, or 2 n m^2 >= 2^64: the
+ * upload sorts by 64-bit keys over (k, i, j)), BKS_EINDEX, BKS_EVALUE,
  * BKS_EASYM, BKS_EDUP, BKS_ENOMEM, BKS_EDEVICE. */
 int bks_tensor_upload(bks_ctx ctx, int64_t m, int64_t n, int64_t nnz, const int32_t *i,
                       const int32_t *j, const int32_t *k, const void *val, int val_dtype,

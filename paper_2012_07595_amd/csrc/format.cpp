@@ -120,6 +120,9 @@ void upload(DevBuf &d, const void *h, size_t bytes) {
 void build_formats(Tensor &t, const int32_t *I, const int32_t *J, const int32_t *K,
                    const void *val, int val_dtype, unsigned flags) {
     const int64_t m = t.m, n = t.n, nnz = t.nnz;
+    // sort keys pack (k, lo, hi, orientation) into 64 bits: 2 n m^2 must fit
+    if ((long double)n * (long double)m * (long double)m * 2.0L >= 18446744073709551616.0L)
+        fail(BKS_EINVAL, "index space too large: 2 n m^2 must be below 2^64");
     const bool f64 = (val_dtype == BKS_F64);
     const float *v32in = static_cast<const float *>(val);
     const double *v64in = static_cast<const double *>(val);

@@ -44,3 +44,31 @@ def test_host_logic(tmp_path, build):
     for name in ("schedule", "wide_schedule", "fix_tree", "dgemm", "cholesky_threads", "sym_eig",
                  "inner_device"):
         assert f"ok {name}" in r.stdout
+
+
+def test_upload_formats(tmp_path):
+    """The tensor upload's host code (canonicalisation, merging of repeated
+    positions, validation, the slice-major, row-major and pair layouts)
+    against an ordered-map construction of the same layouts, with the HIP
+    runtime calls it makes replaced by host memory; built with
+    AddressSanitizer + UBSan (host code only, g++)."""
+    cxx = shutil.which("g++") or shutil.which("c++")
+    if cxx is None:
+        pytest.skip("no host C++ compiler")
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    if not os.path.exists(os.path.join(rocm, "include", "hip", "hip_runtime.h")):
+        pytest.skip("no HIP headers")
+    exe = str(tmp_path / "format_host")
+    cmd = [cxx] + BUILDS["sanitized"] + ["-std=c++17", "-mavx2", "-mfma", "-pthread",
+                                         "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(rocm, "include"),
+                                         "-I", CSRC,
+                                         os.path.join(ROOT, "tests", "cpp", "format_host.cpp"),
+                                         os.path.join(CSRC, "format.cpp"),
+                                         os.path.join(CSRC, "schedule.cpp"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+    print(r.stdout)
+    assert r.returncode == 0, r.stdout + r.stderr
+    for name in ("random", "distinct", "full_symmetric", "validation"):
+        assert f"ok formats_{name}" in r.stdout
