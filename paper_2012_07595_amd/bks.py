@@ -178,7 +178,26 @@ class Ctx:
             idx += 1
 
     def upload(self, m, n, i, j, k, val, flags=0):
-        """Upload host coordinates (numpy int32 arrays, float32/float64 values)."""
+        """Upload coordinates: host arrays (converted to int32 and float32 /
+        float64), or contiguous device tensors (int32 coordinates, float32 or
+        float64 values) that the caller has finished writing, passed as device
+        pointers (BKS_DEVICE_PTRS)."""
+        if all(getattr(a, "is_cuda", False) for a in (i, j, k, val)):
+            for a in (i, j, k):
+                if a.element_size() != 4 or a.is_floating_point() or not a.is_contiguous():
+                    raise ValueError("device coordinates must be contiguous int32 tensors")
+            if not val.is_floating_point() or val.element_size() not in (4, 8) \
+                    or not val.is_contiguous():
+                raise ValueError("device values must be a contiguous float32/float64 tensor")
+            nnz = int(i.numel())
+            if j.numel() != nnz or k.numel() != nnz or val.numel() != nnz:
+                raise ValueError("coordinate and value lengths differ")
+            dt = F64 if val.element_size() == 8 else F32
+            h = C.c_void_p()
+            self.check(self.lib.bks_tensor_upload(self.h, m, n, nnz, _ptr(i), _ptr(j), _ptr(k),
+                                                  _ptr(val), dt, flags | DEVICE_PTRS,
+                                                  C.byref(h)))
+            return self._track(Tensor(self, h))
         i = np.ascontiguousarray(i, dtype=np.int32)
         j = np.ascontiguousarray(j, dtype=np.int32)
         k = np.ascontiguousarray(k, dtype=np.int32)
@@ -189,7 +208,9 @@ class Ctx:
         h = C.c_void_p()
         self.check(self.lib.bks_tensor_upload(self.h, m, n, int(i.shape[0]), _ptr(i), _ptr(j),
                                               _ptr(k), _ptr(val), dt, flags, C.byref(h)))
-        t = Tensor(self, h)
+        return self._track(Tensor(self, h))
+
+    def _track(self, t):
         import weakref
         if not hasattr(self, "_tensors"):
             self._tensors = []

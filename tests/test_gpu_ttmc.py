@@ -221,6 +221,33 @@ def test_edge_cases(ctx, kind):
     assert abs(t.frob - np.sqrt(sptensor.frob2(o))) <= 1e-12 * max(1.0, t.frob)
 
 
+def test_upload_from_device_arrays(ctx):
+    """Coordinates and values given as device arrays (BKS_DEVICE_PTRS) build
+    the same tensor as the host upload: same sizes, norm and pair pattern,
+    and bitwise the same products for every op and precision."""
+    c = workloads.sparse_sym(1031, 17, 9000, zipf=1.1, seed=8, dtype=np.float64)
+    th = ctx.upload_coo(c)
+    dev = [torch.tensor(a, dtype=torch.int32, device=DEV) for a in (c.i, c.j, c.k)]
+    v = torch.tensor(c.val, dtype=torch.float64, device=DEV)
+    torch.cuda.synchronize()
+    td = ctx.upload(c.m, c.n, *dev, v)
+    assert (td.nnz, td.npairs, td.frob) == (th.nnz, th.npairs, th.frob)
+    for a, b in zip(td.pairs(), th.pairs()):
+        np.testing.assert_array_equal(a, b)
+    for prec in PRECS:
+        X = factors(c.m, 4, 1, prec)
+        Z = factors(c.n, 3, 2, prec)
+        got = [(run(ctx, t_, bks.FREE3, X, None, c.n, 10, prec, sym=True),
+                run(ctx, t_, bks.FREE1, X, Z, c.m, 12, prec),
+                run(ctx, t_, bks.MODE3, None, Z, t_.npairs, 3, prec)) for t_ in (td, th)]
+        for a, b in zip(*got):
+            np.testing.assert_array_equal(a, b)
+    with pytest.raises(ValueError):
+        ctx.upload(c.m, c.n, dev[0].to(torch.int64), dev[1], dev[2], v)
+    td.free()
+    th.free()
+
+
 def test_upload_errors(ctx):
     with pytest.raises(bks.BksError) as e:
         ctx.upload(5, 2, [0], [5], [0], np.array([1.0]))
