@@ -181,7 +181,7 @@ def test_bks_rank8_device_newton(ctx):
 def test_bks_rank8_device_newton_on_dirty_memory(precision):
     """The same solve (plain FP64, and mixed: FP32 products on the matrix
     cores) in a new ctx after 4 GiB of device memory was filled
-    with NaN and handed back to the driver, so that fresh allocations are
+    with NaN and returned to the HIP runtime, so that fresh allocations are
     likely to hold NaN: every device buffer the solve reads must have been
     written by it first (a freshly mapped allocation reads as zeros and would
     hide such a read).  The device-side ones vectors (the Newton shift and
