@@ -1,5 +1,6 @@
 """Full-size BKS solves in the bench's configurations, checked by properties
-that hold at any size (the oracle cannot solve these in test time).
+that hold at any size, and at C2 also against the oracle's own solve (the
+oracle cannot solve the C3 shape in test time).
 
 C2-shaped planted tensor (20000 x 20000 x 2000, 2e6 stored; rank (5,5,5),
 BKS(2,4)) and C3-shaped planted tensor (200000 x 200000 x 10000, 5e7 stored;
@@ -78,3 +79,28 @@ def test_c3_planted_full(ctx):
     print("[fullsize] generating the planted C3-shaped tensor (5e7 stored)", flush=True)
     t, ref, mix = solve_pair(ctx, workloads.c3_planted(), 10)
     check_solve(t, ref, mix, 10, [8000.0 - 500.0 * x for x in range(10)], 9)
+
+
+def test_c2_planted_vs_oracle(ctx):
+    """The bench's C2 solve itself against the oracle: the oracle's FP64 BKS
+    solve of the whole C2-shaped planted tensor from the bench's start
+    (BKS(2,4), tolerance 1e-11; about a minute of CPU time) and the
+    mixed-precision GPU solve converge to U, W within a 1e-8 subspace angle
+    and to the same ||F|| within 1e-10."""
+    from oracle import bks as obks, sptensor
+    coo = workloads.c2_planted()
+    U0, W0 = workloads.random_start(coo.m, coo.n, 5, 5, 2024)
+    t = ctx.upload_coo(coo)
+    U, W, F, info, rc = ctx.solve(t, 5, 5, U0=U0, W0=W0, p=4, s=2, max_outer=200, tol=1e-11,
+                                  precision=bks.PREC_MIXED)
+    assert rc == 0 and info.converged, (rc, info.rel_grad)
+    print("[fullsize] oracle FP64 BKS solve of the C2-shaped tensor", flush=True)
+    T = sptensor.from_coo(coo.m, coo.n, coo.i, coo.j, coo.k, coo.val.astype(np.float64))
+    ref = obks.bks_solve(T, 5, 5, U0, W0, p=4, s=2, tol=1e-11, max_outer=200)
+    assert ref["converged"]
+    a = max(obks.subspace_distance(ref["U"], U), obks.subspace_distance(ref["W"], W))
+    nF, nref = float(np.linalg.norm(F)), float(np.linalg.norm(ref["F"]))
+    print(f"[fullsize] C2 mixed vs oracle: outer {info.outer_iters} / {ref.get('outer_iters')}, "
+          f"angle {a:.1e}, normF {nF:.12e} ref {nref:.12e}", flush=True)
+    assert a <= 1e-8, a
+    assert abs(nF - nref) <= 1e-10 * nref
