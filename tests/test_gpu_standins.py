@@ -62,26 +62,29 @@ def test_standin(ctx, name, r, r3):
           f"angle {a:.1e} normF {nF:.6e} HOOI {ih.normF:.6e} status {rch}", flush=True)
 
 
-@pytest.mark.parametrize("name,r,r3", [("p_reuters", 2, 2), ("p_darpa", 2, 2)])
-def test_standin_vs_oracle(ctx, name, r, r3):
+@pytest.mark.parametrize("name,r,r3,variant", [("p_reuters", 2, 2, "bk"), ("p_darpa", 2, 2, "bk"),
+                                                ("p_darpa", 2, 2, "min"), ("p_darpa", 2, 2, "max")])
+def test_standin_vs_oracle(ctx, name, r, r3, variant):
     """The mixed-precision GPU solve against the oracle's FP64 BKS solve of the
-    same stand-in from the same start (BKS(2,4), tolerance 1e-10): both
-    converge, U and W agree within a 1e-8 subspace angle and ||F|| to 1e-9.
+    same stand-in from the same start (BKS(2,4) with the Table 3 schedule,
+    and on the DARPA-shaped one also min-BK and max-BK of Tables 1-2;
+    tolerance 1e-10): both converge, U and W agree within a 1e-8 subspace
+    angle and ||F|| to 1e-9.
     (The Princeton stand-in needs about 45 outer iterations, 85 s of oracle
     time on one core, and is left to the GPU-only comparison above.)"""
     from oracle import bks as obks, sptensor
     coo = getattr(workloads, name)()
     T = sptensor.from_coo(coo.m, coo.n, coo.i, coo.j, coo.k, coo.val.astype(np.float64))
     U0, W0 = workloads.random_start(coo.m, coo.n, r, r3, 2024)
-    ref = obks.bks_solve(T, r, r3, U0, W0, p=4, s=2, tol=1e-10, max_outer=300)
+    ref = obks.bks_solve(T, r, r3, U0, W0, p=4, s=2, variant=variant, tol=1e-10, max_outer=300)
     assert ref["converged"]
     t = ctx.upload_coo(coo)
-    U, W, F, info, rc = ctx.solve(t, r, r3, U0=U0, W0=W0, p=4, s=2, max_outer=300, tol=1e-10,
-                                  precision=bks.PREC_MIXED)
+    U, W, F, info, rc = ctx.solve(t, r, r3, U0=U0, W0=W0, p=4, s=2, variant=variant,
+                                  max_outer=300, tol=1e-10, precision=bks.PREC_MIXED)
     assert rc == 0 and info.converged, (rc, info.rel_grad)
     a = max(obks.subspace_distance(ref["U"], U), obks.subspace_distance(ref["W"], W))
     nF, nref = float(np.linalg.norm(F)), float(np.linalg.norm(ref["F"]))
-    print(f"[standin-oracle] {name} ({r},{r},{r3}) outer gpu {info.outer_iters} oracle "
+    print(f"[standin-oracle] {name} ({r},{r},{r3}) {variant} outer gpu {info.outer_iters} oracle "
           f"{ref.get('outer_iters')} angle {a:.1e} normF {nF:.9e} ref {nref:.9e}", flush=True)
     assert a <= 1e-8, a
     assert abs(nF - nref) <= 1e-9 * nref
