@@ -51,10 +51,12 @@ def test_c4_small_requests_vs_oracle():
     print(f"[serving-oracle] largest angle {worst:.1e}", flush=True)
 
 
-def test_served_solves_on_dirty_memory():
-    """Four of those requests served by a new ctx after 4 GiB of device memory
-    was filled with NaN and handed back: the sessions' buffers are likely to
-    land on NaN, and every result must still match the oracle."""
+@pytest.mark.parametrize("precision", [bks.PREC_MIXED, bks.PREC_FP64])
+def test_served_solves_on_dirty_memory(precision):
+    """Four of those requests served (mixed precision, and plain FP64) by a
+    new ctx after 4 GiB of device memory was filled with NaN and returned to
+    the HIP runtime: the sessions' buffers are likely to land on NaN, and
+    every result must still match the oracle."""
     reqs = sorted((q for q in workloads.c4_requests(count=512, rate_per_s=1.0,
                                                     nnz_range=(10_000, 5_000_000))
                    if q.nnz <= 300_000), key=lambda q: q.nnz)[:4]
@@ -67,7 +69,7 @@ def test_served_solves_on_dirty_memory():
     ctx = bks.Ctx(0)
     srv = bks.Server(ctx, max_active=4, host_workers=4)
     try:
-        ids = [srv.submit(None, q.r, q.r, precision=bks.PREC_MIXED, U0=U0, W0=W0, coo=coo,
+        ids = [srv.submit(None, q.r, q.r, precision=precision, U0=U0, W0=W0, coo=coo,
                           tol=1e-11)
                for q, coo, (U0, W0) in zip(reqs, coos, starts)]
         got = []
@@ -83,5 +85,6 @@ def test_served_solves_on_dirty_memory():
         T = sptensor.from_coo(coo.m, coo.n, coo.i, coo.j, coo.k, coo.val.astype(np.float64))
         ref = obks.bks_solve(T, q.r, q.r, U0, W0, p=4, s=2, tol=1e-11)
         a = max(obks.subspace_distance(ref["U"], U), obks.subspace_distance(ref["W"], W))
-        print(f"[serving-dirty] request {q.rid} nnz={q.nnz} r={q.r} angle {a:.1e}", flush=True)
+        print(f"[serving-dirty] precision {precision} request {q.rid} nnz={q.nnz} r={q.r} "
+              f"angle {a:.1e}", flush=True)
         assert a <= 1e-8, (q.rid, a)
