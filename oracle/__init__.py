@@ -8,13 +8,13 @@ product path never does.  It shares no code with the HIP path.
 
 Modules
   sptensor : stored-entry representation, densification, norms
-  ttmc     : the three tensor-times-block contractions (Section 2.2)
+  ttmc     : the three tensor-times-block contractions (section "Multilinear tensor-matrix multiplication")
   orth     : order-preserving Gram-Schmidt with reorthogonalisation and
              deflation (Algorithm 3 steps (ii)-(iv), Appendix B)
   bk       : block-Krylov schedules (Tables 1-3) and the basis builder
   core     : dense projected problem: HOSVD, HOOI and Newton-Grassmann
-             (Algorithm 5 step (i), Section 5.2)
+             (Algorithm 5 step (i), section "Experiments")
   bks      : tensor Krylov-Schur driver, gradient and S-values
-             (Algorithm 5, Proposition 3.2, Section 2.6)
-  hooi     : sparse HOOI (Section 5.1)
+             (Algorithm 5, Proposition 3.2, section "Conditioning of the best approximation problem")
+  hooi     : sparse HOOI (section "Higher Order Orthogonal Iteration")
 """

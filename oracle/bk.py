@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-Two sequences of ON-blocks are built (Section 3.3.1): U-blocks for modes 1-2
+Two sequences of ON-blocks are built (section "Block-Krylov methods for (1,2)-symmetric tensors"): U-blocks for modes 1-2
 and W-blocks for mode 3.  A new U-block comes from A.(Ubar_a, Wbar_b)_{2,3}
 (Algorithm 3, mode 1); a new W-block from A.(Ubar_a, Ubar_b)_{1,2}, using the
 upper-triangular mode-3 unfolding (triunfold_3) when a = b.
@@ -19,8 +19,8 @@ Which block pairs are multiplied is the variant (Tables 1-3):
           of whole blocks available at the start of the stage.
 
 A bar means the first p columns of a block, except that U0 and W0 are always
-used whole (Section 3.3.2).  A mode stops growing once its basis reaches the
-mode size (Section 3.3.4).
+used whole (section "Min-BK method").  A mode stops growing once its basis reaches the
+mode size (section "BK method").
 """
 from __future__ import annotations
 

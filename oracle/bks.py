@@ -2,28 +2,28 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-Algorithm 5 (tensor Krylov-Schur) with U = V (Section 4, symmetric case):
+Algorithm 5 (tensor Krylov-Schur) with U = V (section "A Tensor Krylov-Schur like method", symmetric case):
 
   start  (U0, W0) orthonormal (the paper does not state the BKS start; here it
-         is the same seeded random start HOOI uses, Section 5.1)
+         is the same seeded random start HOOI uses, section "Higher Order Orthogonal Iteration")
   expand stages 1..s of a BK method to X = [U0 U1 ...], Z = [W0 W1 ...]
   loop
     (i)   best rank-(r, r, r3) approximation of C = A.(X, X, Z) (eq. tkd,
-          eq. maxrC) by HOSVD + 5 HOOI + Newton-Grassmann (Section 5.2)
+          eq. maxrC) by HOSVD + 5 HOOI + Newton-Grassmann (section "Experiments")
     (ii)  U0 = X P, W0 = Z S (eq. tks1)
     (iii) one BK step from (U0, W0): T1 = A.(U0, W0)_{2,3} and
           T3 = A.(U0, U0)_{1,2}, orthogonalised against U0, W0 -> U1, W1
     (iv)  G-gradient at (U0, W0) from that step (Proposition 3.2, Lemma 3.1):
           ||grad||^2 = 2 ||<H0, H1^1>_{-1}||^2 + ||<H0, H1^3>_{-3}||^2,
           modes 1 and 2 equal because U = V; stop at ||grad|| / ||F|| <= tol
-          (Section 5.2)
+          (section "Experiments")
     (v)   expand stages 2..s from ([U0 U1], [W0 W1])
 
 With H0 = F = U0^T T1 (as r x r x r3) and H1^1 = U1^T (I - U0 U0^T) T1 = R1,
 <H0, H1^1>_{-1} is R1 F_(1)^T; in mode 3, R3 = W1^T (I - W0 W0^T) T3 on the
 full (not sym-half) unfolding and <H0, H1^3>_{-3} = R3 F_(3)^T.
 
-S-values (Section 2.6): s_i^(k) = sqrt(lambda_i(<F, F>_{-k})) and
+S-values (section "Conditioning of the best approximation problem"): s_i^(k) = sqrt(lambda_i(<F, F>_{-k})) and
 s_{r_k+1}^(k) = sqrt(lambda_max(<F_perp^k, F_perp^k>_{-k})), which by
 Lemma 3.1 equals the largest singular value of R1 (resp. R3).
 """

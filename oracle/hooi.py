@@ -2,12 +2,12 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-Section 5.1: HOOI alternates maximisations.  For a (1,2)-symmetric tensor
+section "Higher Order Orthogonal Iteration": HOOI alternates maximisations.  For a (1,2)-symmetric tensor
 each iteration updates U as the r leading left singular vectors of
 C1 = A.(U, W)_{2,3} (mode-1 unfolding, using the previous U), then W as the
 r3 leading left singular vectors of C3 = A.(U, U)_{1,2} with the new U.  The
 start is random with orthonormal columns; the G-gradient (global
-coordinates, Section 2.5) is evaluated every ten iterations:
+coordinates, section "Gradient on the product manifold") is evaluated every ten iterations:
 
   Gamma1 = <A.(U, W)_{2,3}, F>_{-1} = T1 F_(1)^T,   grad_U = (I - U U^T) Gamma1
   Gamma3 = T3 F_(3)^T,                              grad_W = (I - W W^T) Gamma3

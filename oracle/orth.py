@@ -9,7 +9,7 @@ done column by column, in column order, with classical Gram-Schmidt against
 every previous column (the existing basis and the new columns kept so far),
 applied twice (reorthogonalisation).
 
-Deflation (the paper only caps the basis at the mode size, Section 3.3.4;
+Deflation (the paper only caps the basis at the mode size, section "BK method";
 this rule is a reading): column b is dropped when the norm left after
 orthogonalisation is at most ``tau`` times ||b||, or when the basis already
 spans the whole space.  The barred block U(:, 1:p) means the first p kept

@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 A (1,2)-symmetric A in R^{m x m x n} satisfies A(i,j,k) = A(j,i,k)
-(Definition in Section 2.1).  The oracle keeps the distinct positions
+(Definition in section "Notation").  The oracle keeps the distinct positions
 (i <= j, k) and their values in FP64; the entry at (j, i, k) is implied.
 """
 from __future__ import annotations
@@ -79,6 +79,6 @@ def from_dense(A: np.ndarray) -> SymTensor:
 
 def frob2(T: SymTensor) -> float:
     """||A||^2 over the full tensor: off-diagonal stored entries count twice
-    (inner product and norm, Section 2.3)."""
+    (inner product and norm, section "Inner product and norm, contractions")."""
     w = np.where(T.i == T.j, 1.0, 2.0)
     return float(np.sum(w * T.a * T.a))

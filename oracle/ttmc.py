@@ -2,8 +2,8 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-Definitions (Section 2.2, mode-i and multilinear products; Section 3.3 block
-steps; Section 3.3.1 for the (1,2)-symmetric case).  With the transposed
+Definitions (section "Multilinear tensor-matrix multiplication", mode-i and multilinear products; section "Block-Krylov methods" block
+steps; section "Block-Krylov methods for (1,2)-symmetric tensors" for the (1,2)-symmetric case).  With the transposed
 notation A.(X, Y)_{1,2} = (X^T, Y^T)_{1,2} . A:
 
   FREE3   T3 = A.(X, Y)_{1,2} in R^{px x py x n}
@@ -17,7 +17,7 @@ Each is evaluated as a plain sum over the stored entries (i <= j, k, a) and
 their mirrors (j, i, k, a) for i != j.
 
 Unfolding convention (the paper leaves the column order of unfold_i and
-triunfold_3 open, Section 2.4 and Section 3.3.1): Matlab column-major, first
+triunfold_3 open, section "Multilinear rank" and section "Block-Krylov methods for (1,2)-symmetric tensors"): Matlab column-major, first
 remaining index fastest.
   FREE3 (X != Y):  row k, column a + px*b            (n x px*py)
   FREE3 sym-half:  row k, column b*(b+1)/2 + a, a<=b (n x p(p+1)/2),

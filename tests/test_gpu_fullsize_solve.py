@@ -8,7 +8,7 @@ rank (10,10,10)), both from the bench's seeded start:
 - the mixed-precision solve converges to a relative G-gradient <= 1e-11 and
   its U, W lie within a 1e-8 subspace angle of the plain FP64 GPU solve's
   (the precision target);
-- the S-values (Section 2.6) are the singular values of F_(1) and F_(3), so
+- the S-values (section "Conditioning of the best approximation problem") are the singular values of F_(1) and F_(3), so
   sum_i s_i^2 = ||F||^2 in both modes, and ||F|| <= ||A||;
 - the planted core is recovered: ||F||^2 is at least the plant's energy,
   s_{r+1} is far below s_r, and the S-values of the planted components that

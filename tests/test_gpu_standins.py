@@ -1,12 +1,12 @@
-"""BKS on seeded stand-ins for the paper's data sets (Section 5.2, Examples
+"""BKS on seeded stand-ins for the paper's data sets (section "Experiments", Examples
 2-4; the data sets themselves are not used): Princeton-, Reuters- and
 DARPA-shaped tensors at the ranks the paper uses for them.
 
 On each, the plain FP64 GPU solve and the mixed-precision solve (BKS(2,4),
 same seeded start, tolerance 1e-10 on the relative G-gradient) both
 converge, agree within a 1e-8 subspace angle (the precision target) and in
-||F|| to 1e-9, and satisfy sum_i s_i^2 = ||F||^2 in both modes (Section 2.6)
-and ||F|| <= ||A||.  HOOI (Section 5.1) from the same start is run beside
+||F|| to 1e-9, and satisfy sum_i s_i^2 = ||F||^2 in both modes (section "Conditioning of the best approximation problem")
+and ||F|| <= ||A||.  HOOI (section "Higher Order Orthogonal Iteration") from the same start is run beside
 them and never ends above BKS (on the Reuters stand-in it stalls at a lower
 objective, the starting-point sensitivity the paper reports)."""
 import numpy as np
@@ -91,7 +91,7 @@ def test_standin_vs_oracle(ctx, name, r, r3, variant):
 
 
 def test_hooi_standin_vs_oracle(ctx):
-    """Symmetric HOOI (Section 5.1) on the DARPA-shaped stand-in at rank
+    """Symmetric HOOI (section "Higher Order Orthogonal Iteration") on the DARPA-shaped stand-in at rank
     (2,2,2), FP64 and mixed precision on the GPU, against the oracle's HOOI
     from the same start (tolerance 1e-10; the oracle needs ~30 iterations,
     about 20 s): all converge, U and W agree within 1e-8 and ||F|| to 1e-10."""

@@ -1,7 +1,7 @@
 """Pins for the oracle's block-Krylov basis builder: the basis dimensions the
-paper prints (Tables 1-3 and the method labels of Section 5.2), Lemma 3.1
+paper prints (Tables 1-3 and the method labels of section "Experiments"), Lemma 3.1
 (the Rayleigh-quotient structure), orthonormality, deflation and the mode-size
-cap (Section 3.3.4)."""
+cap (section "BK method")."""
 import json
 import os
 
@@ -74,7 +74,7 @@ def test_rayleigh_structure_lemma():
 
 
 def test_mode_size_cap():
-    """Once k3 reaches n the W-expansion stops (Section 3.3.4)."""
+    """Once k3 reaches n the W-expansion stops (section "BK method")."""
     T = small_tensor(7, m=30, n=4, nnz=400)
     basis = build(T, 2, 2, 4, 2)
     assert basis.Z.shape[1] == T.n

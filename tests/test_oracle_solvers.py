@@ -1,10 +1,10 @@
-"""Pins for the oracle's solvers (Algorithm 5, Section 5.1 HOOI, the inner
+"""Pins for the oracle's solvers (Algorithm 5, section "Higher Order Orthogonal Iteration" HOOI, the inner
 Newton-Grassmann solve): closed forms (n = 1 and rank-1-in-mode-3 reduce to a
 symmetric eigenproblem), exact recovery of a planted tensor, the Pythagoras
-identity behind eq. Rayleigh, local = global gradient (Section 2.5 and
-Proposition 3.2), the S-value identity (Section 2.6, Lemma 3.1), the
+identity behind eq. Rayleigh, local = global gradient (section "Gradient on the product manifold" and
+Proposition 3.2), the S-value identity (section "Conditioning of the best approximation problem", Lemma 3.1), the
 non-decreasing objective (eq. Fnon-decr), BKS = HOOI on a well-conditioned
-problem (Section 5.2.1) and the Newton model against finite differences."""
+problem (Example 1 of the Experiments section) and the Newton model against finite differences."""
 import numpy as np
 import pytest
 
@@ -129,7 +129,7 @@ def test_monotone_objective_bounded_by_norm():
 @pytest.mark.parametrize("rho", [1e-2, 1e-4])
 def test_bks_equals_hooi_well_conditioned(rho):
     """Example-1-like signal plus noise: BKS and HOOI reach the same subspaces
-    (Section 5.2.1 compares the solutions by their subspace angles)."""
+    (Example 1 of the Experiments section compares the solutions by their subspace angles)."""
     c = workloads.dense_signal_noise(40, 40, 2, 2, rho, seed=3)
     T = to_T(c)
     U_init, W_init = workloads.random_start(40, 40, 2, 2, 5)

@@ -1,6 +1,6 @@
-"""Pins for the oracle's contractions (Section 2.2): dense brute force on tiny
+"""Pins for the oracle's contractions (section "Multilinear tensor-matrix multiplication"): dense brute force on tiny
 tensors, (1,2)-symmetry of every product, the cross-kernel identity, norm
-invariance under orthogonal transforms (Section 2.3) and the p = 1 vector
+invariance under orthogonal transforms (section "Inner product and norm, contractions") and the p = 1 vector
 case (tensor-times-vector products of the minimal Krylov recursion)."""
 import numpy as np
 import pytest
@@ -97,7 +97,7 @@ def test_cross_kernel_identity():
 
 
 def test_norm_invariance_square_orthogonal():
-    """||A.(Q, Q, Q3)|| = ||A|| for square orthogonal Q, Q3 (Section 2.3)."""
+    """||A.(Q, Q, Q3)|| = ||A|| for square orthogonal Q, Q3 (section "Inner product and norm, contractions")."""
     T = tiny(17)
     rng = np.random.default_rng(2)
     Q = np.linalg.qr(rng.standard_normal((T.m, T.m)))[0]
