@@ -115,3 +115,35 @@ def test_every_inner_solve_of_a_bks_run_reaches_the_tolerance(variant, s):
         # quadratic convergence: a handful of steps (the paper reports 4-5
         # typical inner iterations), never the cap
         assert info["rel_grad"] <= 1e-13 and info["ng_iters"] <= 10, info
+
+
+def test_slice_scaling_closed_forms():
+    """Slice scalings (Examples 3 and 4) against closed forms: the complete
+    graph K_q times c has largest eigenvalue c (q - 1); a diagonal slice has
+    spectral radius max |d|; a rank-one slice u u^T has ||u||^2; the 2 x 2
+    slice [[a, b], [b, c]] has Frobenius norm sqrt(a^2 + 2 b^2 + c^2)."""
+    from oracle import preprocess, sptensor
+    m, q, c = 30, 7, 2.5
+    A = np.zeros((m, m, 4))
+    idx = np.arange(3, 3 + q)
+    A[np.ix_(idx, idx, [0])] = c
+    A[idx, idx, 0] = 0.0                       # K_q: no self loops
+    d = np.array([1.0, -4.0, 2.0])
+    A[[5, 9, 12], [5, 9, 12], 1] = d           # diagonal slice
+    u = np.zeros(m)
+    u[[2, 8, 20]] = [1.0, -2.0, 0.5]
+    A[:, :, 2] = np.outer(u, u)                # rank one
+    A[[0, 0, 1, 1], [0, 1, 0, 1], 3] = [1.5, -0.7, -0.7, 3.0]
+    T = sptensor.from_dense(A)
+    L = preprocess.scale_slices(T, "lambda_max")
+    F = preprocess.scale_slices(T, "frobenius")
+    want_l = [c * (q - 1), 4.0, u @ u, None]
+    for k, w in enumerate(want_l):
+        if w is None:
+            continue
+        np.testing.assert_allclose(L.a[L.k == k], T.a[T.k == k] / w, rtol=1e-13)
+    np.testing.assert_allclose(F.a[F.k == 3], T.a[T.k == 3] / np.sqrt(1.5 ** 2 + 2 * 0.7 ** 2 + 9.0),
+                               rtol=1e-14)
+    # every nonempty slice of the Frobenius-scaled tensor has norm 1, so
+    # ||A||^2 is the number of nonempty slices
+    assert abs(sptensor.frob2(F) - 4.0) <= 1e-13
