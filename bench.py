@@ -1,17 +1,23 @@
 #!/usr/bin/env python3
-"""Benchmark: served-style BKS solves on one MI355X.
+"""Benchmark: BKS solves on one MI355X.
 
 One step = one mixed-precision block Krylov-Schur solve (Algorithm 5,
-BKS(2,4; k1, k3), rank (5,5,5)) of the C2-shaped workload to the solver's
-tolerance, from a fixed seeded start, with the tensor already resident in
-HBM.  `value` = solves/s over the K timed steps; p50/p99 are per-solve
-latencies.  The roofline object reports the dominant tensor-product kernel
-class, timed live with HIP events on the stream it runs on.  The CPU
-baseline is the FP64 NumPy oracle's own BKS solve of the same workload and
-start, stopped after 3 outer iterations and scaled by the GPU's
-outer-iteration count.
+BKS(2,4; k1, k3), rank (5,5,5)) of the C2 law as printed (20000 x 20000 x
+2000, 2e6 stored, Zipf(1.3) modes 1-2, uniform mode 3, |N(0,1)| FP32) run
+to its stopping rule -- the tolerance or the outer-iteration cap -- from a
+fixed seeded start, with the tensor already resident in HBM.  `value` =
+solves/s over the K timed steps; p50/p99 are per-solve latencies.  Beside
+them: whether the solve converged, its angle to the plain FP64 GPU solve
+of the same start, and the relative S-value gaps that condition the
+subspaces.  The roofline object reports the dominant tensor-product kernel
+class, timed live with HIP events on the stream it runs on
+(`roofline_narrow` the dominant narrow product).  The `c2p` key reports the
+same shape with a planted rank-(5,5,5) part.  The CPU baseline is the FP64
+NumPy oracle's own BKS solve of the same workload and start, stopped after
+3 outer iterations and scaled by the GPU's outer-iteration count.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py --workload c5 --steps 1 --warmup 0   # the 2e8-entry tensor, rank 20
     python bench.py --ttmc-sweep      # C3-shaped product sweep (one JSON line per product)
     python bench.py --ablation        # block vs repeated one-column products
 """
@@ -56,10 +62,15 @@ WORKLOAD_TEXT = {
                  "indices, Zipf(2) integer weights",
     "p_darpa": "DARPA-shaped stand-in 8891x8891x371: 1e6 stored, Zipf(1.2) indices, binary, "
                "slices scaled to Frobenius norm 1",
+    "c5": "C5-shaped (1,2)-symmetric 1000000x1000000x500, 2e8 stored, Zipf(1.6) mode-1/2 degrees "
+          "(Chung-Lu law), uniform mode 3, |N(0,1)| FP32",
 }
-# the paper's ranks for its data sets (Section 5.2)
+WORKLOAD_GEN = {"c2p": "c2_planted", "c2": "c2", "c3": "c3", "c3p": "c3_planted",
+                "p_princeton": "p_princeton", "p_reuters": "p_reuters", "p_darpa": "p_darpa",
+                "c5": "c5"}
+# the paper's ranks for its data sets (section "Experiments")
 DEFAULT_RANK = {"c2p": 5, "c2": 5, "c3": 10, "c3p": 10, "p_princeton": 3, "p_reuters": 2,
-                "p_darpa": 2}
+                "p_darpa": 2, "c5": 20}
 
 
 def load_traffic(kernel_class, workload):
@@ -129,6 +140,41 @@ def roofline_of(stats, workload=None):
             "algorithmic_bytes_per_launch": by / calls, **extra}
 
 
+def host_cpu():
+    """(logical CPUs, model name) of this host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return os.cpu_count() or 1, model
+
+
+def cpu_baseline_b(coo, r, U0, W0, gpu_iters, outer=3):
+    """Baseline B: the oracle's BKS algorithm with C++/OpenMP FP64 products
+    and numpy's BLAS/LAPACK on all host cores, stopped after `outer` outer
+    iterations, scaled to a whole solve by the GPU solve's iterations."""
+    from baseline import cpu
+    from oracle import sptensor
+    T = sptensor.from_coo(coo.m, coo.n, coo.i, coo.j, coo.k, coo.val.astype(np.float64))
+    cpu.layouts(T)  # the sorted layouts are built once, outside the timing
+    t0 = time.perf_counter()
+    res = cpu.bks_solve(T, r, r, U0, W0, p=4, s=2, tol=1e-11, max_outer=outer)
+    dt = time.perf_counter() - t0
+    per_iter = dt / max(res["outer_iters"], 1)
+    ncpu, model = host_cpu()
+    return {"value": round(1.0 / (per_iter * max(gpu_iters, 1)), 6), "unit": "solves/s",
+            "cores": cpu.threads(), "kind": "cpp-openmp", "host_cpus": ncpu, "host_model": model,
+            "sample": f"the oracle's BKS(2,4) algorithm with C++/OpenMP FP64 products on "
+                      f"{cpu.threads()} threads, same workload and start, {res['outer_iters']} "
+                      f"outer iterations ({dt:.1f} s), scaled by the GPU solve's {gpu_iters} "
+                      f"outer iterations"}
+
+
 def cpu_baseline(coo, r, U0, W0, gpu_iters, outer=3):
     """The FP64 oracle's BKS solve on the same workload and start, stopped
     after `outer` outer iterations (about 10 s on one thread), scaled to a
@@ -146,58 +192,111 @@ def cpu_baseline(coo, r, U0, W0, gpu_iters, outer=3):
     if ctxm is not None:
         ctxm.unregister() if hasattr(ctxm, "unregister") else None
     per_iter = dt / max(res["outer_iters"], 1)
+    ncpu, model = host_cpu()
     return {"value": round(1.0 / (per_iter * max(gpu_iters, 1)), 6), "unit": "solves/s",
-            "cores": 1, "kind": "oracle",
+            "cores": 1, "kind": "oracle", "host_cpus": ncpu, "host_model": model,
             "sample": f"the FP64 NumPy oracle's BKS(2,4) solve of the same workload and start, "
                       f"{res['outer_iters']} outer iterations ({dt:.1f} s, 1 BLAS thread), "
                       f"scaled by the GPU solve's {gpu_iters} outer iterations"}
+
+
+def narrow_roofline(stats, workload):
+    """Roofline of the narrow product class (FREE3, FREE1, MODE3) that took
+    the most kernel time."""
+    narrow = {k: v for k, v in stats.items()
+              if not k.endswith("_call") and not k.startswith("free3_sym_wide")}
+    if not narrow:
+        return None
+    return roofline_of(narrow | {k + "_call": stats[k + "_call"] for k in narrow
+                                 if k + "_call" in stats}, workload)
+
+
+def s_gaps(info, r, r3):
+    """Relative S-value gaps (s_r - s_{r+1}) / s_1 of modes 1 and 3 (the
+    conditioning of the subspaces, section "Conditioning of the best
+    approximation problem")."""
+    s1, s3 = list(info.svals1[:r + 1]), list(info.svals3[:r3 + 1])
+    g1 = (s1[r - 1] - s1[r]) / s1[0] if s1[0] > 0 else 0.0
+    g3 = (s3[r3 - 1] - s3[r3]) / s3[0] if s3[0] > 0 else 0.0
+    return g1, g3
+
+
+def timed_solves(ctx, t, rank, precision, steps, kw):
+    import torch
+    lat, results = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a = time.perf_counter()
+        results.append(ctx.solve(t, rank, rank, precision=precision, **kw))
+        lat.append(time.perf_counter() - a)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, lat, results
+
+
+def solve_summary(elapsed, lat, results, ref, rank):
+    U, W, F, info, rc = results[0]
+    Ur, Wr, Fr, info_r, rc_r = ref
+    g1, g3 = s_gaps(info_r, rank, rank)
+    au, aw = dist(Ur, U), dist(Wr, W)
+    conv = bool(info.converged) and bool(info_r.converged)
+    return {
+        "value": round(len(lat) / elapsed, 4),
+        "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 2),
+        "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 2),
+        "converged": bool(info.converged), "outer_iters": info.outer_iters,
+        "rel_grad": info.rel_grad,
+        "angle_U_vs_fp64": au, "angle_W_vs_fp64": aw,
+        "fp64_converged": bool(info_r.converged), "fp64_outer_iters": info_r.outer_iters,
+        "fp64_rel_grad": info_r.rel_grad,
+        "rel_gap_mode1": g1, "rel_gap_mode3": g3,
+        # SURVEY-style reading of the paper's conditioning: parity is claimed
+        # for converged solves on subspaces whose relative S-value gap is at
+        # least 1e-3; otherwise the gaps are reported beside the angle
+        "parity": ("pinned" if conv and max(au, aw) <= 1e-8 and min(g1, g3) >= 1e-3 else
+                   "not converged in max_outer" if not conv else
+                   "unpinned (ill-conditioned)" if min(g1, g3) < 1e-3 else "angle above 1e-8"),
+    }
 
 
 def run_bks(args):
     import torch
     rank = args.rank if args.rank else DEFAULT_RANK[args.workload]
     t_gen = time.perf_counter()
-    coo = {"c2p": workloads.c2_planted, "c2": workloads.c2, "c3": workloads.c3,
-           "c3p": workloads.c3_planted, "p_princeton": workloads.p_princeton,
-           "p_reuters": workloads.p_reuters, "p_darpa": workloads.p_darpa}[args.workload]()
+    coo = getattr(workloads, WORKLOAD_GEN[args.workload])()
     U0, W0 = workloads.random_start(coo.m, coo.n, rank, rank, 2024)
     t_gen = time.perf_counter() - t_gen
     assert torch.cuda.is_available(), "bench needs a GPU"
     ctx = bks.Ctx(0)
+    t_up = time.perf_counter()
     t = ctx.upload_coo(coo)
-    kw = dict(U0=U0, W0=W0, p=4, s=2, max_outer=args.max_outer, tol=1e-11)
-    # plain FP64 GPU solve: accuracy reference; then the comparison throughput
-    # from warm FP64 solves
-    Ur, Wr, Fr, info_r, rc_r = ctx.solve(t, rank, rank, precision=bks.PREC_FP64, **kw)
-    n64 = max(1, min(args.steps, 3))
-    torch.cuda.synchronize()
+    t_up = time.perf_counter() - t_up
+    big = args.workload == "c5"
+    max_outer = args.max_outer if args.max_outer else (4 if big else 200)
+    kw = dict(U0=U0, W0=W0, p=4, s=2, max_outer=max_outer, tol=1e-11)
+    # plain FP64 GPU solve: the accuracy reference, then the comparison
+    # throughput from warm FP64 solves
     a = time.perf_counter()
-    for _ in range(n64):
-        ctx.solve(t, rank, rank, precision=bks.PREC_FP64, **kw)
+    ref = ctx.solve(t, rank, rank, precision=bks.PREC_FP64, **kw)
     torch.cuda.synchronize()
-    fp64_s = (time.perf_counter() - a) / n64
+    ref_s = time.perf_counter() - a
+    n64 = 0 if big else max(1, min(args.steps, 2))
+    fp64_s = ref_s
+    if n64:
+        el, _, _ = timed_solves(ctx, t, rank, bks.PREC_FP64, n64, kw)
+        fp64_s = el / n64
     for _ in range(args.warmup):
         ctx.solve(t, rank, rank, precision=bks.PREC_MIXED, **kw)
     torch.cuda.synchronize()
     ctx.profile(True)
-    lat = []
-    results = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        a = time.perf_counter()
-        res = ctx.solve(t, rank, rank, precision=bks.PREC_MIXED, **kw)
-        lat.append(time.perf_counter() - a)
-        results.append(res)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    elapsed, lat, results = timed_solves(ctx, t, rank, bks.PREC_MIXED, args.steps, kw)
     stats = ctx.profile_read()
     ctx.profile(False)
+    summ = solve_summary(elapsed, lat, results, ref, rank)
     U, W, F, info, rc = results[0]
-    iters = info.outer_iters
     out = {
         "metric": "BKS solves/s + p50/p99 latency at 1e-8 subspace angle; TTMc HBM GB/s vs peak",
-        "value": round(args.steps / elapsed, 4),
+        "value": summ.pop("value"),
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -213,17 +312,9 @@ def run_bks(args):
         "config": {
             "workload": WORKLOAD_TEXT[args.workload],
             "rank": [rank, rank, rank], "method": f"BKS(2,4;{info.k1},{info.k3})",
-            "precision": "mixed", "tol": 1e-11, "max_outer": args.max_outer,
+            "precision": "mixed", "tol": 1e-11, "max_outer": max_outer,
         },
-        "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 2),
-        "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 2),
-        "converged": bool(info.converged),
-        "outer_iters": iters,
-        "rel_grad": info.rel_grad,
-        "angle_U_vs_fp64": dist(Ur, U),
-        "angle_W_vs_fp64": dist(Wr, W),
-        "fp64_converged": bool(info_r.converged),
-        "fp64_outer_iters": info_r.outer_iters,
+        **summ,
         "fp64_solves_per_s": round(1.0 / fp64_s, 4),
         "phase_s": {"expand": round(info.t_expand, 4), "core": round(info.t_core, 4),
                     "inner_host": round(info.t_inner, 4), "bk_step": round(info.t_step, 4)},
@@ -231,12 +322,25 @@ def run_bks(args):
         "svals3": list(np.round(info.svals3[:rank + 1], 4)),
         "kernels": {k: {"calls": v[0], "ms": round(v[1], 3)} for k, v in stats.items()},
         "roofline": roofline_of(stats, workload=args.workload),
+        "roofline_narrow": narrow_roofline(stats, args.workload),
         "gen_s": round(t_gen, 2),
+        "upload_s": round(t_up, 2),
     }
+    if args.workload == "c2" and not args.no_extra:
+        # the same law with a planted rank-(5,5,5) part: a well-conditioned
+        # solve of the C2 shape (reported beside the headline, not as it)
+        cp = workloads.c2_planted()
+        tp = ctx.upload_coo(cp)
+        refp = ctx.solve(tp, rank, rank, precision=bks.PREC_FP64, **kw)
+        ctx.solve(tp, rank, rank, precision=bks.PREC_MIXED, **kw)
+        el, latp, resp = timed_solves(ctx, tp, rank, bks.PREC_MIXED, max(args.steps, 5), kw)
+        out["c2p"] = {"workload": WORKLOAD_TEXT["c2p"], **solve_summary(el, latp, resp, refp, rank)}
+        tp.free()
     if args.copy_ref_mb:
         copy_reference(args.copy_ref_mb)
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(coo, rank, U0, W0, iters)
+    if not args.no_cpu and not big:
+        out["cpu_baseline"] = cpu_baseline(coo, rank, U0, W0, info.outer_iters)
+        out["cpu_baseline_b"] = cpu_baseline_b(coo, rank, U0, W0, info.outer_iters)
     print(json.dumps(out), flush=True)
 
 
@@ -320,7 +424,7 @@ def ttmc_sweep(args):
 
 def ablation(args):
     """Block products against repeated single-vector products (the paper's
-    3-9x claim for 6 vectors, Section 3.3): on two tensors of the paper's
+    3-9x claim for 6 vectors, section "Block-Krylov methods"): on two tensors of the paper's
     stated sizes, each block product and the equivalent sequence of
     one-column products, timed with HIP events (one JSON line each)."""
     import torch
@@ -485,10 +589,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=sorted(WORKLOAD_TEXT), default="c2p")
+    ap.add_argument("--workload", choices=sorted(WORKLOAD_TEXT), default="c2")
     ap.add_argument("--rank", type=int, default=0)
-    ap.add_argument("--max-outer", type=int, default=200)
+    ap.add_argument("--max-outer", type=int, default=0,
+                    help="outer iteration cap (default 200; 4 for c5)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the planted C2 variant reported beside the C2 line")
     ap.add_argument("--ttmc-sweep", action="store_true")
     ap.add_argument("--widths", type=int, nargs="*", default=[5, 10, 20])
     ap.add_argument("--ops", nargs="*", default=None,

@@ -16,10 +16,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libbks.so")
 
 OK, EINVAL, EINDEX, EVALUE, EASYM, ENOMEM, EDEVICE, ENOTFOUND, EDUP = 0, -1, -2, -3, -4, -5, -6, -7, -8
+ECANCELED = -9
 ENOTCONV = 1
 F32, F64, F32IN_F64ACC = 0, 1, 2
 FREE3, FREE1, MODE3 = 0, 1, 2
 DEVICE_PTRS, SUM_DUPLICATES, FULL_SYMMETRIC = 1, 2, 4
+SCALE_FROBENIUS, SCALE_LAMBDA_MAX = 8, 16
 VARIANT = {"bk": 0, "min": 1, "max": 2}
 PREC_FP64, PREC_MIXED = 0, 1
 
@@ -28,8 +30,9 @@ SYMBOLS = [
     "bks_ctx_profile", "bks_ctx_profile_read",
     "bks_tensor_upload", "bks_tensor_info", "bks_tensor_pairs", "bks_tensor_free",
     "bks_ttmc", "bks_solve", "hooi_solve",
+    "bks_gtensor_upload", "bks_gttmc", "bks_gsolve",
     "bks_server_create", "bks_server_submit", "bks_server_submit_coo", "bks_server_poll",
-    "bks_server_wait", "bks_server_now", "bks_server_destroy",
+    "bks_server_wait", "bks_server_cancel", "bks_server_now", "bks_server_destroy",
 ]
 
 
@@ -59,7 +62,15 @@ class Info(C.Structure):
                 ("normA", C.c_double), ("svals1", C.c_double * 65), ("svals3", C.c_double * 65),
                 ("t_expand", C.c_double), ("t_core", C.c_double), ("t_inner", C.c_double),
                 ("t_step", C.c_double), ("t_total", C.c_double), ("n_hist", C.c_int),
-                ("rel_hist", C.c_double * 512), ("normF_hist", C.c_double * 512)]
+                ("rel_hist", C.c_double * 512), ("normF_hist", C.c_double * 512),
+                ("svals2", C.c_double * 65)]
+
+
+class GParams(C.Structure):
+    _fields_ = [("r1", C.c_int), ("r2", C.c_int), ("r3", C.c_int), ("s", C.c_int), ("p", C.c_int),
+                ("precision", C.c_int), ("tol", C.c_double), ("inner_tol", C.c_double),
+                ("max_outer", C.c_int), ("U0", C.c_void_p), ("V0", C.c_void_p),
+                ("W0", C.c_void_p), ("seed", C.c_uint64)]
 
 
 class ServerParams(C.Structure):
@@ -69,7 +80,12 @@ class ServerParams(C.Structure):
 
 class Result(C.Structure):
     _fields_ = [("status", C.c_int), ("done", C.c_int), ("t_submit", C.c_double),
-                ("t_start", C.c_double), ("t_end", C.c_double), ("info", Info)]
+                ("t_start", C.c_double), ("t_end", C.c_double), ("info", Info),
+                ("footprint", C.c_size_t), ("dev_peak", C.c_size_t), ("_error", C.c_char * 160)]
+
+    @property
+    def error(self):
+        return self._error.decode(errors="replace")
 
 
 _lib = None
@@ -103,6 +119,11 @@ def load(path: str = LIBPATH):
     lib.bks_tensor_free.restype = None
     lib.bks_ttmc.argtypes = [vp, vp, C.c_int, vp, i64, C.c_int, vp, i64, C.c_int, C.c_int,
                              C.c_int, vp, i64, vp]
+    lib.bks_gtensor_upload.argtypes = [vp, i64, i64, i64, i64, vp, vp, vp, vp, C.c_int, C.c_uint,
+                                       C.POINTER(vp)]
+    lib.bks_gttmc.argtypes = [vp, vp, C.c_int, vp, i64, C.c_int, vp, i64, C.c_int, C.c_int, vp,
+                              i64, vp]
+    lib.bks_gsolve.argtypes = [vp, vp, C.POINTER(GParams), vp, vp, vp, vp, C.POINTER(Info)]
     lib.bks_solve.argtypes = [vp, vp, C.POINTER(Params), vp, vp, vp, C.POINTER(Info)]
     lib.hooi_solve.argtypes = [vp, vp, C.POINTER(HooiParams), vp, vp, vp, C.POINTER(Info)]
     lib.bks_server_create.argtypes = [vp, C.POINTER(ServerParams), C.POINTER(vp)]
@@ -111,6 +132,7 @@ def load(path: str = LIBPATH):
                                           vp, vp, vp, C.POINTER(C.c_uint64)]
     lib.bks_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(Result)]
     lib.bks_server_wait.argtypes = [vp, C.c_uint64, C.POINTER(Result)]
+    lib.bks_server_cancel.argtypes = [vp, C.c_uint64]
     lib.bks_server_now.argtypes = [vp]
     lib.bks_server_now.restype = C.c_double
     lib.bks_server_destroy.argtypes = [vp]
@@ -221,14 +243,109 @@ class Ctx:
         return self.upload(coo.m, coo.n, coo.i, coo.j, coo.k, coo.val, flags)
 
     def ttmc(self, t, op, B1, B2, out, sym_half=False, prec=F32, stream=None):
-        """out <- product; B1, B2, out are 2-D row-major device tensors."""
+        """out <- product; B1, B2, out are 2-D row-major device tensors (rows
+        with unit stride).  The shapes and dtypes are checked here against the
+        tensor and the precision (ValueError), since the library sees raw
+        pointers.  stream: a hipStream_t value; None means torch's current
+        stream on out's device."""
+        esz = 4 if prec == F32 else 8
+        want_rows = {FREE3: (t.m, t.m, t.n), FREE1: (t.m, t.n, t.m),
+                     MODE3: (None, t.n, t.npairs)}
+        if op not in want_rows:
+            raise ValueError(f"unknown op {op}")
+        r1, r2, ro = want_rows[op]
+        for name, a, rows in (("B1", B1, r1), ("B2", B2, r2), ("out", out, ro)):
+            if a is None:
+                continue
+            if not getattr(a, "is_cuda", False):
+                raise ValueError(f"{name} must be a device tensor")
+            if a.dim() != 2 or a.stride(1) != 1 or a.stride(0) < a.shape[1]:
+                raise ValueError(f"{name} must be 2-D with unit column stride")
+            if not a.is_floating_point() or a.element_size() != esz:
+                raise ValueError(f"{name} must be float{8 * esz} for precision {prec}")
+            if rows is not None and a.shape[0] != rows:
+                raise ValueError(f"{name} has {a.shape[0]} rows, the product needs {rows}")
+        if out is None or (op != MODE3 and B1 is None) or (op in (FREE1, MODE3) and B2 is None):
+            raise ValueError("missing operand")
         p1 = B1.shape[1] if B1 is not None else 0
         ld1 = B1.stride(0) if B1 is not None else 0
         p2 = B2.shape[1] if B2 is not None else 0
         ld2 = B2.stride(0) if B2 is not None else 0
+        if op == FREE3:
+            q = p1 * (p1 + 1) // 2 if sym_half else p1 * (p2 if B2 is not None else p1)
+        else:
+            q = p1 * p2 if op == FREE1 else p2
+        if out.shape[1] < q:
+            raise ValueError(f"out has {out.shape[1]} columns, the product writes {q}")
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream(out.device).cuda_stream
         s = C.c_void_p(stream) if stream else None
         self.check(self.lib.bks_ttmc(self.h, t.h, op, _ptr(B1), ld1, p1, _ptr(B2), ld2, p2,
-                                     1 if sym_half else 0, prec, _ptr(out), out.stride(0), s))
+                      1 if sym_half else 0, prec, _ptr(out), out.stride(0), s))
+
+    def upload_general(self, l, m, n, i, j, k, val, flags=0):
+        """bks_gtensor_upload from host arrays (int32 coordinates, float32 or
+        float64 values); returns a Tensor with dims (l, m, n)."""
+        i = np.ascontiguousarray(i, dtype=np.int32)
+        j = np.ascontiguousarray(j, dtype=np.int32)
+        k = np.ascontiguousarray(k, dtype=np.int32)
+        val = np.ascontiguousarray(val)
+        dt = F64 if val.dtype == np.float64 else F32
+        if dt == F32:
+            val = np.ascontiguousarray(val, dtype=np.float32)
+        h = C.c_void_p()
+        self.check(self.lib.bks_gtensor_upload(self.h, l, m, n, int(i.shape[0]), _ptr(i), _ptr(j),
+                                               _ptr(k), _ptr(val), dt, flags, C.byref(h)))
+        t = self._track(Tensor(self, h))
+        t.dims = (l, m, n)
+        return t
+
+    def gttmc(self, t, mode, B1, B2, out, prec=F32, stream=None):
+        """bks_gttmc: product of a general tensor with free mode `mode` (0, 1,
+        2); B1, B2 the factors of the other two modes in mode order."""
+        esz = 4 if prec == F32 else 8
+        l, m, n = t.dims
+        rows = {0: (m, n, l), 1: (l, n, m), 2: (l, m, n)}
+        if mode not in rows:
+            raise ValueError(f"mode must be 0, 1 or 2, not {mode}")
+        for name, a, nr in zip(("B1", "B2", "out"), (B1, B2, out), rows[mode]):
+            if not getattr(a, "is_cuda", False) or a.dim() != 2 or a.stride(1) != 1:
+                raise ValueError(f"{name} must be a 2-D device tensor with unit column stride")
+            if not a.is_floating_point() or a.element_size() != esz:
+                raise ValueError(f"{name} must be float{8 * esz} for precision {prec}")
+            if a.shape[0] != nr:
+                raise ValueError(f"{name} has {a.shape[0]} rows, the product needs {nr}")
+        if out.shape[1] < B1.shape[1] * B2.shape[1]:
+            raise ValueError("out is narrower than the product")
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream(out.device).cuda_stream
+        s = C.c_void_p(stream) if stream else None
+        self.check(self.lib.bks_gttmc(self.h, t.h, mode, _ptr(B1), B1.stride(0), B1.shape[1],
+                                      _ptr(B2), B2.stride(0), B2.shape[1], prec, _ptr(out),
+                                      out.stride(0), s))
+
+    def gsolve(self, t, r, U0=None, V0=None, W0=None, p=4, s=2, precision=PREC_FP64, tol=0.0,
+               inner_tol=0.0, max_outer=0, seed=0):
+        """bks_gsolve: returns (U, V, W, F, info, status); r = (r1, r2, r3)."""
+        l, m, n = t.dims
+        prm = GParams(r[0], r[1], r[2], s, p, precision, tol, inner_tol, max_outer, None, None,
+                      None, seed)
+        keep = []
+        for name, X in (("U0", U0), ("V0", V0), ("W0", W0)):
+            if X is not None:
+                a = np.asfortranarray(X, dtype=np.float64)
+                keep.append(a)
+                setattr(prm, name, a.ctypes.data)
+        U = np.zeros((l, r[0]), order="F")
+        V = np.zeros((m, r[1]), order="F")
+        W = np.zeros((n, r[2]), order="F")
+        F = np.zeros(tuple(r), order="F")
+        info = Info()
+        rc = self.check(self.lib.bks_gsolve(self.h, t.h, C.byref(prm), _ptr(U), _ptr(V), _ptr(W),
+                                            _ptr(F), C.byref(info)))
+        return U, V, W, F, info, rc
 
     def solve(self, t, r, r3, U0=None, W0=None, p=4, s=2, variant="bk", precision=PREC_FP64,
               tol=0.0, inner_tol=0.0, max_outer=0, hooi_warm=-1, ng_max=0, seed=0,
@@ -319,7 +436,8 @@ class Server:
                                                 _ptr(F), C.byref(rid))
         if rc != OK:
             raise BksError(rc, "submit refused")
-        self._out[rid.value] = (U, W, F, keep)
+        # the tensor must outlive the request: hold it with the outputs
+        self._out[rid.value] = (U, W, F, (keep, t))
         return rid.value
 
     def poll(self, rid):
@@ -333,6 +451,11 @@ class Server:
         self.ctx.check(self.lib.bks_server_wait(self.h, rid, C.byref(res)))
         U, W, F, _ = self._out.pop(rid)
         return U, W, F, res
+
+    def cancel(self, rid):
+        """bks_server_cancel: returns the status code (0 taken or pending,
+        ENOTFOUND, EINVAL if the request had finished)."""
+        return self.lib.bks_server_cancel(self.h, rid)
 
     def now(self):
         return self.lib.bks_server_now(self.h)

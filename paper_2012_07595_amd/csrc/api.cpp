@@ -16,6 +16,15 @@ void check_hip(hipError_t e, const char *what) {
     fail(BKS_EDEVICE, std::string(hipGetErrorString(e)) + " in " + what);
 }
 
+thread_local std::shared_ptr<DevAccount> DevAccount::current;
+
+void DevAccount::add(size_t b) {
+    const size_t now = live.fetch_add(b) + b;
+    size_t p = peak.load();
+    while (now > p && !peak.compare_exchange_weak(p, now)) {
+    }
+}
+
 DevBuf::~DevBuf() { release(); }
 
 void DevBuf::alloc(size_t b) {
@@ -34,6 +43,8 @@ void DevBuf::alloc(size_t b) {
         fail(BKS_ENOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed");
     }
     bytes = b;
+    acct = DevAccount::current;
+    if (acct) acct->add(b);
 }
 
 void DevBuf::ensure(size_t b) {
@@ -43,8 +54,10 @@ void DevBuf::ensure(size_t b) {
 
 void DevBuf::release() {
     if (ptr) (void)hipFree(ptr);
+    if (ptr && acct) acct->sub(bytes);
     ptr = nullptr;
     bytes = 0;
+    acct.reset();
 }
 
 PinnedBuf::~PinnedBuf() {
@@ -67,6 +80,13 @@ void PinnedBuf::ensure(size_t b) {
     }
     ptr = static_cast<char *>(q);
     bytes = b;
+}
+
+void Ctx::release_workspaces() {
+    for (DevBuf *b : {&ws_partial, &ws_pack1, &ws_pack2, &ws_fac1, &ws_fac2, &devsolve.dH,
+                      &devsolve.dA, &devsolve.db, &devsolve.dones, &devinner.dC, &devinner.dA,
+                      &devinner.dOut, &devinner.dT, &devinner.dY, &devinner.dOnes})
+        b->release();
 }
 
 }  // namespace bks
@@ -193,10 +213,11 @@ int bks_tensor_upload(bks_ctx ctx, int64_t m, int64_t n, int64_t nnz, const int3
 int bks_tensor_info(bks_tensor t, int64_t *m, int64_t *n, int64_t *nnz_stored, int64_t *npairs,
                     double *frob_norm, size_t *dev_bytes) {
     if (!t) return BKS_EINVAL;
-    if (m) *m = t->m;
+    // a general tensor reports its mode-1 size as m and its mode-2 size as npairs
+    if (m) *m = t->general ? t->l : t->m;
     if (n) *n = t->n;
     if (nnz_stored) *nnz_stored = t->nnz;
-    if (npairs) *npairs = t->npairs;
+    if (npairs) *npairs = t->general ? t->m : t->npairs;
     if (frob_norm) *frob_norm = std::sqrt(t->frob2);
     if (dev_bytes) *dev_bytes = t->dev_bytes;
     return BKS_OK;
@@ -262,6 +283,74 @@ int bks_ttmc(bks_ctx ctx, bks_tensor t, int op, const void *B1, int64_t ld1, int
         HIPCHECK(hipSetDevice(ctx->device));
         ttmc(*ctx, *t, op, B1, ld1, p1, B2, ld2, p2, sym_half != 0, prec, out, ldo,
              static_cast<hipStream_t>(stream));
+    });
+}
+
+int bks_gtensor_upload(bks_ctx ctx, int64_t l, int64_t m, int64_t n, int64_t nnz,
+                       const int32_t *i, const int32_t *j, const int32_t *k, const void *val,
+                       int val_dtype, unsigned flags, bks_tensor *out) {
+    if (!ctx || !out) return BKS_EINVAL;
+    *out = nullptr;
+    if (l < 1 || m < 1 || n < 1 || nnz < 0 || l > (int64_t)INT32_MAX || m > (int64_t)INT32_MAX ||
+        n > (int64_t)INT32_MAX || (val_dtype != BKS_F32 && val_dtype != BKS_F64))
+        return guard(ctx, [] { fail(BKS_EINVAL, "bad sizes or value type"); });
+    if (nnz > 0 && (!i || !j || !k || !val)) return BKS_EINVAL;
+    if (flags & ~(unsigned)(BKS_DEVICE_PTRS | BKS_SUM_DUPLICATES))
+        return guard(ctx, [] { fail(BKS_EINVAL, "flags: only BKS_DEVICE_PTRS and BKS_SUM_DUPLICATES"); });
+    auto t = std::make_unique<bks_tensor_s>();
+    t->ctx = ctx;
+    t->l = l;
+    t->m = m;
+    t->n = n;
+    t->nnz = nnz;
+    const int rc = guard(ctx, [&] {
+        HIPCHECK(hipSetDevice(ctx->device));
+        const size_t vb = val_dtype == BKS_F64 ? 8 : 4;
+        std::vector<int32_t> hi, hj, hk;
+        std::vector<char> hv;
+        const int32_t *pi = i, *pj = j, *pk = k;
+        const void *pv = val;
+        if (flags & BKS_DEVICE_PTRS) {
+            hi.resize(nnz);
+            hj.resize(nnz);
+            hk.resize(nnz);
+            hv.resize((size_t)nnz * vb);
+            if (nnz) {
+                HIPCHECK(hipMemcpy(hi.data(), i, nnz * 4, hipMemcpyDeviceToHost));
+                HIPCHECK(hipMemcpy(hj.data(), j, nnz * 4, hipMemcpyDeviceToHost));
+                HIPCHECK(hipMemcpy(hk.data(), k, nnz * 4, hipMemcpyDeviceToHost));
+                HIPCHECK(hipMemcpy(hv.data(), val, nnz * vb, hipMemcpyDeviceToHost));
+            }
+            pi = hi.data();
+            pj = hj.data();
+            pk = hk.data();
+            pv = hv.data();
+        }
+        build_formats_general(*t, pi, pj, pk, pv, val_dtype, flags & ~(unsigned)BKS_DEVICE_PTRS);
+        if (ctx->budget && ctx->used + t->dev_bytes > ctx->budget)
+            fail(BKS_ENOMEM, "tensor exceeds the context memory budget");
+        ctx->used += t->dev_bytes;
+    });
+    if (rc != BKS_OK) {
+        t->release_device();
+        return rc;
+    }
+    {
+        std::lock_guard<std::mutex> g(ctx->tensors_mu);
+        ctx->tensors.push_back(t.get());
+    }
+    *out = t.release();
+    return BKS_OK;
+}
+
+int bks_gttmc(bks_ctx ctx, bks_tensor t, int mode, const void *B1, int64_t ld1, int p1,
+              const void *B2, int64_t ld2, int p2, int prec, void *out, int64_t ldo,
+              void *stream) {
+    if (!ctx || !t) return BKS_EINVAL;
+    return guard(ctx, [&] {
+        HIPCHECK(hipSetDevice(ctx->device));
+        gttmc(*ctx, *t, mode, B1, ld1, p1, B2, ld2, p2, prec, out, ldo,
+              static_cast<hipStream_t>(stream));
     });
 }
 

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <functional>
 #include <map>
@@ -27,10 +28,21 @@ void check_hip(hipError_t e, const char *what);
 #define HIPCHECK(x) ::bks::check_hip((x), #x)
 
 // ---------------------------------------------------------------- device memory
+// Device bytes held by the library's buffers, counted per accounting scope:
+// a thread that sets DevAccount::current (a served session) has every buffer
+// it allocates counted there until the buffer is released.
+struct DevAccount {
+    std::atomic<size_t> live{0}, peak{0};
+    void add(size_t b);
+    void sub(size_t b) { live.fetch_sub(b); }
+    static thread_local std::shared_ptr<DevAccount> current;
+};
+
 // A device buffer owned by the library.
 struct DevBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
+    std::shared_ptr<DevAccount> acct;  // scope that counted this allocation
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
@@ -65,6 +77,23 @@ struct Segmented {
     DevBuf v32;      // float [nent]
     DevBuf v64;      // double [nent] (only for FP64-valued tensors)
     std::vector<int64_t> h_segptr;  // host copy for schedule building
+};
+
+// Host copy of a schedule (built once per tensor, order and E; kept so
+// that a schedule can be placed in caller-provided device memory).
+struct HostSchedule {
+    int64_t nslots = 0;
+    std::vector<Item> items;
+    std::vector<Fixup> fix;
+    std::vector<std::vector<Fixup>> levels;  // tree levels, run in order before fix
+};
+
+// Device pointers of a schedule as one product call uses it.
+struct SchedView {
+    int64_t nitems = 0, nfix = 0, nslots = 0;
+    const Item *items = nullptr;
+    const Fixup *fix = nullptr;
+    std::vector<std::pair<int64_t, const Fixup *>> levels;
 };
 
 struct Schedule {
@@ -137,12 +166,16 @@ struct Ctx {
     DevBuf ws_partial;              // TTMc partial rows
     DevBuf ws_pack1, ws_pack2;      // dense-kernel partials
     DevBuf ws_fac1, ws_fac2;        // block-packed factor copies for TTMc
+    DevBuf ws_tmp;                  // intermediate products of two-step TTMc
     PinnedBuf pin;                  // staging of the solver's small copies
     std::mutex mu;
     std::mutex tensors_mu;
     std::vector<Tensor *> tensors;  // live tensors uploaded through this ctx
     // optional bracket around host-side dense solves (serving: bounded pool)
     std::function<void()> host_acquire, host_release;
+    // set by a server while a request runs: the solve stops at its next outer
+    // iteration once this reads true
+    const std::atomic<bool> *cancel = nullptr;
     DevSolver devsolve;
     DevInner devinner;
     bool prof = false;
@@ -152,6 +185,8 @@ struct Ctx {
     void prof_record(const std::string &name, hipEvent_t a, hipEvent_t b, double bytes,
                      double flops);
     void prof_flush();
+    // free the grow-only device workspaces (a served slot between requests)
+    void release_workspaces();
 };
 
 struct Tensor {
@@ -161,18 +196,37 @@ struct Tensor {
     double frob2 = 0.0;
     size_t dev_bytes = 0;
     Segmented o3;    // slices k: entries (i, j) with i <= j          (FREE3)
-    Segmented o1;    // rows r: entries (col, k), both orientations   (FREE1)
-    Segmented op;    // pairs (i <= j): entries (-, k)                (MODE3)
+    Segmented op;    // pairs (i <= j): entries (-, k)                (MODE3, FREE1)
+    Segmented pr;    // rows r: (col, pair id) of the pairs touching r (FREE1, no values)
+    // a general (non-symmetric) l x m x n tensor instead: segments by the
+    // index of mode a + 1, entries (the other two indices in mode order, value)
+    bool general = false;
+    int64_t l = 0;
+    Segmented g[3];
+    // the segmented stream of schedule format `fmt` (0 o3, 1 pr, 2 op, 4..6 g)
+    const Segmented &seg_of(int fmt) const {
+        return fmt == 0 ? o3 : fmt == 1 ? pr : fmt == 2 ? op : g[fmt - 4];
+    }
     std::vector<int32_t> pair_i, pair_j;
     std::mutex sched_mu;
     std::map<std::pair<int, int>, std::unique_ptr<Schedule>> sched;  // (order, E or CW) -> schedule
+    std::map<std::pair<int, int>, std::unique_ptr<HostSchedule>> hsched;
     const Schedule &schedule(int order, int E);
+    const HostSchedule &host_schedule(int order, int E);
     void release_device();  // free every device buffer (ctx teardown)
 };
 
 // Build formats from host COO (validated, canonicalised).  Throws Error.
 void build_formats(Tensor &t, const int32_t *i, const int32_t *j, const int32_t *k,
                    const void *val, int val_dtype, unsigned flags);
+// The same for a general tensor (t.l, t.m, t.n set; repeats summed with
+// BKS_SUM_DUPLICATES, else BKS_EDUP).
+void build_formats_general(Tensor &t, const int32_t *i, const int32_t *j, const int32_t *k,
+                           const void *val, int val_dtype, unsigned flags);
+// Product of a general tensor with one free mode `mode` (0, 1, 2): B1, B2
+// are the factors of the other two modes in mode order; out(row, a + p1 b).
+void gttmc(Ctx &c, Tensor &t, int mode, const void *B1, int64_t ld1, int p1, const void *B2,
+           int64_t ld2, int p2, int prec, void *out, int64_t ldo, hipStream_t s);
 
 // ---------------------------------------------------------------- TTMc
 // Launch a TTMc on device buffers; dtype of B/out follows prec.

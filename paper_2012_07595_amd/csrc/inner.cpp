@@ -1,7 +1,7 @@
 // Inner solve of Algorithm 5 step (i) on the host in FP64.
 //
 // g(P, S) = ||C.(P, P, S)||^2 on Gr(k1, r) x Gr(k3, r3).  Start: truncated
-// HOSVD of C and `hooi_warm` symmetric HOOI iterations (Section 5.2), then
+// HOSVD of C and `hooi_warm` symmetric HOOI iterations (section "Experiments"), then
 // Newton-Grassmann.  The paper cites Newton-Grassmann without giving it; the
 // step used here comes from the second-order expansion of g in the local
 // coordinates of Appendix A.  With [P P_perp], [S S_perp] orthogonal and
@@ -94,7 +94,7 @@ void lead_left(const std::vector<double> &M, int rows, int cols, int w, std::vec
     la::orthonormalize(rows, w, U.data());
 }
 
-// One symmetric HOOI iteration on the core (Section 5.1).
+// One symmetric HOOI iteration on the core (section "Higher Order Orthogonal Iteration").
 void hooi_step(const View &V, int r, int r3, std::vector<double> &P, std::vector<double> &S) {
     const int k1 = V.k1, k3 = V.k3;
     const size_t sl = (size_t)k1 * k1;

@@ -55,7 +55,7 @@ struct InnerInfo {
 
 // C: k1 x k1 x k3, column-major (a + k1*(b + k1*c)), symmetric in a, b.
 // P (k1 x r) and S (k3 x r3), row-major, are outputs; with `warm` they are
-// also the start (else HOSVD + hooi_warm HOOI steps, Section 5.2).
+// also the start (else HOSVD + hooi_warm HOOI steps, section "Experiments").
 // g(P, S) = ||C.(P, P, S)||^2 (P k1 x r, S k3 x r3, row-major)
 double inner_objective(const std::vector<double> &C, int k1, int k3, const std::vector<double> &P,
                        const std::vector<double> &S, int r, int r3, InnerDevice *dev = nullptr);

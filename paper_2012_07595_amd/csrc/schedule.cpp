@@ -36,6 +36,52 @@ void build_schedule(const std::vector<int64_t> &segptr, int E, std::vector<Item>
     }
 }
 
+void build_group_schedule(const std::vector<int64_t> &segptr, std::vector<Item> &items,
+                          std::vector<Fixup> &fix, int64_t &nslots) {
+    const int64_t nseg = (int64_t)segptr.size() - 1;
+    items.clear();
+    fix.clear();
+    nslots = 0;
+    // smallest power-of-two group that gives each lane at most kGroupLPE entries
+    auto group_of = [](int64_t len) {
+        int L = 1;
+        while (L < 64 && (int64_t)L * kGroupLPE < len) L <<= 1;
+        return L;
+    };
+    int64_t s = 0;
+    while (s < nseg) {
+        const int64_t len = segptr[s + 1] - segptr[s];
+        if (len > (int64_t)64 * kGroupLPE) {
+            const int64_t nch = (len + kGroupChunk - 1) / kGroupChunk;
+            if (nch == 1) {
+                items.push_back({(int32_t)s, -1, segptr[s], segptr[s + 1], -1, 64});
+            } else {
+                fix.push_back({(int32_t)s, (int32_t)nslots, (int32_t)nch, 0});
+                for (int64_t c = 0; c < nch; ++c) {
+                    const int64_t b = segptr[s] + len * c / nch, e = segptr[s] + len * (c + 1) / nch;
+                    items.push_back({(int32_t)s, -1, b, e, (int32_t)(nslots + c), 64});
+                }
+                nslots += nch;
+            }
+            ++s;
+            continue;
+        }
+        // a run of segments that all fit one group width L, 64 / L of them
+        const int64_t s0 = s;
+        int L = group_of(len);
+        ++s;
+        while (s < nseg) {
+            const int64_t l2 = segptr[s + 1] - segptr[s];
+            if (l2 > (int64_t)64 * kGroupLPE) break;
+            const int L2 = std::max(L, group_of(l2));
+            if ((s - s0 + 1) * L2 > 64) break;
+            L = L2;
+            ++s;
+        }
+        items.push_back({(int32_t)s0, (int32_t)s, 0, 0, -1, L});
+    }
+}
+
 void build_wide_schedule(const std::vector<int64_t> &segptr, int CW, std::vector<Item> &items,
                          std::vector<Fixup> &fix, int64_t &nslots) {
     const int64_t nseg = (int64_t)segptr.size() - 1;

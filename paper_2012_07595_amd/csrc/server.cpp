@@ -1,19 +1,28 @@
 // Serving: continuous batching of BKS solves of different tensors and ranks.
 //
-// Requests wait in a FIFO queue.  A request is admitted when a session slot
-// is free and its device footprint (tensor formats when the server uploads
-// them, plus the solver's basis, product and core buffers) fits the memory
-// budget left by the sessions already running; requests larger than the
-// whole budget are refused at submit.  Each admitted session runs on a worker
-// thread with its own HIP stream and workspaces, so the device work of
-// different sessions overlaps on the GPU; the host-side dense inner solves
-// share a bounded pool of host slots.  A solve's arithmetic does not depend on
-// what else runs (fixed-order reductions, no atomics), so a request's result
-// is the same alone and in the mix.
+// Requests wait in a queue in arrival order.  A free session slot takes the
+// oldest waiting request whose device footprint (tensor formats when the
+// server uploads them, plus the solver's basis, product and core buffers)
+// fits the memory budget left by the sessions already running; a request
+// that does not fit is passed over for a later one that does, but at most
+// kMaxBypass times, after which nothing behind it is admitted until it is
+// (so a large request is not starved by a stream of small ones).  Requests
+// larger than the whole budget are refused at submit.  Each admitted session
+// runs on a worker thread with its own HIP stream and workspaces, so the
+// device work of different sessions overlaps on the GPU; the host-side dense
+// inner solves share a bounded pool of host slots.  A slot frees its
+// workspaces when its request ends, so that the device bytes it holds are
+// the admitted footprint's.  A solve's arithmetic does not depend on what
+// else runs (fixed-order reductions, no atomics), so a request's result is
+// the same alone and in the mix.
+//
+// Cancellation: a waiting request leaves the queue at once; a running one
+// stops at its next outer iteration and returns the point it had reached.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <thread>
@@ -25,7 +34,7 @@ namespace bks {
 
 int run_bks(Ctx &c, Tensor &t, const bks_params &prm, double *U, double *W, double *F,
             bks_info *info, hipStream_t s);
-size_t solve_footprint(int64_t m, int64_t n, const bks_params &prm);
+size_t solve_footprint(int64_t m, int64_t n, int64_t nnz, const bks_params &prm);
 
 namespace {
 
@@ -39,11 +48,18 @@ struct Request {
     bks_params prm;
     double *U, *W, *F;
     size_t footprint = 0;
+    size_t dev_peak = 0;
     double t_submit = 0, t_start = 0, t_end = 0;
     int status = 0;
     bool done = false;
+    bool running = false;
+    int bypassed = 0;                 // times a later request was admitted first
+    std::string error;                // message of a failed request
+    std::atomic<bool> cancel{false};
     bks_info info;
 };
+
+constexpr int kMaxBypass = 16;
 
 }  // namespace
 }  // namespace bks
@@ -90,20 +106,25 @@ struct bks_server_s {
             cv_host.notify_one();
         };
         if (hipStreamCreateWithFlags(&sc.stream, hipStreamNonBlocking) != hipSuccess) return;
+        auto acct = std::make_shared<DevAccount>();
+        DevAccount::current = acct;
         while (true) {
             Request *r = nullptr;
             {
                 std::unique_lock<std::mutex> g(mu);
-                cv_queue.wait(g, [&] {
-                    return stop || (!queue.empty() && in_use + queue.front()->footprint <= budget);
-                });
+                cv_queue.wait(g, [&] { return stop || pick() != queue.end(); });
                 if (stop && queue.empty()) break;
-                if (queue.empty() || in_use + queue.front()->footprint > budget) continue;
-                r = queue.front();
-                queue.pop_front();
+                auto it = pick();
+                if (it == queue.end()) continue;
+                r = *it;
+                for (auto b = queue.begin(); b != it; ++b) ++(*b)->bypassed;
+                queue.erase(it);
                 in_use += r->footprint;
+                r->running = true;
                 r->t_start = now();
             }
+            acct->peak.store(acct->live.load());
+            sc.cancel = &r->cancel;
             int status = BKS_OK;
             try {
                 if (!r->tensor) {
@@ -124,19 +145,28 @@ struct bks_server_s {
                 status = run_bks(sc, *r->tensor, r->prm, r->U, r->W, r->F, &r->info, sc.stream);
             } catch (const Error &e) {
                 status = e.code;
+                r->error = e.msg;
             } catch (const std::bad_alloc &) {
                 status = BKS_ENOMEM;
-            } catch (const std::exception &) {
+                r->error = "host allocation failed";
+            } catch (const std::exception &e) {
                 status = BKS_EDEVICE;
+                r->error = e.what();
             }
+            sc.cancel = nullptr;
+            (void)hipStreamSynchronize(sc.stream);
+            const size_t peak = acct->peak.load();
             if (r->owns_tensor) {
                 r->tensor->release_device();
                 delete r->tensor;
                 r->tensor = nullptr;
             }
+            sc.release_workspaces();
             {
                 std::lock_guard<std::mutex> g(mu);
                 in_use -= r->footprint;
+                r->dev_peak = peak;
+                r->running = false;
                 r->status = status;
                 r->t_end = now();
                 r->done = true;
@@ -144,10 +174,20 @@ struct bks_server_s {
             cv_done.notify_all();
             cv_queue.notify_all();
         }
-        sc.ws_partial.release();
-        sc.ws_pack1.release();
-        sc.ws_pack2.release();
+        sc.release_workspaces();
+        DevAccount::current.reset();
         (void)hipStreamDestroy(sc.stream);
+    }
+
+    // The request a free slot takes (caller holds mu): the oldest one that
+    // fits the budget left, unless the head has been passed over kMaxBypass
+    // times, in which case only the head may go.
+    std::deque<Request *>::iterator pick() {
+        for (auto it = queue.begin(); it != queue.end(); ++it) {
+            if (in_use + (*it)->footprint <= budget) return it;
+            if ((*it)->bypassed >= kMaxBypass) break;
+        }
+        return queue.end();
     }
 };
 
@@ -157,7 +197,8 @@ int submit(bks_server s, std::unique_ptr<Request> r, uint64_t *id) {
     const int r1 = r->prm.r, r3 = r->prm.r3;
     const int64_t m = r->tensor ? r->tensor->m : r->m, n = r->tensor ? r->tensor->n : r->n;
     if (r1 < 1 || r3 < 1 || r1 > m || r3 > n || r3 > r1 * (r1 + 1) / 2) return BKS_EINVAL;
-    size_t fp = solve_footprint(m, n, r->prm);
+    const int64_t nnz = r->tensor ? r->tensor->nnz : r->nnz;
+    size_t fp = solve_footprint(m, n, nnz, r->prm);
     if (!r->tensor) fp += (size_t)r->nnz * 48 + (size_t)(m + n) * 16 + 4096;
     r->footprint = fp;
     if (fp > s->budget) return BKS_ENOMEM;
@@ -174,6 +215,9 @@ int submit(bks_server s, std::unique_ptr<Request> r, uint64_t *id) {
 }
 
 void fill(const Request &r, bks_result *res) {
+    res->footprint = r.footprint;
+    res->dev_peak = r.dev_peak;
+    std::snprintf(res->error, sizeof(res->error), "%s", r.error.c_str());
     res->status = r.status;
     res->done = r.done ? 1 : 0;
     res->t_submit = r.t_submit;
@@ -257,6 +301,30 @@ int bks_server_wait(bks_server s, uint64_t id, bks_result *res) {
     return BKS_OK;
 }
 
+int bks_server_cancel(bks_server s, uint64_t id) {
+    if (!s) return BKS_EINVAL;
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->reqs.find(id);
+    if (it == s->reqs.end()) return BKS_ENOTFOUND;
+    Request *r = it->second.get();
+    if (r->done) return BKS_EINVAL;
+    if (r->running) {
+        r->cancel.store(true);
+        return BKS_OK;
+    }
+    auto q = std::find(s->queue.begin(), s->queue.end(), r);
+    if (q != s->queue.end()) s->queue.erase(q);
+    r->ci.clear(); r->cj.clear(); r->ck.clear(); r->cv.clear();
+    r->ci.shrink_to_fit(); r->cj.shrink_to_fit(); r->ck.shrink_to_fit(); r->cv.shrink_to_fit();
+    r->status = BKS_ECANCELED;
+    r->t_start = r->t_end = s->now();
+    r->done = true;
+    s->cv_done.notify_all();
+    // the queue changed: a request behind this one may fit now
+    s->cv_queue.notify_all();
+    return BKS_OK;
+}
+
 double bks_server_now(bks_server s) { return s ? s->now() : 0.0; }
 
 void bks_server_destroy(bks_server s) {
@@ -266,7 +334,7 @@ void bks_server_destroy(bks_server s) {
         s->stop = true;
         // requests that were never admitted are cancelled
         for (Request *r : s->queue) {
-            r->status = BKS_EINVAL;
+            r->status = BKS_ECANCELED;
             r->done = true;
         }
         s->queue.clear();

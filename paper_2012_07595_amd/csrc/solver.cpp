@@ -1,5 +1,5 @@
 // Block Krylov-Schur (Algorithm 5, symmetric case U = V) and symmetric HOOI
-// (Section 5.1) driven from the host; every product with the large tensor
+// (section "Higher Order Orthogonal Iteration") driven from the host; every product with the large tensor
 // and every tall-skinny operation runs on the device, the small projected
 // problems on the host in FP64.
 //
@@ -564,7 +564,7 @@ struct Solver {
             }
         o.normF = std::sqrt(f2);
         o.rel = o.normF > 0 ? std::sqrt(2.0 * g1 + g3) / o.normF : INFINITY;
-        // S-values (Section 2.6)
+        // S-values (section "Conditioning of the best approximation problem")
         auto svals = [](int rows_, int cols, const std::vector<double> &M, int nv) {
             // singular values of M (rows_ x cols) via eig of M M^T
             std::vector<double> G((size_t)rows_ * rows_, 0.0), w(rows_), V((size_t)rows_ * rows_);
@@ -727,6 +727,7 @@ void fill_info(bks_info *info, const Solver::StepOut &o, int iters, bool conv, i
     info->normA = normA;
     for (int i = 0; i < 65; ++i) {
         info->svals1[i] = i < (int)o.s1.size() ? o.s1[i] : 0.0;
+        info->svals2[i] = info->svals1[i];  // U = V
         info->svals3[i] = i < (int)o.s3.size() ? o.s3[i] : 0.0;
     }
 }
@@ -735,7 +736,7 @@ void fill_info(bks_info *info, const Solver::StepOut &o, int iters, bool conv, i
 
 // Device bytes a bks_solve of an m x m x n tensor allocates (the buffers of
 // Solver::allocate plus the product workspaces), for admission control.
-size_t solve_footprint(int64_t m, int64_t n, const bks_params &prm) {
+size_t solve_footprint(int64_t m, int64_t n, int64_t nnz, const bks_params &prm) {
     Ctx c;
     Tensor t;
     t.m = m;
@@ -752,13 +753,31 @@ size_t solve_footprint(int64_t m, int64_t n, const bks_params &prm) {
     b += (size_t)m * prm.r * prm.r3 * 8 + (size_t)n * (prm.r * (prm.r + 1) / 2) * 8;
     b += (size_t)n * Q * (mixed ? 4 : 8) + k3 * Q * 8;
     b += 2 * std::max(k1, k3) * std::max<size_t>(q, 64) * 8 + 64 * 64 * 16;
-    // product partials and the split reductions (grow-only workspaces): the
-    // wide core product keeps one k1 x k1 partial per slice chunk and a
-    // block-packed copy of X
+    // product partials and the split reductions (grow-only workspaces, 25%
+    // slack each): a core product wider than 24 columns keeps one k1 x k1
+    // partial per slice chunk, counted as the product counts its chunks
+    // (chunk width clamp(nnz / 4096, 256, 2048), widened so that at most
+    // max(n + 1, 512 MB / partial) chunks exist, every slice at least one),
+    // plus a block-packed copy of X
     const size_t cts = mixed ? 4 : 8;
-    b += std::min<size_t>((size_t)(n + 4096) * k1 * k1 * cts, (size_t)1 << 29) +
-         (size_t)m * (k1 + 16) * cts;
+    if (k1 > 24) {
+        const double per_item = (double)k1 * k1 * cts;
+        const int64_t max_items = std::max<int64_t>(n + 1, (int64_t)(536870912.0 / per_item));
+        int64_t cw = std::min<int64_t>(2048, std::max<int64_t>(256, nnz / 4096));
+        cw = std::max<int64_t>(cw, nnz / std::max<int64_t>(1, max_items - n) + 1);
+        const int64_t items = std::min<int64_t>(max_items, n + nnz / cw + 1);
+        b += (size_t)items * k1 * k1 * cts / 4 * 5 + (size_t)m * (k1 + 16) * cts / 4 * 5;
+    }
     b += (size_t)n * Q * 8 / 4 + rows * 64 * 8 + (size_t)(1 << 20) * 8;
+    // inner solve on the device: the core and its rotated blocks (each at
+    // most k1^2 k3 doubles) for large cores, and the Newton matrix with its
+    // shifted copy for large Newton systems (grow-only, 25% slack)
+    const size_t core = k1 * k1 * k3 * 8;
+    if ((double)k1 * k1 * k3 >= device_core_min())
+        b += 4 * core / 4 * 5 + (k1 * k1 + k3 * k3) * 8 / 4 * 5;
+    const size_t N = (size_t)prm.r * (k1 - std::min<size_t>(k1, prm.r)) +
+                     (size_t)prm.r3 * (k3 - std::min<size_t>(k3, prm.r3));
+    if ((int64_t)N >= device_solve_min()) b += 2 * N * N * 8 / 4 * 5 + N * 16 + 4096;
     return b;
 }
 
@@ -766,6 +785,7 @@ int run_bks(Ctx &c, Tensor &t, const bks_params &prm, double *U, double *W, doub
             bks_info *info, hipStream_t s) {
     const double t0 = now_s();
     const int r = prm.r, r3 = prm.r3;
+    if (t.general) fail(BKS_EINVAL, "a general tensor: use bks_gsolve");
     if (r < 1 || r3 < 1 || r > t.m || r3 > t.n || r3 > r * (r + 1) / 2)
         fail(BKS_EINVAL, "need 1 <= r <= m, 1 <= r3 <= min(n, r(r+1)/2)");
     if (r > 64 || r3 > 64) fail(BKS_EINVAL, "r and r3 are limited to 64");
@@ -809,7 +829,14 @@ int run_bks(Ctx &c, Tensor &t, const bks_params &prm, double *U, double *W, doub
     std::vector<double> rel_hist, f_hist;
     long inner_newton = 0;
     int last_k1 = S.k1, last_k3 = S.k3;
+    bool cancelled = false;
     while (true) {
+        // a served request that was cancelled stops here, at the point of its
+        // last restart (or its start), which is returned
+        if (c.cancel && c.cancel->load()) {
+            cancelled = true;
+            break;
+        }
         last_k1 = S.k1;
         last_k3 = S.k3;
         a = now_s();
@@ -916,15 +943,16 @@ int run_bks(Ctx &c, Tensor &t, const bks_params &prm, double *U, double *W, doub
             info->normF_hist[i] = f_hist[i];
         }
     }
+    if (cancelled) return BKS_ECANCELED;
     return conv ? BKS_OK : BKS_ENOTCONV;
 }
 
-// Symmetric HOOI (Section 5.1): U from the r leading left singular vectors
+// Symmetric HOOI (section "Higher Order Orthogonal Iteration"): U from the r leading left singular vectors
 // of T1 = A.(U, W)_{2,3}, then W from A.(U, U)_{1,2} with the new U (its
 // sym-half unfolding with off-diagonal columns weighted by sqrt(2) has the
 // Gram matrix of the full unfolding).  Singular vectors come from the small
 // Gram matrix: U = T1 V_r diag(sigma)^{-1}, then re-orthonormalised in FP64.
-// The G-gradient (global coordinates, Section 2.5) is evaluated every
+// The G-gradient (global coordinates, section "Gradient on the product manifold") is evaluated every
 // `grad_every` iterations with FP64-accurate products.  In mixed precision
 // the iteration products are FP32 until the measured relative gradient is
 // below 1e-4, then FP64-accurate.
@@ -932,6 +960,7 @@ int run_hooi(Ctx &c, Tensor &t, const hooi_params &prm, double *U, double *W, do
              bks_info *info, hipStream_t s) {
     const double t0 = now_s();
     const int r = prm.r, r3 = prm.r3;
+    if (t.general) fail(BKS_EINVAL, "a general tensor: use bks_gsolve");
     if (r < 1 || r3 < 1 || r > t.m || r3 > t.n || r3 > r * (r + 1) / 2)
         fail(BKS_EINVAL, "need 1 <= r <= m, 1 <= r3 <= min(n, r(r+1)/2)");
     if (r > 64 || r3 > 64) fail(BKS_EINVAL, "r and r3 are limited to 64");
@@ -1096,6 +1125,623 @@ int run_hooi(Ctx &c, Tensor &t, const hooi_params &prm, double *U, double *W, do
     return conv ? BKS_OK : BKS_ENOTCONV;
 }
 
+// ---------------------------------------------------------------- general tensors
+// Algorithm 5 for a general (non-symmetric) tensor A in R^{l x m x n}
+// (section "A Tensor Krylov-Schur like method"): three bases X, Y, Z grown
+// by the mode-1, -2, -3 block-Krylov steps of Algorithm 3 (section
+// "Block-Krylov methods"), the core C = A.(X, Y, Z), its best rank-(r1, r2,
+// r3) approximation, the restart and one block-Krylov step per mode with the
+// three-term G-gradient of Proposition 3.2.  Schedule (the paper gives the BK
+// diagrams for the (1,2)-symmetric case only): min-BK in every mode -- stage
+// t: U_t from (Vbar_{t-1}, Wbar_{t-1}), V_t from (Ubar_{t-1}, Wbar_{t-1}),
+// W_t from (Ubar_{t-1}, Vbar_{t-1}); U0, V0, W0 whole, later blocks their
+// first p columns.  Inner solve: truncated HOSVD, then HOOI until the
+// projected problem's relative gradient reaches the tolerance (the paper's
+// alternative to Newton-Grassmann, with the same fixed points).
+namespace {
+
+// dense core helpers (host, small sizes): C is k0 x k1 x k2, column-major
+struct GCore {
+    int k[3];
+    std::vector<double> C;
+    double at(int a, int b, int c) const { return C[a + (size_t)k[0] * (b + (size_t)k[1] * c)]; }
+};
+
+// M = mode-`md` unfolding of C.(P0, P1, P2) with the factor of mode md the
+// identity: rows k[md], columns (first remaining fastest) r_b * r_c
+static std::vector<double> partial_unfold(const GCore &G, int md, const std::vector<double> *P[3],
+                                          const int r[3]) {
+    const int k0 = G.k[0], k1 = G.k[1], k2 = G.k[2];
+    // contract the two other modes one at a time
+    int d[3] = {k0, k1, k2};
+    std::vector<double> cur = G.C;
+    for (int mode = 0; mode < 3; ++mode) {
+        if (mode == md) continue;
+        const std::vector<double> &Pm = *P[mode];  // k[mode] x r[mode], row-major
+        int nd[3] = {d[0], d[1], d[2]};
+        nd[mode] = r[mode];
+        std::vector<double> nxt((size_t)nd[0] * nd[1] * nd[2], 0.0);
+        for (int c = 0; c < d[2]; ++c)
+            for (int b = 0; b < d[1]; ++b)
+                for (int a = 0; a < d[0]; ++a) {
+                    const double v = cur[a + (size_t)d[0] * (b + (size_t)d[1] * c)];
+                    if (v == 0.0) continue;
+                    const int idx[3] = {a, b, c};
+                    for (int x = 0; x < r[mode]; ++x) {
+                        int o[3] = {a, b, c};
+                        o[mode] = x;
+                        nxt[o[0] + (size_t)nd[0] * (o[1] + (size_t)nd[1] * o[2])] +=
+                            v * Pm[(size_t)idx[mode] * r[mode] + x];
+                    }
+                }
+        cur.swap(nxt);
+        d[0] = nd[0];
+        d[1] = nd[1];
+        d[2] = nd[2];
+    }
+    // unfold in mode md: rows d[md], columns the other two (first fastest)
+    const int o1 = md == 0 ? 1 : 0, o2 = md == 2 ? 1 : 2;
+    std::vector<double> M((size_t)d[md] * d[o1] * d[o2]);
+    for (int c = 0; c < d[2]; ++c)
+        for (int b = 0; b < d[1]; ++b)
+            for (int a = 0; a < d[0]; ++a) {
+                const int idx[3] = {a, b, c};
+                M[(size_t)idx[md] * d[o1] * d[o2] + idx[o1] + (size_t)d[o1] * idx[o2]] =
+                    cur[a + (size_t)d[0] * (b + (size_t)d[1] * c)];
+            }
+    return M;
+}
+
+// leading r left singular vectors of M (rows x cols, row-major), rows x r row-major
+static std::vector<double> top_left(const std::vector<double> &M, int rows, int cols, int r) {
+    std::vector<double> G((size_t)rows * rows);
+    la::dgemm(false, true, rows, rows, cols, 1.0, M.data(), cols, M.data(), cols, 0.0, G.data(), rows);
+    std::vector<double> V((size_t)rows * r);
+    la::top_eigvecs(rows, G.data(), r, V.data());
+    return V;
+}
+
+// relative G-gradient of ||C.(P0, P1, P2)||^2 and ||F||^2
+static double g_gradient(const GCore &G, const std::vector<double> *P[3], const int r[3],
+                         double *f2out) {
+    double g2 = 0.0, f2 = 0.0;
+    for (int md = 0; md < 3; ++md) {
+        const int rows = G.k[md];
+        const int o1 = md == 0 ? 1 : 0, o2 = md == 2 ? 1 : 2;
+        const int cols = r[o1] * r[o2];
+        const std::vector<double> M = partial_unfold(G, md, P, r);      // rows x cols
+        const std::vector<double> &B = *P[md];                            // rows x r[md]
+        // F_(md) = B^T M (r x cols); G = (M - B F) F^T
+        std::vector<double> F((size_t)r[md] * cols), R = M, Gm((size_t)rows * r[md]);
+        la::dgemm(true, false, r[md], cols, rows, 1.0, B.data(), r[md], M.data(), cols, 0.0, F.data(), cols);
+        la::dgemm(false, false, rows, cols, r[md], -1.0, B.data(), r[md], F.data(), cols, 1.0, R.data(), cols);
+        la::dgemm(false, true, rows, r[md], cols, 1.0, R.data(), cols, F.data(), cols, 0.0, Gm.data(), r[md]);
+        for (double v : Gm) g2 += v * v;
+        if (md == 0)
+            for (double v : F) f2 += v * v;
+    }
+    if (f2out) *f2out = f2;
+    return f2 > 0 ? std::sqrt(g2 / f2) : INFINITY;
+}
+
+static void g_inner(const GCore &G, const int r[3], double tol, int max_iter, bool from_e0,
+                    std::vector<double> out[3]) {
+    std::vector<double> P[3];
+    const std::vector<double> *pp[3] = {&P[0], &P[1], &P[2]};
+    for (int md = 0; md < 3; ++md) {
+        if (from_e0) {
+            P[md].assign((size_t)G.k[md] * r[md], 0.0);
+            for (int j = 0; j < r[md]; ++j) P[md][(size_t)j * r[md] + j] = 1.0;
+        } else {
+            // truncated HOSVD: leading left singular vectors of the unfoldings
+            std::vector<double> I3[3];
+            int rr[3] = {G.k[0], G.k[1], G.k[2]};
+            for (int x = 0; x < 3; ++x) {
+                I3[x].assign((size_t)G.k[x] * G.k[x], 0.0);
+                for (int j = 0; j < G.k[x]; ++j) I3[x][(size_t)j * G.k[x] + j] = 1.0;
+            }
+            const std::vector<double> *ip[3] = {&I3[0], &I3[1], &I3[2]};
+            const int o1 = md == 0 ? 1 : 0, o2 = md == 2 ? 1 : 2;
+            const std::vector<double> M = partial_unfold(G, md, ip, rr);
+            P[md] = top_left(M, G.k[md], G.k[o1] * G.k[o2], r[md]);
+        }
+    }
+    double rel = g_gradient(G, pp, r, nullptr);
+    for (int it = 1; rel > tol && it <= max_iter; ++it) {
+        for (int md = 0; md < 3; ++md) {
+            const int o1 = md == 0 ? 1 : 0, o2 = md == 2 ? 1 : 2;
+            const std::vector<double> M = partial_unfold(G, md, pp, r);
+            P[md] = top_left(M, G.k[md], r[o1] * r[o2], r[md]);
+        }
+        if (it % 5 == 0 || it == max_iter) rel = g_gradient(G, pp, r, nullptr);
+    }
+    for (int md = 0; md < 3; ++md) out[md] = P[md];
+}
+
+struct GSolver {
+    Ctx &c;
+    Tensor &t;
+    hipStream_t s;
+    int64_t dim[3];
+    int r[3], p, stages;
+    bool mixed;
+    double tau64 = 1e-14, tau32 = 1e-5;
+    int kcap[3] = {0, 0, 0}, k[3] = {0, 0, 0}, qcap = 0;
+    DevBuf B64[3], B32[3], P32, P64, W64a, T64[3], Hd, Gd, Tb32, Tb64, Cb;
+    std::vector<int> off[3], w[3];
+
+    GSolver(Ctx &c_, Tensor &t_, hipStream_t s_, const int r_[3], int p_, int st, bool mx)
+        : c(c_), t(t_), s(s_), p(p_), stages(st), mixed(mx) {
+        dim[0] = t.l;
+        dim[1] = t.m;
+        dim[2] = t.n;
+        for (int x = 0; x < 3; ++x) r[x] = r_[x];
+    }
+
+    void sync() { HIPCHECK(hipStreamSynchronize(s)); }
+    template <class T_> void d2h(T_ *h, const void *d, size_t count) {
+        HIPCHECK(hipMemcpyAsync(h, d, count * sizeof(T_), hipMemcpyDeviceToHost, s));
+        sync();
+    }
+    template <class T_> void h2d(void *d, const T_ *h, size_t count) {
+        HIPCHECK(hipMemcpyAsync(d, h, count * sizeof(T_), hipMemcpyHostToDevice, s));
+        sync();
+    }
+    double *col(int md, int j) { return B64[md].as<double>() + j; }
+    static int other1(int md) { return md == 0 ? 1 : 0; }
+    static int other2(int md) { return md == 2 ? 1 : 2; }
+    int bar(int md, int blk) const { return blk == 0 ? w[md][0] : std::min(p, w[md][blk]); }
+
+    void plan() {
+        int64_t K[3];
+        int wd[3][16];
+        for (int x = 0; x < 3; ++x) {
+            K[x] = r[x];
+            wd[x][0] = r[x];
+        }
+        qcap = std::max({r[1] * r[2], r[0] * r[2], r[0] * r[1]});
+        for (int st = 1; st <= stages && st < 16; ++st) {
+            int q[3];
+            for (int md = 0; md < 3; ++md) {
+                auto b = [&](int x) { return st - 1 == 0 ? wd[x][0] : std::min(p, wd[x][st - 1]); };
+                q[md] = b(other1(md)) * b(other2(md));
+                qcap = std::max(qcap, q[md]);
+            }
+            for (int md = 0; md < 3; ++md) {
+                const int ww = (int)std::min<int64_t>(q[md], dim[md] - K[md]);
+                wd[md][st] = ww;
+                K[md] += ww;
+            }
+        }
+        for (int x = 0; x < 3; ++x) {
+            kcap[x] = (int)std::min<int64_t>(dim[x], K[x]);
+            if (kcap[x] > 4096) fail(BKS_EINVAL, "basis would exceed 4096 columns");
+        }
+    }
+
+    void allocate() {
+        const int64_t rows = std::max({dim[0], dim[1], dim[2]});
+        for (int x = 0; x < 3; ++x) {
+            B64[x].alloc((size_t)dim[x] * kcap[x] * 8);
+            if (mixed) B32[x].alloc((size_t)dim[x] * kcap[x] * 4);
+            const int q = r[other1(x)] * r[other2(x)];
+            T64[x].alloc((size_t)dim[x] * q * 8);
+        }
+        P64.alloc((size_t)rows * qcap * 8);
+        if (mixed) P32.alloc((size_t)rows * qcap * 4);
+        W64a.alloc((size_t)rows * std::max(qcap, std::max({r[0], r[1], r[2]})) * 8);
+        const int kmax = std::max({kcap[0], kcap[1], kcap[2]});
+        Hd.alloc((size_t)kmax * std::max(qcap, 64) * 8 + 4096);
+        Gd.alloc((size_t)64 * 64 * 8 * 2 + 64 * 8);
+        // core blocks: (n x 20*20) products and their k2 x 400 projections
+        Tb64.alloc((size_t)dim[2] * 400 * 8);
+        if (mixed) Tb32.alloc((size_t)dim[2] * 400 * 4);
+        Cb.alloc((size_t)kcap[2] * 400 * 8);
+    }
+
+    int orth_append(int md, double *B, int64_t ldb, int q, double tau) {
+        const int64_t rows = dim[md];
+        int &kk = k[md];
+        const int cap = kcap[md];
+        const int64_t ldbas = kcap[md];
+        int total = 0;
+        for (int c0 = 0; c0 < q; c0 += 64) {
+            const int qc = std::min(64, q - c0);
+            double *Bc = B + c0;
+            const int room = cap - kk;
+            if (room <= 0) break;
+            colnorm2(Bc, ldb, rows, qc, Gd.as<double>() + 2 * 64 * 64, c, s);
+            double *H = Hd.as<double>();
+            for (int pass = 0; pass < 2 && kk > 0; ++pass) {
+                gemm_tn_f64(B64[md].as<double>(), ldbas, Bc, ldb, rows, kk, qc, H, qc, c, s);
+                gemm_nn_f64(B64[md].as<double>(), ldbas, H, qc, rows, kk, qc, -1.0, 1.0, Bc, ldb, s);
+            }
+            gram_dd(Bc, ldb, rows, qc, Gd.as<double>(), Gd.as<double>() + 64 * 64, c, s);
+            std::vector<double> all((size_t)2 * 64 * 64 + qc);
+            d2h(all.data(), Gd.ptr, all.size());
+            std::vector<double> Ghi(all.begin(), all.begin() + (size_t)qc * qc),
+                Glo(all.begin() + 64 * 64, all.begin() + 64 * 64 + (size_t)qc * qc),
+                before2(all.begin() + 2 * 64 * 64, all.begin() + 2 * 64 * 64 + qc);
+            std::vector<int> kept;
+            std::vector<double> T;
+            chol_drop(qc, Ghi, Glo, before2, tau, room, kept, T);
+            const int qk = (int)kept.size();
+            if (qk == 0) continue;
+            double *Q1 = W64a.as<double>();
+            h2d(H, T.data(), T.size());
+            gemm_nn_f64(Bc, ldb, H, qk, rows, qc, qk, 1.0, 0.0, Q1, qk, s);
+            if (kk > 0) {
+                gemm_tn_f64(B64[md].as<double>(), ldbas, Q1, qk, rows, kk, qk, H, qk, c, s);
+                gemm_nn_f64(B64[md].as<double>(), ldbas, H, qk, rows, kk, qk, -1.0, 1.0, Q1, qk, s);
+            }
+            gram_dd(Q1, qk, rows, qk, Gd.as<double>(), Gd.as<double>() + 64 * 64, c, s);
+            std::vector<double> all2((size_t)64 * 64 + (size_t)qk * qk);
+            d2h(all2.data(), Gd.ptr, all2.size());
+            std::vector<double> G2h(all2.begin(), all2.begin() + (size_t)qk * qk),
+                G2l(all2.begin() + 64 * 64, all2.begin() + 64 * 64 + (size_t)qk * qk);
+            std::vector<double> ones(qk, 1.0), T2;
+            std::vector<int> kept2;
+            chol_drop(qk, G2h, G2l, ones, 0.0, qk, kept2, T2);
+            if ((int)kept2.size() != qk) fail(BKS_EDEVICE, "orthogonalisation lost rank");
+            h2d(H, T2.data(), T2.size());
+            gemm_nn_f64(Q1, qk, H, qk, rows, qk, qk, 1.0, 0.0, B64[md].as<double>() + kk, ldbas, s);
+            if (mixed)
+                convert_f64_f32(B64[md].as<double>() + kk, ldbas, B32[md].as<float>() + kk, ldbas,
+                                rows, qk, s);
+            kk += qk;
+            total += qk;
+        }
+        return total;
+    }
+
+    // orthonormalise columns [0, ww) of basis md (CholQR twice) as its only block
+    void reset_basis(int md, int ww) {
+        const int64_t rows = dim[md], ld = kcap[md];
+        double *W = W64a.as<double>();
+        for (int pass = 0; pass < 2; ++pass) {
+            copy2d_f64(B64[md].as<double>(), ld, W, ww, rows, ww, s);
+            gram_dd(W, ww, rows, ww, Gd.as<double>(), Gd.as<double>() + 64 * 64, c, s);
+            std::vector<double> all((size_t)64 * 64 + (size_t)ww * ww);
+            d2h(all.data(), Gd.ptr, all.size());
+            std::vector<double> Gh(all.begin(), all.begin() + (size_t)ww * ww),
+                Gl(all.begin() + 64 * 64, all.begin() + 64 * 64 + (size_t)ww * ww), ones(ww, 1.0), T;
+            std::vector<int> kept;
+            chol_drop(ww, Gh, Gl, ones, 0.0, ww, kept, T);
+            if ((int)kept.size() != ww) fail(BKS_EINVAL, "start matrix is rank deficient");
+            h2d(Hd.ptr, T.data(), T.size());
+            gemm_nn_f64(W, ww, Hd.as<double>(), ww, rows, ww, ww, 1.0, 0.0, B64[md].as<double>(), ld, s);
+        }
+        if (mixed) convert_f64_f32(B64[md].as<double>(), ld, B32[md].as<float>(), ld, rows, ww, s);
+        k[md] = ww;
+        off[md] = {0};
+        w[md] = {ww};
+    }
+
+    void load_start(int md, const double *h) {
+        const int64_t rows = dim[md], ld = kcap[md];
+        std::vector<double> rm((size_t)rows * ld, 0.0);
+        for (int64_t i = 0; i < rows; ++i)
+            for (int j = 0; j < r[md]; ++j) rm[(size_t)i * ld + j] = h[(size_t)j * rows + i];
+        h2d(B64[md].ptr, rm.data(), rm.size());
+        reset_basis(md, r[md]);
+    }
+
+    // product for a new block of mode md from blocks (b1 of the first other
+    // mode, b2 of the second), into dst (dim[md] x q, FP64)
+    int product(int md, int b1, int b2, int prec, double *dst, int64_t ldd) {
+        const int m1 = other1(md), m2 = other2(md);
+        const int p1 = bar(m1, b1), p2 = bar(m2, b2);
+        if (p1 == 0 || p2 == 0) return 0;
+        const int q = p1 * p2;
+        if (prec == BKS_F32) {
+            gttmc(c, t, md, B32[m1].as<float>() + off[m1][b1], kcap[m1], p1,
+                  B32[m2].as<float>() + off[m2][b2], kcap[m2], p2, BKS_F32, P32.ptr, q, s);
+            convert_f32_f64(P32.as<float>(), q, dst, ldd, dim[md], q, s);
+        } else {
+            gttmc(c, t, md, col(m1, off[m1][b1]), kcap[m1], p1, col(m2, off[m2][b2]), kcap[m2], p2,
+                  prec, dst, ldd, s);
+        }
+        return q;
+    }
+
+    void expand(int from_stage) {
+        const int prec = mixed ? BKS_F32 : BKS_F64;
+        const double tau = mixed ? tau32 : tau64;
+        for (int st = from_stage; st <= stages; ++st) {
+            const int src = st - 1;
+            // bars from the blocks existing at the start of the stage
+            int have[3];
+            for (int md = 0; md < 3; ++md) have[md] = (int)w[md].size();
+            for (int md = 0; md < 3; ++md) {
+                int got = 0, o = k[md];
+                if (src < have[other1(md)] && src < have[other2(md)] && k[md] < kcap[md]) {
+                    double *B = P64.as<double>();
+                    const int q = product(md, src, src, prec, B, qcap);
+                    got = q > 0 ? orth_append(md, B, qcap, q, tau) : 0;
+                }
+                off[md].push_back(o);
+                w[md].push_back(got);
+            }
+        }
+    }
+
+    // C = A.(X, Y, Z), column-major k0 x k1 x k2, formed in 20 x 20 blocks
+    // of the first two modes (T = A.(X_a, Y_b)_{1,2}, then Z^T T); the
+    // slices that define the gradient at (U0, V0, W0) are then replaced by
+    // the FP64-accumulated step-(iii) products (see form_core above)
+    void form_core(GCore &G) {
+        const int k0 = k[0], k1 = k[1], k2 = k[2];
+        G.k[0] = k0;
+        G.k[1] = k1;
+        G.k[2] = k2;
+        G.C.assign((size_t)k0 * k1 * k2, 0.0);
+        constexpr int BW = 20;
+        std::vector<double> h((size_t)k2 * BW * BW);
+        for (int a0 = 0; a0 < k0; a0 += BW)
+            for (int b0 = 0; b0 < k1; b0 += BW) {
+                const int pa = std::min(BW, k0 - a0), pb = std::min(BW, k1 - b0), q = pa * pb;
+                if (mixed) {
+                    gttmc(c, t, 2, B32[0].as<float>() + a0, kcap[0], pa, B32[1].as<float>() + b0,
+                          kcap[1], pb, BKS_F32, Tb32.ptr, q, s);
+                    gemm_tn_f32f64(col(2, 0), kcap[2], Tb32.as<float>(), q, dim[2], k2, q,
+                                   Cb.as<double>(), q, c, s);
+                } else {
+                    gttmc(c, t, 2, col(0, a0), kcap[0], pa, col(1, b0), kcap[1], pb, BKS_F64,
+                          Tb64.ptr, q, s);
+                    gemm_tn_f64(col(2, 0), kcap[2], Tb64.as<double>(), q, dim[2], k2, q,
+                                Cb.as<double>(), q, c, s);
+                }
+                d2h(h.data(), Cb.ptr, (size_t)k2 * q);
+                for (int cc = 0; cc < k2; ++cc)
+                    for (int b = 0; b < pb; ++b)
+                        for (int a = 0; a < pa; ++a)
+                            G.C[(a0 + a) + (size_t)k0 * ((b0 + b) + (size_t)k1 * cc)] =
+                                h[(size_t)cc * q + a + pa * b];
+            }
+        // gradient-defining slices from the step-(iii) products: mode md's
+        // product T_md (dim[md] x r_o1 r_o2) projected on basis md gives C
+        // with the other two indices in their leading r
+        for (int md = 0; md < 3; ++md) {
+            const int o1 = other1(md), o2 = other2(md);
+            const int q = r[o1] * r[o2];
+            std::vector<double> P((size_t)k[md] * q);
+            gemm_tn_f64(col(md, 0), kcap[md], T64[md].as<double>(), q, dim[md], k[md], q,
+                        Hd.as<double>(), q, c, s);
+            d2h(P.data(), Hd.ptr, P.size());
+            for (int x = 0; x < k[md]; ++x)
+                for (int b = 0; b < r[o2]; ++b)
+                    for (int a = 0; a < r[o1]; ++a) {
+                        int idx[3];
+                        idx[md] = x;
+                        idx[o1] = a;
+                        idx[o2] = b;
+                        G.C[idx[0] + (size_t)k0 * (idx[1] + (size_t)k1 * idx[2])] =
+                            P[(size_t)x * q + a + r[o1] * b];
+                    }
+        }
+    }
+
+    // U0 = X P, V0 = Y Q, W0 = Z S (eq. tks1), orthonormalised, single blocks
+    void restart(const std::vector<double> Pm[3]) {
+        for (int md = 0; md < 3; ++md) {
+            double *W = W64a.as<double>();
+            h2d(Hd.ptr, Pm[md].data(), Pm[md].size());
+            gemm_nn_f64(col(md, 0), kcap[md], Hd.as<double>(), r[md], dim[md], k[md], r[md], 1.0,
+                        0.0, W, r[md], s);
+            copy2d_f64(W, r[md], col(md, 0), kcap[md], dim[md], r[md], s);
+            reset_basis(md, r[md]);
+        }
+    }
+
+    struct StepOut {
+        double rel = INFINITY, normF = 0.0;
+        std::vector<double> F;  // r0 x r1 x r2 column-major
+        std::vector<double> sv[3];
+    };
+
+    // step (iii)/(iv): one block-Krylov step per mode from (U0, V0, W0)
+    // (FP64 accumulation), the new blocks U1, V1, W1, and Proposition 3.2
+    StepOut bk_step() {
+        StepOut o;
+        const int prec = BKS_F64;
+        for (int md = 0; md < 3; ++md) {
+            const int o1 = other1(md), o2 = other2(md), q = r[o1] * r[o2];
+            gttmc(c, t, md, col(o1, 0), kcap[o1], r[o1], col(o2, 0), kcap[o2], r[o2], prec,
+                  T64[md].ptr, q, s);
+        }
+        // F_(1) = U0^T T_0 : r0 x r1 r2 (column b + r1 c), i.e. F(a, b, c)
+        const int q0 = r[1] * r[2];
+        std::vector<double> F1((size_t)r[0] * q0);
+        gemm_tn_f64(col(0, 0), kcap[0], T64[0].as<double>(), q0, dim[0], r[0], q0, Hd.as<double>(),
+                    q0, c, s);
+        d2h(F1.data(), Hd.ptr, F1.size());
+        o.F.assign((size_t)r[0] * q0, 0.0);
+        double f2 = 0.0;
+        for (int a = 0; a < r[0]; ++a)
+            for (int x = 0; x < q0; ++x) {
+                o.F[a + (size_t)r[0] * x] = F1[(size_t)a * q0 + x];
+                f2 += F1[(size_t)a * q0 + x] * F1[(size_t)a * q0 + x];
+            }
+        o.normF = std::sqrt(f2);
+        auto Fat = [&](int a, int b, int cc) { return o.F[a + (size_t)r[0] * (b + (size_t)r[1] * cc)]; };
+        double g2 = 0.0;
+        for (int md = 0; md < 3; ++md) {
+            const int o1 = other1(md), o2 = other2(md), q = r[o1] * r[o2];
+            double *B = P64.as<double>();
+            copy2d_f64(T64[md].as<double>(), q, B, q, dim[md], q, s);
+            const int kn = orth_append(md, B, q, q, tau64);
+            off[md].push_back(r[md]);
+            w[md].push_back(kn);
+            // H1 = B1^T T_md (kn x q): B1 is orthogonal to U0, so this is
+            // B1^T (I - U0 U0^T) T_md
+            std::vector<double> H1((size_t)kn * q);
+            if (kn > 0) {
+                gemm_tn_f64(col(md, r[md]), kcap[md], T64[md].as<double>(), q, dim[md], kn, q,
+                            Hd.as<double>(), q, c, s);
+                d2h(H1.data(), Hd.ptr, H1.size());
+            }
+            // F_(md): r[md] x q with columns a + r[o1] b
+            std::vector<double> Fm((size_t)r[md] * q);
+            for (int x = 0; x < r[md]; ++x)
+                for (int b = 0; b < r[o2]; ++b)
+                    for (int a = 0; a < r[o1]; ++a) {
+                        int idx[3];
+                        idx[md] = x;
+                        idx[o1] = a;
+                        idx[o2] = b;
+                        Fm[(size_t)x * q + a + r[o1] * b] = Fat(idx[0], idx[1], idx[2]);
+                    }
+            // <H0, H1^md>_{-md} = H1 F_(md)^T
+            for (int i = 0; i < kn; ++i)
+                for (int x = 0; x < r[md]; ++x) {
+                    double acc = 0.0;
+                    for (int y = 0; y < q; ++y) acc += H1[(size_t)i * q + y] * Fm[(size_t)x * q + y];
+                    g2 += acc * acc;
+                }
+            // S-values: singular values of F_(md), then sigma_max(H1)
+            auto svals = [](int rows, int cols, const std::vector<double> &M, int nv) {
+                std::vector<double> G((size_t)rows * rows, 0.0), wv(rows), V((size_t)rows * rows);
+                if (rows > 0) {
+                    la::dgemm(false, true, rows, rows, cols, 1.0, M.data(), cols, M.data(), cols,
+                              0.0, G.data(), rows);
+                    la::sym_eig(rows, G.data(), wv.data(), V.data());
+                }
+                std::vector<double> out;
+                for (int i = 0; i < std::min(nv, rows); ++i) out.push_back(std::sqrt(std::max(wv[i], 0.0)));
+                return out;
+            };
+            o.sv[md] = svals(r[md], q, Fm, r[md]);
+            auto t1 = svals(kn, q, H1, 1);
+            o.sv[md].push_back(t1.empty() ? 0.0 : t1[0]);
+        }
+        o.rel = o.normF > 0 ? std::sqrt(g2) / o.normF : INFINITY;
+        return o;
+    }
+
+    void outputs(double *U, double *V, double *W) {
+        double *outs[3] = {U, V, W};
+        for (int md = 0; md < 3; ++md) {
+            if (!outs[md]) continue;
+            std::vector<double> h((size_t)dim[md] * kcap[md]);
+            d2h(h.data(), B64[md].ptr, h.size());
+            for (int64_t i = 0; i < dim[md]; ++i)
+                for (int j = 0; j < r[md]; ++j)
+                    outs[md][(size_t)j * dim[md] + i] = h[(size_t)i * kcap[md] + j];
+        }
+    }
+};
+
+}  // namespace
+
+int run_gbks(Ctx &c, Tensor &t, const bks_gparams &prm, double *U, double *V, double *W,
+             double *F, bks_info *info, hipStream_t s) {
+    const double t0 = now_s();
+    if (!t.general) fail(BKS_EINVAL, "not a general tensor (use bks_solve)");
+    const int r[3] = {prm.r1, prm.r2, prm.r3};
+    const int64_t dim[3] = {t.l, t.m, t.n};
+    for (int x = 0; x < 3; ++x) {
+        if (r[x] < 1 || r[x] > dim[x] || r[x] > 64) fail(BKS_EINVAL, "need 1 <= r_k <= min(dim_k, 64)");
+        const int o1 = x == 0 ? 1 : 0, o2 = x == 2 ? 1 : 2;
+        if (r[x] > r[o1] * r[o2]) fail(BKS_EINVAL, "need r_k <= product of the other two ranks");
+    }
+    if (prm.precision != BKS_PREC_FP64 && prm.precision != BKS_PREC_MIXED) fail(BKS_EINVAL, "precision");
+    const bool mixed = prm.precision == BKS_PREC_MIXED;
+    const int st = prm.s > 0 ? prm.s : 2, p = prm.p > 0 ? prm.p : 4;
+    const double tol = prm.tol > 0 ? prm.tol : (mixed ? 1e-11 : 1e-13);
+    const double itol = prm.inner_tol > 0 ? prm.inner_tol : 1e-13;
+    const int max_outer = prm.max_outer > 0 ? prm.max_outer : 200;
+    GSolver S(c, t, s, r, p, st, mixed);
+    S.plan();
+    S.allocate();
+    const double *starts[3] = {prm.U0, prm.V0, prm.W0};
+    std::vector<double> h;
+    for (int md = 0; md < 3; ++md) {
+        if (starts[md]) {
+            S.load_start(md, starts[md]);
+        } else {
+            draw_start(prm.seed * 3 + 1 + md, dim[md], r[md], h);
+            S.load_start(md, h.data());
+        }
+    }
+    double te = 0, tc = 0, ti = 0, ts = 0, a = now_s();
+    GSolver::StepOut o = S.bk_step();
+    ts += now_s() - a;
+    a = now_s();
+    S.expand(2);
+    te += now_s() - a;
+    int it = 0;
+    bool conv = false;
+    std::vector<double> rel_hist, f_hist;
+    int last_k[3] = {S.k[0], S.k[1], S.k[2]};
+    while (true) {
+        for (int x = 0; x < 3; ++x) last_k[x] = S.k[x];
+        a = now_s();
+        GCore G;
+        S.form_core(G);
+        tc += now_s() - a;
+        a = now_s();
+        std::vector<double> Pm[3];
+        g_inner(G, r, itol, 5000, false, Pm);
+        // keep the outer objective non-decreasing (eq. Fnon-decr)
+        {
+            std::vector<double> E[3];
+            for (int x = 0; x < 3; ++x) {
+                E[x].assign((size_t)G.k[x] * r[x], 0.0);
+                for (int j = 0; j < r[x]; ++j) E[x][(size_t)j * r[x] + j] = 1.0;
+            }
+            const std::vector<double> *pp[3] = {&Pm[0], &Pm[1], &Pm[2]};
+            const std::vector<double> *pe[3] = {&E[0], &E[1], &E[2]};
+            double g_new = 0, g_cur = 0;
+            g_gradient(G, pp, r, &g_new);
+            g_gradient(G, pe, r, &g_cur);
+            if (g_new < g_cur * (1.0 - 1e-14)) g_inner(G, r, itol, 5000, true, Pm);
+        }
+        ti += now_s() - a;
+        a = now_s();
+        S.restart(Pm);
+        o = S.bk_step();
+        ts += now_s() - a;
+        ++it;
+        rel_hist.push_back(o.rel);
+        f_hist.push_back(o.normF);
+        if (o.rel <= tol) {
+            conv = true;
+            break;
+        }
+        if (it >= max_outer) break;
+        a = now_s();
+        S.expand(2);
+        te += now_s() - a;
+    }
+    S.outputs(U, V, W);
+    if (F) std::copy(o.F.begin(), o.F.end(), F);
+    if (info) {
+        info->outer_iters = it;
+        info->converged = conv ? 1 : 0;
+        info->k1 = last_k[0];
+        info->k3 = last_k[2];
+        info->rel_grad = o.rel;
+        info->normF = o.normF;
+        info->normA = std::sqrt(t.frob2);
+        for (int i = 0; i < 65; ++i) {
+            info->svals1[i] = i < (int)o.sv[0].size() ? o.sv[0][i] : 0.0;
+            info->svals2[i] = i < (int)o.sv[1].size() ? o.sv[1][i] : 0.0;
+            info->svals3[i] = i < (int)o.sv[2].size() ? o.sv[2][i] : 0.0;
+        }
+        info->t_expand = te;
+        info->t_core = tc;
+        info->t_inner = ti;
+        info->t_step = ts;
+        info->t_total = now_s() - t0;
+        info->n_hist = (int)std::min<size_t>(512, rel_hist.size());
+        for (int i = 0; i < info->n_hist; ++i) {
+            info->rel_hist[i] = rel_hist[i];
+            info->normF_hist[i] = f_hist[i];
+        }
+    }
+    return conv ? BKS_OK : BKS_ENOTCONV;
+}
+
 }  // namespace bks
 
 using namespace bks;
@@ -1130,6 +1776,18 @@ int bks_solve(bks_ctx ctx, bks_tensor t, const bks_params *prm, double *U, doubl
         HIPCHECK(hipSetDevice(c->device));
         if (info) std::memset(info, 0, sizeof(*info));
         return run_bks(*c, *reinterpret_cast<Tensor *>(t), *prm, U, W, F, info, c->stream);
+    });
+}
+
+int bks_gsolve(bks_ctx ctx, bks_tensor t, const bks_gparams *prm, double *U, double *V, double *W,
+               double *F, bks_info *info) {
+    if (!ctx || !t || !prm) return BKS_EINVAL;
+    return guard_solve(ctx, [&] {
+        Ctx *c = reinterpret_cast<Ctx *>(ctx);
+        std::lock_guard<std::mutex> g(c->mu);
+        HIPCHECK(hipSetDevice(c->device));
+        if (info) std::memset(info, 0, sizeof(*info));
+        return run_gbks(*c, *reinterpret_cast<Tensor *>(t), *prm, U, V, W, F, info, c->stream);
     });
 }
 

@@ -1,5 +1,5 @@
 // Tensor-times-block products over a stored (1,2)-symmetric tensor
-// (Section 2.2 mode products; Algorithm 3 step (i); Section 3.3.1).
+// (section "Multilinear tensor-matrix multiplication" mode products; Algorithm 3 step (i); section "Block-Krylov methods for (1,2)-symmetric tensors").
 //
 //   FREE3  T3(k, a + px*b) = sum_{stored (i<=j,k,v)} v*(X(i,a)Y(j,b) + [i!=j] X(j,a)Y(i,b))
 //          sym-half (Y = X): columns b*(b+1)/2 + a, a <= b (triunfold_3)
@@ -21,6 +21,7 @@
 // output tile pair) stages the gathered factor rows of 32 entries at a time
 // in LDS and accumulates a 4x4 register tile per thread.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 
 #include "bks_internal.h"
@@ -277,7 +278,7 @@ __global__ __launch_bounds__(64) void ttmc_wave(
                 pc[u] = i32x2{0, ck[b0 + x]};
             else
                 pc[u] = cp[b0 + x];
-            pv[u] = val[b0 + x];
+            pv[u] = val ? val[b0 + x] : VT(1);
         }
     };
     if (beg < end) fetch(beg);
@@ -428,6 +429,167 @@ __global__ __launch_bounds__(256) void pack_blocks(const CT *__restrict__ F, int
         const int col = t * P + u;
         out[x] = (u < P && col < p) ? F[r * ld + col] : CT(0);
     }
+}
+
+// ---------------------------------------------------------------- register-direct
+// Narrow products with the whole output block of a segment in each lane's
+// registers (P1 x P2 accumulators, the upper triangle only for a symmetric
+// half).  A group of L lanes (a power of two, from the item) takes one
+// segment and strides its entries, so the group's loads of indices and
+// values are coalesced; each lane gathers its entries' factor rows straight
+// into registers with aligned 16-byte loads from the block-packed copies,
+// U entries at a time so that their loads are in flight together.  The group
+// then sums its lanes with cross-lane shuffles in a fixed butterfly order
+// (deterministic) and its first lane writes the row, or, for a chunk of a
+// split segment, the chunk's partial slot.  Four independent waves per
+// workgroup, one item per wave.
+template <typename CT, int P>
+__device__ __forceinline__ void row_load(const CT *__restrict__ F, int64_t row, int W,
+                                         CT (&r)[P]) {
+    using VT4 = typename Vec<CT>::T;
+    constexpr int V = Vec<CT>::V;
+    constexpr int NV = (P + V - 1) / V;
+    const VT4 *p = reinterpret_cast<const VT4 *>(F + row * W);
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+        const VT4 x = p[u];
+#pragma unroll
+        for (int t = 0; t < V; ++t)
+            if (u * V + t < P) r[u * V + t] = x[t];
+    }
+}
+
+template <typename VT, typename CT, int MODE, int P1, int P2, bool SYM, int U>
+__global__ __launch_bounds__(256) void ttmc_reg(
+    const Item *__restrict__ items, int64_t nitems, const int64_t *__restrict__ segptr,
+    const int2 *__restrict__ c12, const int32_t *__restrict__ ck, const VT *__restrict__ val,
+    const CT *__restrict__ F1, int W1, const CT *__restrict__ F2, int W2, CT *__restrict__ out,
+    int64_t ldo, CT *__restrict__ partial, int q) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wi >= nitems) return;
+    const Item it = items[wi];
+    const bool heavy = it.seg_end < 0;
+    const int L = heavy ? 64 : it.pad;
+    const int gl = lane & (L - 1);
+    const int64_t seg = heavy ? (int64_t)it.seg : (int64_t)it.seg + lane / L;
+    const bool own = heavy || seg < it.seg_end;
+    int64_t beg = 0, end = 0;
+    if (heavy) {
+        beg = it.beg;
+        end = it.end;
+    } else if (own) {
+        beg = segptr[seg];
+        end = segptr[seg + 1];
+    }
+
+    CT acc[P1][P2];
+#pragma unroll
+    for (int a = 0; a < P1; ++a)
+#pragma unroll
+        for (int b = 0; b < P2; ++b) acc[a][b] = CT(0);
+
+    for (int64_t e0 = beg + gl; e0 < end; e0 += (int64_t)L * U) {
+        // U entries per lane: indices and values first (clamped into the
+        // segment, weight 0 past its end), then every row gather, then the
+        // products
+        i32x2 c[U];
+        CT v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t e = e0 + (int64_t)L * u;
+            const int64_t ec = e < end ? e : e0;
+            if constexpr (MODE == MODE_M3)
+                c[u] = i32x2{0, ck[ec]};
+            else
+                c[u] = reinterpret_cast<const i32x2 *>(c12)[ec];
+            const CT x = val ? static_cast<CT>(val[ec]) : CT(1);
+            v[u] = e < end ? x : CT(0);
+        }
+        if constexpr (MODE == MODE_M3) {
+            CT z[U][P2];
+#pragma unroll
+            for (int u = 0; u < U; ++u) row_load<CT, P2>(F2, c[u].y, W2, z[u]);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int b = 0; b < P2; ++b) acc[0][b] = fma(v[u], z[u][b], acc[0][b]);
+        } else if constexpr (MODE == MODE_ONE) {
+            CT y[U][P1], z[U][P2];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                row_load<CT, P1>(F1, c[u].x, W1, y[u]);
+                row_load<CT, P2>(F2, c[u].y, W2, z[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int a = 0; a < P1; ++a) {
+                    const CT x = v[u] * y[u][a];
+#pragma unroll
+                    for (int b = 0; b < P2; ++b) acc[a][b] = fma(x, z[u][b], acc[a][b]);
+                }
+        } else {
+            // v X(i,:)^T Y(j,:) and, off the diagonal, the mirrored entry's
+            // v X(j,:)^T Y(i,:)
+            CT xi[U][P1], xj[U][P1];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                row_load<CT, P1>(F1, c[u].x, W1, xi[u]);
+                row_load<CT, P1>(F1, c[u].y, W1, xj[u]);
+            }
+            if constexpr (SYM) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const CT w = c[u].x != c[u].y ? v[u] : CT(0);
+#pragma unroll
+                    for (int a = 0; a < P1; ++a) {
+                        const CT x1 = v[u] * xi[u][a], x2 = w * xj[u][a];
+#pragma unroll
+                        for (int b = a; b < P2; ++b)
+                            acc[a][b] = fma(x2, xi[u][b], fma(x1, xj[u][b], acc[a][b]));
+                    }
+                }
+            } else {
+                CT yi[U][P2], yj[U][P2];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    row_load<CT, P2>(F2, c[u].x, W2, yi[u]);
+                    row_load<CT, P2>(F2, c[u].y, W2, yj[u]);
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const CT w = c[u].x != c[u].y ? v[u] : CT(0);
+#pragma unroll
+                    for (int a = 0; a < P1; ++a) {
+                        const CT x1 = v[u] * xi[u][a], x2 = w * xj[u][a];
+#pragma unroll
+                        for (int b = 0; b < P2; ++b)
+                            acc[a][b] = fma(x2, yi[u][b], fma(x1, yj[u][b], acc[a][b]));
+                    }
+                }
+            }
+        }
+    }
+
+    // butterfly sum over the group's lanes (all lanes of the wave take part,
+    // each group within itself)
+    for (int off = L >> 1; off > 0; off >>= 1)
+#pragma unroll
+        for (int a = 0; a < P1; ++a)
+#pragma unroll
+            for (int b = 0; b < P2; ++b)
+                if (!SYM || a <= b) acc[a][b] += __shfl_xor(acc[a][b], off, 64);
+    if (!own || gl != 0) return;
+    CT *dst = (heavy && it.slot >= 0) ? partial + (int64_t)it.slot * q : out + seg * ldo;
+#pragma unroll
+    for (int a = 0; a < P1; ++a)
+#pragma unroll
+        for (int b = 0; b < P2; ++b) {
+            if (SYM && a > b) continue;
+            const int col = MODE == MODE_M3 ? b : (SYM ? b * (b + 1) / 2 + a : a + P1 * b);
+            dst[col] = acc[a][b];
+        }
 }
 
 // Sum the partial rows of one split segment: 256 threads as (slot lane,
@@ -842,6 +1004,142 @@ __global__ __launch_bounds__(512) void ttmc_sym_gram_mfma(const Item *__restrict
     }
 }
 
+// The same product for widths beyond 12 tiles (k1 > 192): the T x T tiles
+// of M are cut into TR x TC blocks, one workgroup per (slice chunk, block);
+// block (R, C) stages only the rows X(i, R-block) and X(j, C-block) of each
+// chunk and writes its part of the chunk's partial M (full p x p per slot,
+// summed and symmetrised by sym_gram_reduce as above).  Xp rows hold T16
+// tiles (16 T16 floats); tiles past T16 of the last blocks are skipped.
+template <typename VT, int TR, int TC, int ROWS>
+__global__ __launch_bounds__(256) void ttmc_sym_gram_mfma_blk(
+    const Item *__restrict__ items, const int2 *__restrict__ c12, const VT *__restrict__ val,
+    const float *__restrict__ Xp, int T16, int Wli, int Wlj, int p, float *__restrict__ part) {
+    constexpr int UI = 4 * TR, UJ = 4 * TC;     // 16-byte units of the staged rows
+    constexpr int NW = (TR + ROWS - 1) / ROWS;
+    constexpr int NTH = 64 * NW;
+    constexpr int NG = kMfmaChunk * (UI + UJ);  // row gathers per chunk
+    constexpr int NQ = (NG + NTH - 1) / NTH;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    float *s_xi = reinterpret_cast<float *>(lds_raw);  // [kMfmaChunk][Wli]
+    float *s_xj = s_xi + kMfmaChunk * Wli;             // [kMfmaChunk][Wlj]
+    float *s_v = s_xj + kMfmaChunk * Wlj;              // [2][kMfmaChunk]
+    i32x2 *s_ij = reinterpret_cast<i32x2 *>(s_v + 2 * kMfmaChunk);
+    const i32x2 *__restrict__ cp = reinterpret_cast<const i32x2 *>(c12);
+    const int W = 16 * T16;
+    const int nbc = (T16 + TC - 1) / TC;
+    const int R0 = (int)(blockIdx.y / nbc) * TR, C0 = (int)(blockIdx.y % nbc) * TC;
+
+    const Item it = items[blockIdx.x];
+    const int64_t beg = it.beg, end = it.end;
+    const int nchunk = (int)((end - beg + kMfmaChunk - 1) / kMfmaChunk);
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int kq = lane >> 4, rc = lane & 15;
+    f32x4v acc[ROWS][TC];
+#pragma unroll
+    for (int a = 0; a < ROWS; ++a)
+#pragma unroll
+        for (int J = 0; J < TC; ++J) acc[a][J] = f32x4v{0.f, 0.f, 0.f, 0.f};
+
+    i32x2 nidx = i32x2{0, 0};
+    float nv = 0.f;
+    bool nin = false;
+    auto fetch_idx = [&](int ch) {
+        if (tid < kMfmaChunk) {
+            const int64_t e = beg + (int64_t)ch * kMfmaChunk + tid;
+            nin = e < end;
+            const int64_t ec = nin ? e : end - 1;
+            nidx = cp[ec];
+            nv = static_cast<float>(val[ec]);
+        }
+    };
+    auto commit_idx = [&](int buf) {
+        if (tid < kMfmaChunk) {
+            float v = nin ? nv : 0.f;
+            if (nidx.x == nidx.y) v *= 0.5f;
+            s_ij[buf * kMfmaChunk + tid] = nidx;
+            s_v[buf * kMfmaChunk + tid] = v;
+        }
+    };
+    // gather x: unit u of the staged part of row X(i,:) (u < UI, tiles
+    // R0..) or of X(j,:) (u >= UI, tiles C0..) of entry e; units past the
+    // packed row (the last blocks' missing tiles) re-read unit 0
+    f32x4v g[NQ];
+    int lo[NQ];
+    auto fetch_rows = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int x = min(tid + q * NTH, NG - 1);
+            const int e = x / (UI + UJ), rem = x - e * (UI + UJ);
+            const bool wj = rem >= UI;
+            const int u = wj ? rem - UI : rem;
+            const int col4 = (wj ? C0 : R0) * 4 + u;     // unit within the packed row
+            const i32x2 c = s_ij[buf * kMfmaChunk + e];
+            const int uc = col4 < 4 * T16 ? col4 : 0;
+            g[q] = reinterpret_cast<const f32x4v *>(Xp + (int64_t)(wj ? c.y : c.x) * W)[uc];
+            lo[q] = wj ? kMfmaChunk * Wli + e * Wlj + 4 * u : e * Wli + 4 * u;
+        }
+    };
+    auto commit_rows = [&]() {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (NG % NTH == 0 || tid + q * NTH < NG)
+                *reinterpret_cast<f32x4v *>(s_xi + lo[q]) = g[q];
+    };
+
+    fetch_idx(0);
+    commit_idx(0);
+    fetch_idx(1);
+    commit_idx(1);
+    __syncthreads();
+    fetch_rows(0);
+    fetch_idx(2);
+    commit_rows();
+    __syncthreads();
+    for (int ch = 0; ch < nchunk; ++ch) {
+        const bool more = ch + 1 < nchunk;
+        if (more) fetch_rows((ch + 1) & 1);
+        const int cnt = (int)min<int64_t>(kMfmaChunk, end - beg - (int64_t)ch * kMfmaChunk);
+        const int nk = (cnt + 3) >> 2;
+        const float *sv = s_v + (ch & 1) * kMfmaChunk;
+        for (int kk = 0; kk < nk; ++kk) {
+            const int e = kk * 4 + kq;
+            const float ve = sv[e];
+            float a[ROWS], b[TC];
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                const int I = wave * ROWS + r;
+                a[r] = I < TR ? s_xi[e * Wli + I * 16 + rc] * ve : 0.f;
+            }
+#pragma unroll
+            for (int J = 0; J < TC; ++J) b[J] = s_xj[e * Wlj + J * 16 + rc];
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+                for (int J = 0; J < TC; ++J)
+                    acc[r][J] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r], b[J], acc[r][J], 0, 0, 0);
+        }
+        __syncthreads();
+        if (more) commit_rows();
+        commit_idx(ch & 1);
+        fetch_idx(ch + 3);
+        __syncthreads();
+    }
+    float *o = part + (int64_t)it.slot * p * p;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int I = wave * ROWS + r;
+        if (I >= TR) break;
+#pragma unroll
+        for (int J = 0; J < TC; ++J)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = (R0 + I) * 16 + 4 * kq + i, col = (C0 + J) * 16 + rc;
+                if (row < p && col < p) o[(int64_t)row * p + col] = acc[r][J][i];
+            }
+    }
+}
+
 // ---------------------------------------------------------------- dispatch
 template <typename VT, typename CT, int PA, int PB, int MODE>
 void launch_wave(dim3 grid, size_t lds, hipStream_t s, const Item *items,
@@ -1001,9 +1299,148 @@ bool choose_gram(int p, bool dbl, int &R, int &T) {
 constexpr int kWideThreshold = 24;
 constexpr int kWideThresholdPublic = kWideThreshold;
 
-static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, int p1,
+// Device workspace of one product call: regions 0 and 1 hold block-packed
+// factor copies, 2 the partial rows of split segments, 3 intermediate
+// products; plus the call's schedule.
+struct TtmcWs {
+    virtual ~TtmcWs() = default;
+    virtual void *get(int which, size_t bytes) = 0;
+    virtual SchedView sched(Tensor &t, int order, int E, hipStream_t s) = 0;
+    virtual bool allow_wide() const = 0;
+};
+
+// The ctx's grow-only buffers and the tensor's cached device schedules.
+struct CtxWs final : TtmcWs {
+    Ctx &c;
+    explicit CtxWs(Ctx &c_) : c(c_) {}
+    void *get(int which, size_t bytes) override {
+        DevBuf *b[4] = {&c.ws_fac1, &c.ws_fac2, &c.ws_partial, &c.ws_tmp};
+        b[which]->ensure(bytes);
+        return b[which]->ptr;
+    }
+    SchedView sched(Tensor &t, int order, int E, hipStream_t) override {
+        const Schedule &sc = t.schedule(order, E);
+        SchedView v;
+        v.nitems = sc.nitems;
+        v.nfix = sc.nfix;
+        v.nslots = sc.nslots;
+        v.items = sc.items.as<Item>();
+        v.fix = sc.fix.as<Fixup>();
+        for (const auto &L : sc.levels) v.levels.emplace_back(L->nfix, L->fix.as<Fixup>());
+        return v;
+    }
+    bool allow_wide() const override { return true; }
+};
+
+static void ttmc_launch(TtmcWs &ws, Tensor &t, int op, const void *B1, int64_t ld1, int p1,
                         const void *B2, int64_t ld2, int p2, bool sym_half, int prec, void *out,
                         int64_t ldo, hipStream_t s, hipEvent_t *mk = nullptr);
+
+// What every segmented narrow product of one call shares.
+struct NarrowArgs {
+    TtmcWs &ws;
+    Tensor &t;
+    hipStream_t s;
+    int prec;
+    bool val64, dbl;
+    size_t cts;
+    hipEvent_t *mk;  // profiling: events around the call's main kernels, or NULL
+    void mark(int w) {
+        if (mk) HIPCHECK(hipEventRecord(mk[w], s));
+    }
+};
+static void narrow(NarrowArgs &A, int mode, const Segmented &o, int fmt, const void *val,
+                   const void *F1, int64_t l1, int64_t rows1, int px, const void *F2, int64_t l2,
+                   int64_t rows2, int py, int outmode, int q, void *out, int64_t ldo, bool first,
+                   bool last);
+
+// Register-direct launchers, by precision, mode and widths (NULL where the
+// kernel does not apply: more accumulators than a lane should hold).
+using RegLauncher = void (*)(dim3, hipStream_t, const Item *, int64_t, const int64_t *,
+                             const int2 *, const int32_t *, const void *, const void *, int,
+                             const void *, int, void *, int64_t, void *, int);
+
+template <typename CT, int MODE, int P1, int P2, bool SYM>
+constexpr int reg_unroll() {
+    constexpr int V = Vec<CT>::V;
+    constexpr int r1 = (P1 + V - 1) / V * V * (int)sizeof(CT) / 4;
+    constexpr int r2 = (P2 + V - 1) / V * V * (int)sizeof(CT) / 4;
+    constexpr int per = 3 + (MODE == MODE_M3 ? r2
+                                             : (MODE == MODE_ONE ? r1 + r2 : (SYM ? 2 * r1 : 2 * r1 + 2 * r2)));
+    constexpr int u = 80 / per;
+    return u < 1 ? 1 : (u > 8 ? 8 : u);
+}
+
+template <typename VT, typename CT, int MODE, int P1, int P2, bool SYM>
+void launch_reg(dim3 grid, hipStream_t s, const Item *items, int64_t nitems, const int64_t *segptr,
+                const int2 *c12, const int32_t *ck, const void *val, const void *F1, int W1,
+                const void *F2, int W2, void *out, int64_t ldo, void *partial, int q) {
+    constexpr int U = reg_unroll<CT, MODE, P1, P2, SYM>();
+    hipLaunchKernelGGL((ttmc_reg<VT, CT, MODE, P1, P2, SYM, U>), grid, dim3(256), 0, s, items,
+                       nitems, segptr, c12, ck, static_cast<const VT *>(val),
+                       static_cast<const CT *>(F1), W1, static_cast<const CT *>(F2), W2,
+                       static_cast<CT *>(out), ldo, static_cast<CT *>(partial), q);
+}
+
+constexpr int kRegDefaultMask = 8;
+constexpr int kRegMaxP = 5;   // rectangular blocks up to 5 x 5
+constexpr int kRegMaxSym = 6; // symmetric halves up to 6 (21 accumulators)
+constexpr int kRegMaxM3 = 8;  // mode-3 rows up to 8
+
+template <typename VT, typename CT>
+struct RegTable {
+    RegLauncher two[kRegMaxP][kRegMaxP], one[kRegMaxP][kRegMaxP], sym[kRegMaxSym], m3[kRegMaxM3];
+    RegTable() {
+        rect<1, 1>();
+        syms<1>();
+        m3s<1>();
+    }
+    template <int A, int B>
+    void rect() {
+        two[A - 1][B - 1] = &launch_reg<VT, CT, MODE_TWO, A, B, false>;
+        one[A - 1][B - 1] = &launch_reg<VT, CT, MODE_ONE, A, B, false>;
+        if constexpr (B < kRegMaxP) rect<A, B + 1>();
+        else if constexpr (A < kRegMaxP) rect<A + 1, 1>();
+    }
+    template <int A>
+    void syms() {
+        sym[A - 1] = &launch_reg<VT, CT, MODE_TWO, A, A, true>;
+        if constexpr (A < kRegMaxSym) syms<A + 1>();
+    }
+    template <int B>
+    void m3s() {
+        m3[B - 1] = &launch_reg<VT, CT, MODE_M3, 1, B, false>;
+        if constexpr (B < kRegMaxM3) m3s<B + 1>();
+    }
+    RegLauncher get(int mode, bool sy, int px, int py) const {
+        if (mode == MODE_M3) return py <= kRegMaxM3 ? m3[py - 1] : nullptr;
+        if (mode == MODE_TWO && sy) return px <= kRegMaxSym ? sym[px - 1] : nullptr;
+        if (px > kRegMaxP || py > kRegMaxP) return nullptr;
+        return mode == MODE_TWO ? two[px - 1][py - 1] : one[px - 1][py - 1];
+    }
+};
+
+// Which products take the register-direct kernel (the LDS-staged one
+// otherwise): bit 0 FREE3 symmetric half, bit 1 FREE3 X != Y, bit 2 MODE3
+// (also step 1 of FREE1), bit 3 step 2 of FREE1.  BKS_NARROW_REG overrides
+// the default (read once; results differ only by rounding order).
+int reg_mask() {
+    static const int mask = [] {
+        const char *e = std::getenv("BKS_NARROW_REG");
+        return e ? std::atoi(e) : kRegDefaultMask;
+    }();
+    return mask;
+}
+
+RegLauncher reg_pick(int prec, bool val64, int mode, bool sym, int px, int py) {
+    const int bit = mode == MODE_TWO ? (sym ? 1 : 2) : (mode == MODE_M3 ? 4 : 8);
+    if (!(reg_mask() & bit)) return nullptr;
+    static const RegTable<float, float> f;
+    static const RegTable<double, double> d;
+    static const RegTable<float, double> fd;
+    if (prec == BKS_F32) return f.get(mode, sym, px, py);
+    return val64 ? d.get(mode, sym, px, py) : fd.get(mode, sym, px, py);
+}
 
 // Algorithmic traffic and flops of one product: the stored tensor read once
 // (two 4-byte indices and the value per stored entry; the mode-3 product
@@ -1034,8 +1471,9 @@ static void ttmc_cost(const Tensor &t, int op, int p1, int p2, bool sym, bool sa
 
 void ttmc(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, int p1, const void *B2,
           int64_t ld2, int p2, bool sym_half, int prec, void *out, int64_t ldo, hipStream_t s) {
+    CtxWs ws(c);
     if (!c.prof) {
-        ttmc_launch(c, t, op, B1, ld1, p1, B2, ld2, p2, sym_half, prec, out, ldo, s);
+        ttmc_launch(ws, t, op, B1, ld1, p1, B2, ld2, p2, sym_half, prec, out, ldo, s);
         return;
     }
     // two classes per product: `name` times its main kernel alone (what a
@@ -1047,13 +1485,50 @@ void ttmc(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, int p1, const 
     HIPCHECK(hipEventCreate(&mk[0]));
     HIPCHECK(hipEventCreate(&mk[1]));
     HIPCHECK(hipEventRecord(a, s));
-    ttmc_launch(c, t, op, B1, ld1, p1, B2, ld2, p2, sym_half, prec, out, ldo, s, mk);
+    ttmc_launch(ws, t, op, B1, ld1, p1, B2, ld2, p2, sym_half, prec, out, ldo, s, mk);
     HIPCHECK(hipEventRecord(b, s));
     std::string name;
     double bytes, flops;
     ttmc_cost(t, op, p1, p2, sym_half, B2 == nullptr || B2 == B1, prec, name, bytes, flops);
     c.prof_record(name, mk[0], mk[1], bytes, flops);
     c.prof_record(name + "_call", a, b, bytes, flops);
+}
+
+void gttmc(Ctx &c, Tensor &t, int mode, const void *B1, int64_t ld1, int p1, const void *B2,
+           int64_t ld2, int p2, int prec, void *out, int64_t ldo, hipStream_t s) {
+    if (!t.general) fail(BKS_EINVAL, "not a general tensor (use bks_ttmc)");
+    if (mode < 0 || mode > 2) fail(BKS_EINVAL, "mode must be 0, 1 or 2");
+    if (prec != BKS_F32 && prec != BKS_F64 && prec != BKS_F32IN_F64ACC)
+        fail(BKS_EINVAL, "unknown precision");
+    if (!B1 || !B2 || p1 < 1 || p2 < 1 || ld1 < p1 || ld2 < p2) fail(BKS_EINVAL, "bad factors");
+    if (!out || ldo < (int64_t)p1 * p2) fail(BKS_EINVAL, "bad output");
+    const int64_t dims[3] = {t.l, t.m, t.n};
+    const int64_t rows1 = dims[mode == 0 ? 1 : 0], rows2 = dims[mode == 2 ? 1 : 2];
+    const bool dbl = prec != BKS_F32;
+    const bool val64 = prec == BKS_F64 && t.has64;
+    const Segmented &o = t.g[mode];
+    const void *val = val64 ? o.v64.ptr : o.v32.ptr;
+    CtxWs ws(c);
+    hipEvent_t a = nullptr, b = nullptr, mk[2] = {nullptr, nullptr};
+    if (c.prof) {
+        for (hipEvent_t *e : {&a, &b, &mk[0], &mk[1]}) HIPCHECK(hipEventCreate(e));
+        HIPCHECK(hipEventRecord(a, s));
+    }
+    NarrowArgs na{ws, t, s, prec, val64, dbl, dbl ? (size_t)8 : (size_t)4, c.prof ? mk : nullptr};
+    narrow(na, MODE_ONE, o, 4 + mode, val, B1, ld1, rows1, p1, B2, ld2, rows2, p2, OUT_RECT,
+           p1 * p2, out, ldo, true, true);
+    if (c.prof) {
+        HIPCHECK(hipEventRecord(b, s));
+        // algorithmic traffic: the entry stream once (two indices, value),
+        // both factors and the output once
+        const double vb = val64 ? 8.0 : 4.0, eb = dbl ? 8.0 : 4.0;
+        const double bytes = t.nnz * (8.0 + vb) + (rows1 * p1 + rows2 * p2) * eb +
+                             (double)dims[mode] * p1 * p2 * eb;
+        const double flops = 2.0 * t.nnz * p1 * p2;
+        const std::string name = "gmode" + std::to_string(mode + 1) + (dbl ? "_f64" : "_f32");
+        c.prof_record(name, mk[0], mk[1], bytes, flops);
+        c.prof_record(name + "_call", a, b, bytes, flops);
+    }
 }
 
 void Ctx::prof_record(const std::string &name, hipEvent_t a, hipEvent_t b, double bytes,
@@ -1081,7 +1556,7 @@ void Ctx::prof_flush() {
     }
 }
 
-static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, int p1,
+static void ttmc_launch(TtmcWs &ws, Tensor &t, int op, const void *B1, int64_t ld1, int p1,
                         const void *B2, int64_t ld2, int p2, bool sym_half, int prec, void *out,
                         int64_t ldo, hipStream_t s, hipEvent_t *mk) {
     // mk (profiling): events recorded right around the product's main kernel
@@ -1145,8 +1620,9 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
         fail(BKS_EINVAL, "unknown op");
     }
     if (!out) fail(BKS_EINVAL, "null output");
-    const Segmented &o = order == 0 ? t.o3 : (order == 1 ? t.o1 : t.op);
-    if (o.nseg == 0) {
+    if (t.general) fail(BKS_EINVAL, "a general tensor: use bks_gttmc");
+    const Segmented &o = order == 0 ? t.o3 : t.op;
+    if (op != BKS_FREE1 && o.nseg == 0) {
         mark(0);
         mark(1);
         return;
@@ -1154,10 +1630,16 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
     const void *val = val64 ? o.v64.ptr : o.v32.ptr;
 
     if (op == BKS_FREE3 && outmode == OUT_SYM && px > kWideThreshold) {
+        if (!ws.allow_wide())
+            fail(BKS_EINVAL, "symmetric halves wider than " + std::to_string(kWideThreshold) +
+                                 " columns need bks_ttmc (the allocation-free entry point "
+                                 "runs the narrow products only)");
         int R, T;
         // FP32: the matrix-core kernel (tiles of 16) for widths up to 192
         const int T16 = (px + 15) / 16;
-        const bool mfma = prec == BKS_F32 && T16 >= 2 && T16 <= 12;
+        // beyond 12 tiles: the same matrix-core product in 8 x 8-tile blocks
+        const bool blocked = prec == BKS_F32 && T16 > 12;
+        const bool mfma = prec == BKS_F32 && T16 >= 2;
         if (mfma) {
             R = 16;
             T = T16;
@@ -1173,8 +1655,9 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
             int64_t cw64 = std::min<int64_t>(2048, std::max<int64_t>(256, t.nnz / kGramItems));
             cw64 = std::max<int64_t>(cw64, t.nnz / std::max<int64_t>(1, max_items - o.nseg) + 1);
             const int CW = (int)std::min<int64_t>(cw64, 1 << 30);
-            const Schedule &sc = t.schedule(kWideOrder, CW);
-            c.ws_fac1.ensure((size_t)std::max<int64_t>(t.m, 1) * W * cts);
+            const SchedView sc = ws.sched(t, kWideOrder, CW, s);
+            void *fac = ws.get(0, (size_t)std::max<int64_t>(t.m, 1) * W * cts);
+            void *part = sc.nitems > 0 ? ws.get(2, (size_t)sc.nitems * px * px * cts) : nullptr;
             {
                 const int64_t total = t.m * W;
                 const unsigned grid = (unsigned)std::max<int64_t>(
@@ -1182,14 +1665,37 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
                 if (dbl)
                     hipLaunchKernelGGL(pack_blocks<double>, dim3(grid), dim3(256), 0, s,
                                        static_cast<const double *>(F1), l1, t.m, px, R, RP, W,
-                                       c.ws_fac1.as<double>());
+                                       static_cast<double *>(fac));
                 else
                     hipLaunchKernelGGL(pack_blocks<float>, dim3(grid), dim3(256), 0, s,
                                        static_cast<const float *>(F1), l1, t.m, px, R, RP, W,
-                                       c.ws_fac1.as<float>());
+                                       static_cast<float *>(fac));
                 HIPCHECK(hipGetLastError());
             }
-            if (sc.nitems > 0) c.ws_partial.ensure((size_t)sc.nitems * px * px * cts);
+            if (blocked) {
+                constexpr int TB = 8;
+                const int nb = (T16 + TB - 1) / TB;
+                const int Wb = TB * 16 + ((16 - (TB * 16) % 64) + 64) % 64;
+                const size_t lds_b = (size_t)(2 * kMfmaChunk * Wb + 2 * kMfmaChunk) * 4 +
+                                     (size_t)2 * kMfmaChunk * 8;
+                mark(0);
+                if (sc.nitems > 0) {
+                    hipLaunchKernelGGL((ttmc_sym_gram_mfma_blk<float, TB, TB, 2>),
+                                       dim3((unsigned)sc.nitems, (unsigned)(nb * nb)),
+                                       dim3(64 * (TB / 2)), lds_b, s, sc.items, o.c1.as<int2>(),
+                                       o.v32.as<float>(), static_cast<const float *>(fac), T16,
+                                       Wb, Wb, px, static_cast<float *>(part));
+                    HIPCHECK(hipGetLastError());
+                }
+                mark(1);
+                if (sc.nfix > 0) {
+                    hipLaunchKernelGGL(sym_gram_reduce<float>, dim3((unsigned)sc.nfix), dim3(256), 0,
+                                       s, sc.fix, static_cast<const float *>(part), px,
+                                       static_cast<float *>(out), ldo);
+                    HIPCHECK(hipGetLastError());
+                }
+                return;
+            }
             if (mfma) {
                 // row stride with (Wl * 4) % 256 == 64: the four 16-float rows a
                 // K-step reads fall in different banks
@@ -1198,16 +1704,17 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
                                      (size_t)2 * kMfmaChunk * 8;
                 mark(0);
                 if (sc.nitems > 0) {
-                    if (!launch_gram_mfma(T, dim3((unsigned)sc.nitems), lds_m, s, sc.items.as<Item>(),
-                                          o.c1.as<int2>(), o.v32.as<float>(), c.ws_fac1.as<float>(),
-                                          Wl, px, c.ws_partial.as<float>()))
+                    if (!launch_gram_mfma(T, dim3((unsigned)sc.nitems), lds_m, s, sc.items,
+                                          o.c1.as<int2>(), o.v32.as<float>(),
+                                          static_cast<const float *>(fac), Wl, px,
+                                          static_cast<float *>(part)))
                         fail(BKS_EINVAL, "no matrix-core kernel for this width");
                     HIPCHECK(hipGetLastError());
                 }
                 mark(1);
                 if (sc.nfix > 0) {
                     hipLaunchKernelGGL(sym_gram_reduce<float>, dim3((unsigned)sc.nfix), dim3(256), 0,
-                                       s, sc.fix.as<Fixup>(), c.ws_partial.as<float>(), px,
+                                       s, sc.fix, static_cast<const float *>(part), px,
                                        static_cast<float *>(out), ldo);
                     HIPCHECK(hipGetLastError());
                 }
@@ -1221,20 +1728,20 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
             if (sc.nitems > 0) {
                 const dim3 grid((unsigned)sc.nitems);
                 if (prec == BKS_F32)
-                    ok = launch_gram_r<float, float>(R, grid, block, lds, s, sc.items.as<Item>(),
+                    ok = launch_gram_r<float, float>(R, grid, block, lds, s, sc.items,
                                                      o.c1.as<int2>(), o.v32.as<float>(),
-                                                     c.ws_fac1.as<float>(), T, RP, px,
-                                                     c.ws_partial.as<float>());
+                                                     static_cast<const float *>(fac), T, RP, px,
+                                                     static_cast<float *>(part));
                 else if (val64)
-                    ok = launch_gram_r<double, double>(R, grid, block, lds, s, sc.items.as<Item>(),
+                    ok = launch_gram_r<double, double>(R, grid, block, lds, s, sc.items,
                                                        o.c1.as<int2>(), o.v64.as<double>(),
-                                                       c.ws_fac1.as<double>(), T, RP, px,
-                                                       c.ws_partial.as<double>());
+                                                       static_cast<const double *>(fac), T, RP, px,
+                                                       static_cast<double *>(part));
                 else
-                    ok = launch_gram_r<float, double>(R, grid, block, lds, s, sc.items.as<Item>(),
+                    ok = launch_gram_r<float, double>(R, grid, block, lds, s, sc.items,
                                                       o.c1.as<int2>(), o.v32.as<float>(),
-                                                      c.ws_fac1.as<double>(), T, RP, px,
-                                                      c.ws_partial.as<double>());
+                                                      static_cast<const double *>(fac), T, RP, px,
+                                                      static_cast<double *>(part));
                 HIPCHECK(hipGetLastError());
             }
             mark(1);
@@ -1242,11 +1749,11 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
             if (sc.nfix > 0) {
                 if (dbl)
                     hipLaunchKernelGGL(sym_gram_reduce<double>, dim3((unsigned)sc.nfix), dim3(256),
-                                       0, s, sc.fix.as<Fixup>(), c.ws_partial.as<double>(), px,
+                                       0, s, sc.fix, static_cast<const double *>(part), px,
                                        static_cast<double *>(out), ldo);
                 else
                     hipLaunchKernelGGL(sym_gram_reduce<float>, dim3((unsigned)sc.nfix), dim3(256),
-                                       0, s, sc.fix.as<Fixup>(), c.ws_partial.as<float>(), px,
+                                       0, s, sc.fix, static_cast<const float *>(part), px,
                                        static_cast<float *>(out), ldo);
                 HIPCHECK(hipGetLastError());
             }
@@ -1269,6 +1776,135 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
         return;
     }
 
+    // Narrow products: the register-direct kernel where one lane holds the
+    // whole output block, else the LDS-staged kernel.  FREE1 runs in two
+    // steps over the stored pairs, so that every stored entry is read once:
+    // t = A.(Z)_3 on the pair pattern, then T1(r, :) = sum over the pairs
+    // (r, c) and (c, r) of Y(c, :) (x) t(pair, :).
+    NarrowArgs na{ws, t, s, prec, val64, dbl, cts, mk};
+    if (op == BKS_FREE3) {
+        narrow(na, MODE_TWO, t.o3, 0, val, F1, l1, t.m, px, F2, l2, t.m, py, outmode,
+               q, out, ldo, true, true);
+        return;
+    }
+    if (op == BKS_MODE3) {
+        narrow(na, MODE_M3, t.op, 2, val, nullptr, 0, 0, 1, F2, l2, t.n, py, OUT_RECT, q, out,
+               ldo, true, true);
+        return;
+    }
+    // FREE1, step 1: t = A.(Z)_3 into the intermediate region, with rows
+    // padded to whole 16-byte vectors (the second step gathers them)
+    const int V = dbl ? 2 : 4;
+    const int Wt = pad_to(py, V);
+    void *tmid = ws.get(3, (size_t)std::max<int64_t>(t.npairs, 1) * Wt * cts);
+    if (t.npairs > 0)
+        narrow(na, MODE_M3, t.op, 2, val, nullptr, 0, 0, 1, F2, l2, t.n, py, OUT_RECT, py, tmid,
+               Wt, true, false);
+    // step 2: pair rows, no values; t plays the part of the mode-3 factor
+    narrow(na, MODE_ONE, t.pr, 1, nullptr, F1, l1, t.m, px, tmid, Wt, t.npairs, py, OUT_RECT, q,
+           out, ldo, t.npairs == 0, true);
+}
+
+// One segmented narrow product (see ttmc_launch).  mode MODE_TWO: entries
+// (i, j, v) of `o`, factors F1 (and F2) with rows1 rows; MODE_M3: entries
+// (k, v), factor F2; MODE_ONE: entries (col, k) and values `val` (NULL: all
+// one), factors F1 (rows1) and F2 (rows2).  first / last: whether the
+// profiling marks around the main kernels open / close here.
+static void narrow(NarrowArgs &A, int mode, const Segmented &o, int fmt, const void *val,
+                   const void *F1, int64_t l1, int64_t rows1, int px, const void *F2, int64_t l2,
+                   int64_t rows2, int py, int outmode, int q, void *out, int64_t ldo, bool first,
+                   bool last) {
+    TtmcWs &ws = A.ws;
+    Tensor &t = A.t;
+    hipStream_t s = A.s;
+    const bool dbl = A.dbl;
+    const size_t cts = A.cts;
+    const int prec = A.prec;
+    const int V = dbl ? 2 : 4;
+    auto pack = [&](int which, const void *F, int64_t ld, int64_t rows, int p, int P, int PAD,
+                    int W) -> const void * {
+        void *dst = ws.get(which, (size_t)std::max<int64_t>(rows, 1) * W * cts);
+        const int64_t total = rows * W;
+        const unsigned grid = (unsigned)std::max<int64_t>(
+            1, std::min<int64_t>((total + 255) / 256, 4096));
+        if (total > 0) {
+            if (dbl)
+                hipLaunchKernelGGL(pack_blocks<double>, dim3(grid), dim3(256), 0, s,
+                                   static_cast<const double *>(F), ld, rows, p, P, PAD, W,
+                                   static_cast<double *>(dst));
+            else
+                hipLaunchKernelGGL(pack_blocks<float>, dim3(grid), dim3(256), 0, s,
+                                   static_cast<const float *>(F), ld, rows, p, P, PAD, W,
+                                   static_cast<float *>(dst));
+            HIPCHECK(hipGetLastError());
+        }
+        return dst;
+    };
+    auto fixups = [&](const SchedView &sc, void *partial) {
+        for (const auto &L : sc.levels) {
+            if (dbl)
+                hipLaunchKernelGGL(ttmc_fixup<double>, dim3((unsigned)L.first), dim3(256), 0, s,
+                                   L.second, static_cast<const double *>(partial), q,
+                                   static_cast<double *>(partial), (int64_t)q);
+            else
+                hipLaunchKernelGGL(ttmc_fixup<float>, dim3((unsigned)L.first), dim3(256), 0, s,
+                                   L.second, static_cast<const float *>(partial), q,
+                                   static_cast<float *>(partial), (int64_t)q);
+            HIPCHECK(hipGetLastError());
+        }
+        if (sc.nfix > 0) {
+            if (dbl)
+                hipLaunchKernelGGL(ttmc_fixup<double>, dim3((unsigned)sc.nfix), dim3(256), 0, s,
+                                   sc.fix, static_cast<const double *>(partial), q,
+                                   static_cast<double *>(out), ldo);
+            else
+                hipLaunchKernelGGL(ttmc_fixup<float>, dim3((unsigned)sc.nfix), dim3(256), 0, s,
+                                   sc.fix, static_cast<const float *>(partial), q,
+                                   static_cast<float *>(out), ldo);
+            HIPCHECK(hipGetLastError());
+        }
+    };
+    const bool same = mode == MODE_TWO && F2 == F1 && l2 == l1 && py == px;
+    const bool sym = outmode == OUT_SYM;
+
+    // register-direct kernel
+    RegLauncher rfn = reg_pick(prec, A.val64, mode, sym, px, py);
+    if (rfn) {
+        const int PAD1 = pad_to(px, V), PAD2 = pad_to(py, V);
+        const void *P1 = nullptr, *P2 = nullptr;
+        int W1 = 0, W2 = 0;
+        if (mode != MODE_M3) {
+            P1 = pack(0, F1, l1, rows1, px, px, PAD1, PAD1);
+            W1 = PAD1;
+        }
+        if (mode == MODE_M3 || mode == MODE_ONE || !sym) {
+            if (mode == MODE_ONE && fmt == 1) {
+                // the intermediate t of FREE1 arrives padded: gathered in place
+                P2 = F2;
+                W2 = (int)l2;
+            } else if (same) {
+                P2 = P1;
+                W2 = W1;
+            } else {
+                P2 = pack(1, F2, l2, rows2, py, py, PAD2, PAD2);
+                W2 = PAD2;
+            }
+        }
+        const SchedView sc = ws.sched(t, kGroupOrder + fmt, 0, s);
+        void *partial = sc.nslots > 0 ? ws.get(2, (size_t)sc.nslots * q * cts) : nullptr;
+        if (first) A.mark(0);
+        if (sc.nitems > 0)
+            rfn(dim3((unsigned)((sc.nitems + 3) / 4)), s, sc.items, sc.nitems,
+                o.segptr.as<int64_t>(), mode == MODE_M3 ? nullptr : o.c1.as<int2>(),
+                mode == MODE_M3 ? o.c2.as<int32_t>() : nullptr, val, P1, W1, P2, W2, out, ldo,
+                partial, q);
+        HIPCHECK(hipGetLastError());
+        fixups(sc, partial);
+        if (last) A.mark(1);
+        return;
+    }
+
+    // LDS-staged kernel (several lanes per entry)
     int PA, ga, PB, gb;
     int G;
     if (mode == MODE_M3) {
@@ -1277,7 +1913,7 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
         choose_block(py, PB, gb);
         G = gb;
         if (G > 64) fail(BKS_EINVAL, "MODE3 width too large");
-    } else if (outmode == OUT_SYM) {
+    } else if (sym) {
         choose_block(px, PA, ga);
         PB = PA;
         gb = ga;
@@ -1290,7 +1926,6 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
         if (G > 64) fail(BKS_EINVAL, "widths too large for the narrow kernel");
     }
     const int E = 64 / G;
-    const int V = dbl ? 2 : 4;
     Geo geo;
     std::memset(&geo, 0, sizeof(geo));
     geo.px = px;
@@ -1299,7 +1934,7 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
     geo.ga = ga;
     geo.outmode = outmode;
     geo.q = q;
-    geo.same = (mode == MODE_TWO && F2 == F1 && l2 == l1 && py == px) ? 1 : 0;
+    geo.same = same ? 1 : 0;
     geo.PAD1 = pad_to(PA, V);
     geo.PAD2 = pad_to(PB, V);
     geo.W1 = mode == MODE_M3 ? 0 : ga * geo.PAD1;
@@ -1320,81 +1955,37 @@ static void ttmc_launch(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, 
     const size_t lds = std::max(lds_elems, (size_t)64 * PA * PB) * cts;
     if (lds > 65536) fail(BKS_EINVAL, "widths too large for the narrow kernel");
 
-    // block-pack the factors (rows of X/Y: m; rows of Z: n)
+    // block-pack the factors
     const void *P1 = nullptr, *P2 = nullptr;
-    auto pack = [&](DevBuf &ws, const void *F, int64_t ld, int64_t rows, int p, int P, int PAD,
-                    int W) -> const void * {
-        ws.ensure((size_t)std::max<int64_t>(rows, 1) * W * cts);
-        const int64_t total = rows * W;
-        const unsigned grid = (unsigned)std::max<int64_t>(
-            1, std::min<int64_t>((total + 255) / 256, 4096));
-        if (total > 0) {
-            if (dbl)
-                hipLaunchKernelGGL(pack_blocks<double>, dim3(grid), dim3(256), 0, s,
-                                   static_cast<const double *>(F), ld, rows, p, P, PAD, W,
-                                   ws.as<double>());
-            else
-                hipLaunchKernelGGL(pack_blocks<float>, dim3(grid), dim3(256), 0, s,
-                                   static_cast<const float *>(F), ld, rows, p, P, PAD, W,
-                                   ws.as<float>());
-            HIPCHECK(hipGetLastError());
-        }
-        return ws.ptr;
-    };
     if (mode == MODE_TWO) {
-        P1 = pack(c.ws_fac1, F1, l1, t.m, px, PA, geo.PAD1, geo.W1);
-        P2 = geo.same ? P1 : pack(c.ws_fac2, F2, l2, t.m, py, PB, geo.PAD2, geo.W2);
+        P1 = pack(0, F1, l1, rows1, px, PA, geo.PAD1, geo.W1);
+        P2 = geo.same ? P1 : pack(1, F2, l2, rows2, py, PB, geo.PAD2, geo.W2);
     } else if (mode == MODE_ONE) {
-        P1 = pack(c.ws_fac1, F1, l1, t.m, px, PA, geo.PAD1, geo.W1);
-        P2 = pack(c.ws_fac2, F2, l2, t.n, py, PB, geo.PAD2, geo.W2);
+        P1 = pack(0, F1, l1, rows1, px, PA, geo.PAD1, geo.W1);
+        P2 = pack(1, F2, l2, rows2, py, PB, geo.PAD2, geo.W2);
     } else {
-        P2 = pack(c.ws_fac2, F2, l2, t.n, py, PB, geo.PAD2, geo.W2);
+        P2 = pack(1, F2, l2, rows2, py, PB, geo.PAD2, geo.W2);
     }
 
-    const Schedule &sc = t.schedule(order, E);
-    void *partial = nullptr;
-    if (sc.nslots > 0) {
-        c.ws_partial.ensure((size_t)sc.nslots * q * cts);
-        partial = c.ws_partial.ptr;
-    }
+    const SchedView sc = ws.sched(t, fmt, E, s);
+    void *partial = sc.nslots > 0 ? ws.get(2, (size_t)sc.nslots * q * cts) : nullptr;
     Launcher fn;
     if (prec == BKS_F32)
         fn = pick<float, float>(mode, PA, PB);
-    else if (val64)
+    else if (A.val64)
         fn = pick<double, double>(mode, PA, PB);
     else
         fn = pick<float, double>(mode, PA, PB);
     if (!fn) fail(BKS_EINVAL, "no kernel for this width");
-    mark(0);
+    if (first) A.mark(0);
     if (sc.nitems > 0)
-        fn(dim3((unsigned)sc.nitems), lds, s, sc.items.as<Item>(), o.segptr.as<int64_t>(),
+        fn(dim3((unsigned)sc.nitems), lds, s, sc.items, o.segptr.as<int64_t>(),
            mode == MODE_M3 ? nullptr : o.c1.as<int2>(),
            mode == MODE_M3 ? o.c2.as<int32_t>() : nullptr, val, P1, P2, geo, out, ldo,
            partial);
-    mark(1);
     HIPCHECK(hipGetLastError());
-    for (const auto &L : sc.levels) {
-        if (dbl)
-            hipLaunchKernelGGL(ttmc_fixup<double>, dim3((unsigned)L->nfix), dim3(256), 0, s,
-                               L->fix.as<Fixup>(), static_cast<const double *>(partial), q,
-                               static_cast<double *>(partial), (int64_t)q);
-        else
-            hipLaunchKernelGGL(ttmc_fixup<float>, dim3((unsigned)L->nfix), dim3(256), 0, s,
-                               L->fix.as<Fixup>(), static_cast<const float *>(partial), q,
-                               static_cast<float *>(partial), (int64_t)q);
-        HIPCHECK(hipGetLastError());
-    }
-    if (sc.nfix > 0) {
-        if (dbl)
-            hipLaunchKernelGGL(ttmc_fixup<double>, dim3((unsigned)sc.nfix), dim3(256), 0, s,
-                               sc.fix.as<Fixup>(), static_cast<const double *>(partial), q,
-                               static_cast<double *>(out), ldo);
-        else
-            hipLaunchKernelGGL(ttmc_fixup<float>, dim3((unsigned)sc.nfix), dim3(256), 0, s,
-                               sc.fix.as<Fixup>(), static_cast<const float *>(partial), q,
-                               static_cast<float *>(out), ldo);
-        HIPCHECK(hipGetLastError());
-    }
+    fixups(sc, partial);
+    if (last) A.mark(1);
 }
 
 }  // namespace bks

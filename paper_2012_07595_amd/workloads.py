@@ -5,9 +5,9 @@ arrival times. It performs none of the method's arithmetic (no contractions,
 no orthogonalisation), so both the FP64 oracle and the HIP path can consume
 the same inputs without sharing any computation.
 
-The shapes and value laws follow the paper's experiments (Section 5.2):
+The shapes and value laws follow the paper's experiments (section "Experiments"):
 sparse (1,2)-symmetric tensors A in R^{m x m x n} whose mode-3 slices are
-symmetric (Definition of a (1,2)-symmetric tensor, Section 2.1), with
+symmetric (Definition of a (1,2)-symmetric tensor, section "Notation"), with
 power-law mode-1/2 indices (social-network and word co-occurrence tensors)
 and uniform mode-3 indices.  Indices are 0-based.
 
@@ -206,7 +206,7 @@ def random_block(rows: int, cols: int, seed: int, dtype=np.float64):
 
 
 def dense_signal_noise(m: int, n: int, r: int, r3: int, rho: float, seed: int):
-    """Example-1-like dense tensor (Section 5.2.1): an (r, r, r3) N(0,1) block,
+    """Example-1-like dense tensor (Example 1 of the Experiments section): an (r, r, r3) N(0,1) block,
     symmetrised in modes 1-2, placed in the leading corner of an m x m x n zero
     tensor, plus rho times a symmetrised N(0,1) noise tensor; then one random
     permutation applied to modes 1 and 2 and an independent one to mode 3.
@@ -281,9 +281,111 @@ def c3_planted(seed: int = 1002) -> SymCOO:
     return merge(noise.astype(np.float64), plant).astype(np.float32)
 
 
+def chung_lu_sym(m: int, n: int, nnz: int, s: float, values: str = "abs", seed: int = 0,
+                 dtype=np.float32) -> SymCOO:
+    """Power-law degree generator: exactly ``nnz`` distinct stored positions
+    (i <= j, k) of an m x m x n (1,2)-symmetric tensor whose row degrees
+    follow a Zipf(s) law on the (permuted) row labels.
+
+    Chung-Lu law: the node of rank r has weight w_r = r^-s, and every
+    position (a <= b, k) is stored with probability min(1, c w_a w_b), with c
+    chosen so that the expected count is nnz.  Pairs with c w_a w_b >= 1 are
+    stored in all n slices (enumerated); for the rest, row a draws a Poisson
+    number of positions with mean n c w_a (sum of w_b over its unsaturated
+    partners b >= a), partners b from w restricted to those ranks, slices
+    uniformly.  Repeated positions are removed, rounds are drawn until nnz
+    distinct positions exist, and a seeded subset of exactly nnz is kept."""
+    if nnz < 0:
+        raise ValueError("nnz must be >= 0")
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(m).astype(np.int64)
+    r = np.arange(1, m + 1, dtype=np.float64)
+    w = r ** (-s)
+    pre = np.concatenate([[0.0], np.cumsum(w)])          # pre[b] = sum_{b' <= b} w
+    tot = pre[-1]
+
+    def layout(c):
+        J = np.minimum(np.floor((c * w) ** (1.0 / s)), m).astype(np.int64)
+        a = np.arange(1, m + 1, dtype=np.int64)
+        sat = np.maximum(0, J - a + 1)
+        b0 = np.maximum(a, J + 1)
+        lam = np.where(b0 <= m, n * c * w * (tot - pre[np.minimum(b0, m + 1) - 1]), 0.0)
+        return J, sat, b0, lam
+
+    lo, hi = 1e-12, 1e18
+    for _ in range(200):
+        mid = np.sqrt(lo * hi)
+        _, sat, _, lam = layout(mid)
+        if n * sat.sum() + lam.sum() < nnz:
+            lo = mid
+        else:
+            hi = mid
+    J, sat, b0, lam = layout(hi)
+
+    def key(ra, rb, k):
+        la, lb = perm[ra - 1], perm[rb - 1]
+        return (k * m + np.minimum(la, lb)) * m + np.maximum(la, lb)
+
+    parts = []
+    for a in np.flatnonzero(sat > 0) + 1:
+        bs = np.arange(a, J[a - 1] + 1, dtype=np.int64)
+        kk = np.arange(n, dtype=np.int64)
+        parts.append(key(np.full(bs.size * n, a), np.repeat(bs, n), np.tile(kk, bs.size)))
+    keys = np.unique(np.concatenate(parts)) if parts else np.empty(0, np.int64)
+    rows = np.arange(1, m + 1, dtype=np.int64)
+    rounds = 0
+    scale = 1.0
+    while keys.shape[0] < nnz:
+        cnt = rng.poisson(lam * scale)
+        new = []
+        step = 2_000_000
+        # rows in blocks of about `step` samples
+        cum = np.cumsum(cnt)
+        start = 0
+        while start < m:
+            stop = int(np.searchsorted(cum, (cum[start - 1] if start else 0) + step, side="right"))
+            stop = max(stop, start + 1)
+            ra = np.repeat(rows[start:stop], cnt[start:stop])
+            if ra.size:
+                lo_w = pre[b0[ra - 1] - 1]
+                u = lo_w + rng.random(ra.size) * (tot - lo_w)
+                rb = np.minimum(np.searchsorted(pre, u, side="left"), m)
+                rb = np.maximum(rb, b0[ra - 1])
+                new.append(np.unique(key(ra, rb, rng.integers(0, n, size=ra.size, dtype=np.int64))))
+            start = stop
+        before = keys.shape[0]
+        keys = np.unique(np.concatenate([keys] + new))
+        got = keys.shape[0] - before
+        rounds += 1
+        if rounds > 20:
+            raise RuntimeError("could not draw enough distinct positions")
+        # next round: enough draws for the deficit at this round's yield
+        scale = max(0.05, 1.2 * (nnz - keys.shape[0]) / max(got, 1)) * scale
+    if keys.shape[0] > nnz:
+        keep = rng.choice(keys.shape[0], size=nnz, replace=False)
+        keep.sort()
+        keys = keys[keep]
+    j = keys % m
+    t = keys // m
+    i = t % m
+    k = t // m
+    if values == "normal":
+        v = rng.standard_normal(nnz)
+    elif values == "abs":
+        v = np.abs(rng.standard_normal(nnz))
+    elif values == "ones":
+        v = np.ones(nnz)
+    else:
+        raise ValueError(values)
+    order = rng.permutation(nnz)
+    return SymCOO(m, n, i[order].astype(np.int32), j[order].astype(np.int32),
+                  k[order].astype(np.int32), v[order].astype(dtype))
+
+
 def c5(seed: int = 1004) -> SymCOO:
-    """1e6 x 1e6 x 500, 2e8 stored, Zipf(1.6) modes 1-2, |N(0,1)| FP32."""
-    return sparse_sym(1_000_000, 500, 200_000_000, zipf=1.6, values="abs", seed=seed)
+    """1e6 x 1e6 x 500, 2e8 stored, Zipf(1.6) mode-1/2 degrees (Chung-Lu law,
+    chung_lu_sym), |N(0,1)| FP32."""
+    return chung_lu_sym(1_000_000, 500, 200_000_000, 1.6, values="abs", seed=seed)
 
 
 @dataclasses.dataclass
@@ -298,7 +400,7 @@ class Request:
 
 
 def p_princeton(seed: int = 1010) -> SymCOO:
-    """Stand-in for the Princeton tensor (Section 5.2, Example 2; the data set
+    """Stand-in for the Princeton tensor (section "Experiments", Example 2; the data set
     is not used): 6593 x 6593 x 29, entry (l, m, v) = 1 when l and m are
     friends and one of them has flag v.  Friendships are 3.1e5 distinct
     pairs l != m drawn from a Zipf(1.0) law on the (permuted) node labels;
@@ -327,7 +429,7 @@ def p_princeton(seed: int = 1010) -> SymCOO:
 
 
 def p_reuters(seed: int = 1011) -> SymCOO:
-    """Stand-in for the Reuters tensor (Section 5.2, Example 3; the data set
+    """Stand-in for the Reuters tensor (section "Experiments", Example 3; the data set
     is not used): 13332 x 13332 x 66 with 486,894 nonzeros of the full tensor
     (read as 243,447 stored (i <= j, k) positions), indices from a Zipf(1.0)
     law, positive integer weights from a Zipf(2) law."""
@@ -337,7 +439,7 @@ def p_reuters(seed: int = 1011) -> SymCOO:
 
 
 def p_darpa(seed: int = 1012) -> SymCOO:
-    """Stand-in for the 1998 DARPA tensor (Section 5.2, Example 4; the data
+    """Stand-in for the 1998 DARPA tensor (section "Experiments", Example 4; the data
     set is not used; its nonzero count is not stated and is read as 1e6
     stored positions): 8891 x 8891 x 371, binary, indices from a Zipf(1.2)
     law, then every slice scaled to Frobenius norm 1 as in the paper."""

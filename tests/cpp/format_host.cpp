@@ -122,28 +122,6 @@ static void check_layouts(const bks::Tensor &t, const Canon &M, int64_t m, int64
         CHECK(t.o3.h_segptr.size() == (size_t)n + 1);
     }
 
-    // row-major over both orientations: row r holds (col, k) sorted by (col, k)
-    std::map<std::tuple<int64_t, int64_t, int64_t>, double> R;  // (row, col, k)
-    for (auto &kv : M) {
-        auto [k, lo, hi] = kv.first;
-        R[{lo, hi, k}] = kv.second;
-        if (lo != hi) R[{hi, lo, k}] = kv.second;
-    }
-    CHECK(t.o1.nseg == m && t.o1.nent == (int64_t)R.size());
-    {
-        const int64_t *ptr = dev<int64_t>(t.o1.segptr);
-        int64_t e = 0;
-        for (auto &kv : R) {
-            auto [row, col, k] = kv.first;
-            CHECK(ptr[row] <= e && e < ptr[row + 1]);
-            CHECK(dev<int32_t>(t.o1.c1)[2 * e] == col && dev<int32_t>(t.o1.c1)[2 * e + 1] == k);
-            CHECK(dev<float>(t.o1.v32)[e] == (float)kv.second);
-            if (f64) CHECK(dev<double>(t.o1.v64)[e] == kv.second);
-            ++e;
-        }
-        if (!R.empty()) CHECK(ptr[m] == (int64_t)R.size());
-    }
-
     // stored pair pattern: pairs (lo, hi) ascending, each with its k ascending
     std::map<std::pair<int64_t, int64_t>, std::vector<std::pair<int64_t, double>>> P;
     for (auto &kv : M) {
@@ -168,6 +146,34 @@ static void check_layouts(const bks::Tensor &t, const Canon &M, int64_t m, int64
             }
             ++q;
         }
+    }
+
+    // pair rows: row r lists every stored pair touching it as (col, pair id),
+    // sorted by col (pairs (c, r) with c < r, then (r, c) with c >= r); an
+    // index over the pairs, no values
+    std::map<std::pair<int64_t, int64_t>, int64_t> pid;  // (row, col) -> pair id
+    {
+        int64_t q = 0;
+        for (auto &pv : P) {
+            pid[{pv.first.first, pv.first.second}] = q;
+            if (pv.first.first != pv.first.second) pid[{pv.first.second, pv.first.first}] = q;
+            ++q;
+        }
+    }
+    CHECK(t.pr.nseg == m && t.pr.nent == (int64_t)pid.size());
+    CHECK(t.pr.v32.ptr == nullptr && t.pr.v64.ptr == nullptr);
+    {
+        const int64_t *ptr = dev<int64_t>(t.pr.segptr);
+        CHECK(ptr[0] == 0);
+        int64_t e = 0;
+        for (auto &kv : pid) {
+            const int64_t row = kv.first.first, col = kv.first.second;
+            CHECK(ptr[row] <= e && e < ptr[row + 1]);
+            CHECK(dev<int32_t>(t.pr.c1)[2 * e] == col && dev<int32_t>(t.pr.c1)[2 * e + 1] == kv.second);
+            ++e;
+        }
+        CHECK(ptr[m] == (int64_t)pid.size());
+        CHECK(t.pr.h_segptr.size() == (size_t)m + 1);
     }
 }
 
@@ -282,6 +288,45 @@ int main() {
         check_layouts(t8, canon_of(fits), fits.m, fits.n, true);
     }
     std::printf("ok formats_validation\n");
+
+    // slice scaling at upload: every nonempty slice of the Frobenius-scaled
+    // tensor has norm 1 (||A||^2 = nonempty slices); the lambda_max scaling
+    // of a slice that is 2.5 times the complete graph K_6 divides by 12.5;
+    // both flags at once are refused
+    {
+        Coo c = random_coo(60, 7, 900, 5, false);
+        bks::Tensor t;
+        CHECK(upload(t, c, true, BKS_SUM_DUPLICATES | BKS_SCALE_FROBENIUS) == 0);
+        const int64_t *ptr = dev<int64_t>(t.o3.segptr);
+        const int32_t *c12 = dev<int32_t>(t.o3.c1);
+        const double *v = dev<double>(t.o3.v64);
+        int nonempty = 0;
+        for (int64_t k = 0; k < c.n; ++k) {
+            double s = 0.0;
+            for (int64_t e = ptr[k]; e < ptr[k + 1]; ++e)
+                s += (c12[2 * e] == c12[2 * e + 1] ? 1.0 : 2.0) * v[e] * v[e];
+            if (ptr[k + 1] > ptr[k]) {
+                ++nonempty;
+                CHECK(std::fabs(s - 1.0) <= 1e-13);
+            }
+        }
+        CHECK(std::fabs(t.frob2 - nonempty) <= 1e-12 * nonempty);
+        Coo g{10, 2, {}, {}, {}, {}};
+        for (int a = 0; a < 6; ++a)
+            for (int b = a + 1; b < 6; ++b) {
+                g.i.push_back(a + 2);
+                g.j.push_back(b + 2);
+                g.k.push_back(1);
+                g.v.push_back(2.5);
+            }
+        bks::Tensor t2;
+        CHECK(upload(t2, g, true, BKS_SCALE_LAMBDA_MAX) == 0);
+        const double *v2 = dev<double>(t2.o3.v64);
+        for (int64_t e = 0; e < t2.o3.nent; ++e) CHECK(std::fabs(v2[e] - 0.2) <= 1e-15);
+        bks::Tensor t3;
+        CHECK(upload(t3, g, true, BKS_SCALE_LAMBDA_MAX | BKS_SCALE_FROBENIUS) == BKS_EINVAL);
+    }
+    std::printf("ok formats_scaling\n");
 
     if (failures) {
         std::printf("%d failures\n", failures);

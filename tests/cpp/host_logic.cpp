@@ -1,7 +1,9 @@
 // Host-logic checks of libbks (no GPU): work schedules and the partial-row
 // reduction tree, and the host dense kernels used by the inner solve.
 // Prints one "ok <check>" line per passed check; exits 1 on the first failure.
+#include <climits>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <limits>
@@ -10,6 +12,7 @@
 
 #include "inner.h"
 #include "linalg.h"
+#include "scale.h"
 #include "schedule.h"
 
 using namespace bks;
@@ -83,6 +86,117 @@ static void check_schedule() {
         for (int64_t x = 0; x < nslots; ++x) require(slot_seen[x] == 2, "every slot summed");
     }
     std::printf("ok schedule\n");
+}
+
+// Group schedules of the register-direct kernel: every entry exactly once,
+// every segment (empty ones included) written once, group widths powers of
+// two that hold every segment at <= kGroupLPE entries per lane, 64 / L
+// segments at most per light item, heavy chunks equal (+-1) and whole waves.
+static void check_group_schedule() {
+    std::mt19937_64 g(17);
+    for (int rep = 0; rep < 4; ++rep) {
+        auto sp = random_segptr(g, 4000);
+        if (rep == 3) {
+            // many short segments of mixed lengths (pair fibres, pair rows)
+            std::uniform_int_distribution<int> len(0, 40);
+            for (size_t s = 0; s + 1 < sp.size(); ++s) sp[s + 1] = sp[s] + len(g);
+        }
+        const int64_t nseg = (int64_t)sp.size() - 1;
+        std::vector<Item> items;
+        std::vector<Fixup> fix;
+        int64_t nslots = 0;
+        build_group_schedule(sp, items, fix, nslots);
+        std::vector<int> covered(sp.back(), 0), seg_done(nseg, 0), slot_seen(nslots, 0);
+        for (const Item &it : items) {
+            if (it.seg_end < 0) {
+                require(it.pad == 64, "group: heavy items take the whole wave");
+                require(sp[it.seg + 1] - sp[it.seg] > 64 * kGroupLPE, "group: heavy only when long");
+                require(it.beg < it.end && it.end - it.beg <= kGroupChunk, "group: chunk size");
+                require(it.beg >= sp[it.seg] && it.end <= sp[it.seg + 1], "group: chunk in segment");
+                for (int64_t e = it.beg; e < it.end; ++e) covered[e]++;
+                if (it.slot >= 0) {
+                    require(it.slot < nslots && !slot_seen[it.slot], "group: slot unique");
+                    slot_seen[it.slot] = 1;
+                } else {
+                    require(it.beg == sp[it.seg] && it.end == sp[it.seg + 1], "group: whole");
+                    seg_done[it.seg]++;
+                }
+            } else {
+                const int L = it.pad;
+                require(L >= 1 && L <= 64 && (L & (L - 1)) == 0, "group: L a power of two");
+                require(it.seg_end > it.seg && (it.seg_end - it.seg) * L <= 64, "group: 64 / L segments");
+                for (int64_t s = it.seg; s < it.seg_end; ++s) {
+                    require(sp[s + 1] - sp[s] <= (int64_t)L * kGroupLPE, "group: entries per lane");
+                    for (int64_t e = sp[s]; e < sp[s + 1]; ++e) covered[e]++;
+                    seg_done[s]++;
+                }
+            }
+        }
+        for (const Fixup &f : fix) {
+            int64_t lo = INT64_MAX, hi = 0;
+            for (int32_t x = 0; x < f.nslots; ++x) {
+                require(slot_seen[f.first_slot + x] == 1, "group: fixup slots are chunk slots");
+                slot_seen[f.first_slot + x] = 2;
+            }
+            for (const Item &it : items)
+                if (it.seg_end < 0 && it.seg == f.seg) {
+                    lo = std::min(lo, it.end - it.beg);
+                    hi = std::max(hi, it.end - it.beg);
+                }
+            require(f.nslots >= 2 && hi - lo <= 1, "group: equal chunks");
+            seg_done[f.seg]++;
+        }
+        for (int64_t e = 0; e < sp.back(); ++e) require(covered[e] == 1, "group: every entry once");
+        for (int64_t s = 0; s < nseg; ++s) require(seg_done[s] == 1, "group: every segment once");
+        for (int64_t x = 0; x < nslots; ++x) require(slot_seen[x] == 2, "group: every slot summed");
+    }
+    std::printf("ok group_schedule\n");
+}
+
+// Slice scalings: the spectral radius by the dense path and by Lanczos
+// (more than kDenseRows touched rows) against a dense eigensolve of the same
+// matrix, and the closed form of a complete graph; the Frobenius norm.
+static void check_scale() {
+    std::mt19937_64 g(23);
+    std::uniform_real_distribution<double> u(0.0, 1.0);
+    for (int d : {37, 900}) {
+        std::vector<int64_t> lo, hi;
+        std::vector<double> v;
+        std::vector<double> A((size_t)d * d, 0.0);
+        for (int a = 0; a < d; ++a)
+            for (int b = a; b < d; ++b)
+                if (u(g) < 12.0 / d || b == a + 1) {
+                    const double x = u(g);   // nonnegative, connected (a path)
+                    lo.push_back(3 * a + 1); // arbitrary labels
+                    hi.push_back(3 * b + 1);
+                    v.push_back(x);
+                    A[(size_t)a * d + b] = A[(size_t)b * d + a] = x;
+                }
+        std::vector<double> w(d), V((size_t)d * d);
+        la::sym_eig(d, A.data(), w.data(), V.data());
+        const double want = std::max(std::fabs(w[0]), std::fabs(w[d - 1]));
+        const double got = sym_spectral_radius((int64_t)v.size(), lo.data(), hi.data(), v.data());
+        require(std::fabs(got - want) <= 1e-12 * want, "scale: spectral radius");
+        double f = 0.0;
+        for (double x : A) f += x * x;
+        require(std::fabs(sym_frobenius((int64_t)v.size(), lo.data(), hi.data(), v.data()) -
+                          std::sqrt(f)) <= 1e-13 * std::sqrt(f), "scale: frobenius");
+    }
+    // c K_q: largest eigenvalue c (q - 1); 500 nodes takes the Lanczos path
+    for (int q : {9, 500}) {
+        std::vector<int64_t> lo, hi;
+        std::vector<double> v;
+        for (int a = 0; a < q; ++a)
+            for (int b = a + 1; b < q; ++b) {
+                lo.push_back(a);
+                hi.push_back(b);
+                v.push_back(2.5);
+            }
+        const double got = sym_spectral_radius((int64_t)v.size(), lo.data(), hi.data(), v.data());
+        require(std::fabs(got - 2.5 * (q - 1)) <= 1e-12 * 2.5 * (q - 1), "scale: complete graph");
+    }
+    require(sym_spectral_radius(0, nullptr, nullptr, nullptr) == 0.0, "scale: empty");
+    std::printf("ok scale\n");
 }
 
 static void check_wide_schedule() {
@@ -454,6 +568,8 @@ static void check_inner_device() {
 
 int main() {
     check_schedule();
+    check_group_schedule();
+    check_scale();
     check_wide_schedule();
     check_fix_tree();
     check_dgemm();

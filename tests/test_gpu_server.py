@@ -104,3 +104,118 @@ def test_budget_refusal_and_serialisation(ctx):
     ra, rb = one
     assert ra.status == 0 and rb.status == 0
     assert rb.t_start >= ra.t_end - 1e-6
+
+
+def slow_request(seed, m=5000, n=300, nnz=120_000, r=3):
+    """An unplanted Zipf tensor: the gradient falls slowly, so a solve with a
+    tolerance it cannot reach runs for many outer iterations."""
+    coo = workloads.sparse_sym(m, n, nnz, zipf=1.3, values="abs", seed=seed).astype(np.float32)
+    U0, W0 = workloads.random_start(m, n, r, r, seed + 1)
+    return coo, r, U0, W0
+
+
+def wait_started(srv, rid, timeout=60.0):
+    import time
+    t0 = time.time()
+    while srv.poll(rid).t_start == 0.0:
+        assert time.time() - t0 < timeout, "request never started"
+        time.sleep(0.005)
+
+
+def test_cancel_queued_and_running(ctx):
+    import time
+    # rank 10 on a 2e6-entry tensor: each outer iteration takes tens of ms,
+    # and a tolerance of 1e-300 is never met
+    coo, r, U0, W0 = slow_request(7100, m=20000, n=2000, nnz=2_000_000, r=10)
+    t = ctx.upload_coo(coo)
+    srv = bks.Server(ctx, max_active=1, host_workers=1)
+    a = srv.submit(t, r, r, U0=U0, W0=W0, tol=1e-300, max_outer=2000)
+    b = srv.submit(t, r, r, U0=U0, W0=W0)
+    # b waits behind a (one slot): cancelled at once, never run
+    assert srv.cancel(b) == bks.OK
+    Ub, Wb, Fb, rb = srv.wait(b)
+    assert rb.done and rb.status == bks.ECANCELED and rb.info.outer_iters == 0
+    assert not Ub.any()
+    # a is running: it stops at its next outer iteration with its iterate
+    wait_started(srv, a)
+    time.sleep(0.5)
+    assert srv.cancel(a) == bks.OK
+    Ua, Wa, Fa, ra = srv.wait(a)
+    print(f"cancelled after {ra.info.outer_iters} outer iterations, "
+          f"{ra.t_end - ra.t_start:.2f} s")
+    assert ra.status == bks.ECANCELED
+    assert 0 <= ra.info.outer_iters < 2000
+    np.testing.assert_allclose(Ua.T @ Ua, np.eye(r), atol=1e-12)
+    np.testing.assert_allclose(Wa.T @ Wa, np.eye(r), atol=1e-12)
+    assert abs(np.sqrt(np.sum(Fa ** 2)) - ra.info.normF) <= 1e-10 * ra.info.normF
+    # finished and unknown requests
+    assert srv.cancel(a) == bks.EINVAL
+    assert srv.cancel(123456789) == bks.ENOTFOUND
+    # the slot is free again and serves the next request normally
+    coo2, r2, U02, W02 = requests()[2]
+    t2 = ctx.upload_coo(coo2)
+    c = srv.submit(t2, r2, r2, U0=U02, W0=W02)
+    assert srv.wait(c)[3].status == 0
+    srv.close()
+
+
+def test_head_of_line_request_is_passed_over(ctx):
+    """With a budget that cannot hold the running request and the large one
+    behind it together, a small request queued after the large one is
+    admitted first; the large one starts once the running one ends."""
+    import time
+    slow = slow_request(7200)
+    big = slow_request(7300, m=20000, n=1500, nnz=400_000, r=5)
+    small = requests()[2]
+    probe = bks.Server(ctx, max_active=1)
+    fp = []
+    for coo, r, U0, W0 in (slow, big, small):
+        rid = probe.submit(None, r, r, U0=U0, W0=W0, coo=coo, max_outer=1)
+        fp.append(probe.wait(rid)[3].footprint)
+    probe.close()
+    fa, fb, fc = fp
+    # the first and the small request fit together, the first and the large
+    # one do not
+    assert fc < fb
+    srv = bks.Server(ctx, max_active=2, mem_budget=fa + fb - 1)
+    coo, r, U0, W0 = slow
+    a = srv.submit(None, r, r, U0=U0, W0=W0, coo=coo, tol=1e-300, max_outer=150)
+    wait_started(srv, a)
+    coo, r, U0, W0 = big
+    b = srv.submit(None, r, r, U0=U0, W0=W0, coo=coo, max_outer=2)
+    coo, r, U0, W0 = small
+    c = srv.submit(None, r, r, U0=U0, W0=W0, coo=coo)
+    rc_ = srv.wait(c)[3]
+    ra = srv.wait(a)[3]
+    rb = srv.wait(b)[3]
+    assert rc_.status == 0 and ra.status in (0, bks.ENOTCONV) and rb.status in (0, bks.ENOTCONV)
+    assert rc_.t_start < ra.t_end, "the small request waited behind the large one"
+    assert rb.t_start >= ra.t_end - 1e-6, "the large request ran beside the first"
+    srv.close()
+
+
+def test_device_bytes_within_footprint(ctx):
+    """The device bytes a served session holds (library buffers, tensor
+    formats of server-side uploads included) never exceed the footprint it
+    was admitted with, also for a rank-10 solve whose core product keeps
+    one 190 x 190 partial per slice chunk over 5000 slices (> 512 MB)."""
+    reqs = requests()[:4]
+    wide = workloads.sparse_sym(3000, 5000, 300_000, zipf=1.3, values="abs",
+                                seed=7400).astype(np.float32)
+    srv = bks.Server(ctx, max_active=2, host_workers=2)
+    ids = []
+    tensors = []  # uploaded tensors must outlive their requests
+    for q, (coo, r, U0, W0) in enumerate(reqs):
+        if q % 2:
+            ids.append(srv.submit(None, r, r, U0=U0, W0=W0, coo=coo))
+        else:
+            tensors.append(ctx.upload_coo(coo))
+            ids.append(srv.submit(tensors[-1], r, r, U0=U0, W0=W0))
+    U0, W0 = workloads.random_start(wide.m, wide.n, 10, 10, 7401)
+    ids.append(srv.submit(None, 10, 10, U0=U0, W0=W0, coo=wide, max_outer=1))
+    for rid in ids:
+        res = srv.wait(rid)[3]
+        assert res.status in (0, bks.ENOTCONV), (res.status, res.error)
+        print(f"footprint {res.footprint / 2**20:.1f} MiB peak {res.dev_peak / 2**20:.1f} MiB")
+        assert 0 < res.dev_peak <= res.footprint
+    srv.close()

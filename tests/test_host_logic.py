@@ -35,20 +35,22 @@ def test_host_logic(tmp_path, build):
     cmd = [cxx] + BUILDS[build] + ["-std=c++17", "-mavx2", "-mfma", "-pthread", "-I", CSRC,
            os.path.join(ROOT, "tests", "cpp", "host_logic.cpp"),
            os.path.join(CSRC, "schedule.cpp"), os.path.join(CSRC, "linalg.cpp"),
+           os.path.join(CSRC, "scale.cpp"),
            os.path.join(CSRC, "inner.cpp"), "-o", exe]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
     r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
     print(r.stdout)
     assert r.returncode == 0, r.stdout + r.stderr
-    for name in ("schedule", "wide_schedule", "fix_tree", "dgemm", "cholesky_threads", "sym_eig",
-                 "inner_device"):
+    for name in ("schedule", "group_schedule", "scale", "wide_schedule", "fix_tree", "dgemm",
+                 "cholesky_threads", "sym_eig", "inner_device"):
         assert f"ok {name}" in r.stdout
 
 
 def test_upload_formats(tmp_path):
     """The tensor upload's host code (canonicalisation, merging of repeated
-    positions, validation, the slice-major, row-major and pair layouts)
+    positions, validation, the slice-major and pair layouts and the pair-row
+index)
     against an ordered-map construction of the same layouts, with the HIP
     runtime calls it makes replaced by host memory; built with
     AddressSanitizer + UBSan (host code only, g++)."""
@@ -64,11 +66,13 @@ def test_upload_formats(tmp_path):
                                          "-I", CSRC,
                                          os.path.join(ROOT, "tests", "cpp", "format_host.cpp"),
                                          os.path.join(CSRC, "format.cpp"),
+                                         os.path.join(CSRC, "scale.cpp"),
+                                         os.path.join(CSRC, "linalg.cpp"),
                                          os.path.join(CSRC, "schedule.cpp"), "-o", exe]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
     r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
     print(r.stdout)
     assert r.returncode == 0, r.stdout + r.stderr
-    for name in ("random", "distinct", "full_symmetric", "validation"):
+    for name in ("random", "distinct", "full_symmetric", "validation", "scaling"):
         assert f"ok formats_{name}" in r.stdout
