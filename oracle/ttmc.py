@@ -103,6 +103,26 @@ def free1(T: SymTensor, Y: np.ndarray, Z: np.ndarray) -> np.ndarray:
     return out
 
 
+def free1_rows(T: SymTensor, Y: np.ndarray, Z: np.ndarray, rows) -> np.ndarray:
+    """The rows `rows` of T1 = A.(Y, Z)_{2,3}, one at a time: row i is the
+    sum over the full entries (i, j, k, a) of a Y(j,:) (x) Z(k,:), formed as
+    the product Y_J^T diag(a) Z_K (a library matrix product as the step),
+    column b + py*c.  For sampled rows of a large tensor."""
+    Y = np.asarray(Y, dtype=np.float64)
+    Z = np.asarray(Z, dtype=np.float64)
+    py, pz = Y.shape[1], Z.shape[1]
+    out = np.zeros((len(rows), py * pz))
+    for q, r in enumerate(rows):
+        as_i = T.i == r
+        as_j = (T.j == r) & (T.i != r)   # the mirror (j, i, k) of an off-diagonal entry
+        col = np.concatenate([T.j[as_i], T.i[as_j]])
+        k = np.concatenate([T.k[as_i], T.k[as_j]])
+        a = np.concatenate([T.a[as_i], T.a[as_j]])
+        M = (a[:, None] * Y[col]).T @ Z[k]          # py x pz, M(b, c)
+        out[q] = M.reshape(-1, order="F")           # column b + py*c
+    return out
+
+
 def pairs(T: SymTensor):
     """Distinct stored (i <= j) pairs in (i, j)-sorted order, and the pair
     index of every stored entry."""

@@ -68,6 +68,25 @@ def test_free1_brute_force_and_symmetry(py, pz):
     np.testing.assert_allclose(got, ref13, atol=1e-12)
 
 
+@pytest.mark.parametrize("py,pz", [(1, 1), (2, 3), (4, 2)])
+def test_free1_rows_brute_force(py, pz):
+    """The per-row FREE1 (sampled rows of large tensors) against the dense
+    definition, on a tensor with diagonal (i = j) entries, an empty row and a
+    repeated row in the sample."""
+    T = tiny(13, m=12, n=4, nnz=50)
+    A = sptensor.dense(T)
+    assert np.any(T.i == T.j)
+    rng = np.random.default_rng(4)
+    Y = rng.standard_normal((T.m, py))
+    Z = rng.standard_normal((T.n, pz))
+    ref = np.einsum("ijk,jb,kc->icb", A, Y, Z).reshape(T.m, -1)
+    deg = np.bincount(np.concatenate([T.i, T.j]), minlength=T.m)
+    rows = [0, int(np.argmax(deg)), int(np.argmax(deg)), T.m - 1]
+    if np.any(deg == 0):
+        rows.append(int(np.flatnonzero(deg == 0)[0]))
+    np.testing.assert_allclose(ttmc.free1_rows(T, Y, Z, rows), ref[rows], rtol=0, atol=1e-12)
+
+
 def test_mode3_brute_force():
     T = tiny(5)
     A = sptensor.dense(T)
