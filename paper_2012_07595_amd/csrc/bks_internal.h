@@ -127,6 +127,8 @@ struct DevSolver {
     // b; false if it is not positive definite.  H is uploaded only when
     // new_matrix (it stays on the device between calls).
     bool solve(hipStream_t s, int N, const double *H, double mu, bool new_matrix, double *b);
+    // The same with H already in dH (formed on the device).
+    bool solve_resident(hipStream_t s, int N, double mu, double *b);
 };
 
 // Device products of the inner solve for large cores (devsolve.cpp):
@@ -135,7 +137,9 @@ struct DevInner : InnerDevice {
     DevSolver *ds = nullptr;
     hipStream_t s = nullptr;
     int k1 = 0, k3 = 0;
-    DevBuf dC, dA, dOut, dT, dY, dOnes;
+    DevBuf dC, dA, dOut, dT, dY, dOnes, dNw;
+    int rot_r = -1, rot_r3 = -1;    // rank of the rotation held in dY
+    int newton_n = 0;               // order of the Newton matrix held in ds->dH
     PinnedBuf pin;                  // staging of the small transfers
     double *stage(size_t count);    // pinned host space for `count` doubles
     // out_host(0:len) = sum of the nparts device vectors parts(:, q) (ld len)
@@ -148,6 +152,8 @@ struct DevInner : InnerDevice {
     void hooi3(const double *P, int r, double *M3) override;
     void rotate(const double *Qp, const double *Qs, int r, int r3, double *Y,
                 double *Y2) override;
+    bool newton_matrix(int r, int r3, double *diag) override;  // newton.hip
+    bool newton_solve(double mu, double *b) override;
 };
 
 // Event-timed launches of one kernel class (profiling).

@@ -38,12 +38,18 @@ void *DevSolver::get_handle(hipStream_t s) {
 
 bool DevSolver::solve(hipStream_t s, int N, const double *H, double mu, bool new_matrix,
                       double *b) {
-    rocblas_handle h = static_cast<rocblas_handle>(get_handle(s));
     const size_t bytes = (size_t)N * N * 8;
     if (new_matrix || dH.bytes < bytes) {
         dH.ensure(bytes);
         HIPCHECK(hipMemcpyAsync(dH.ptr, H, bytes, hipMemcpyHostToDevice, s));
     }
+    return solve_resident(s, N, mu, b);
+}
+
+bool DevSolver::solve_resident(hipStream_t s, int N, double mu, double *b) {
+    rocblas_handle h = static_cast<rocblas_handle>(get_handle(s));
+    const size_t bytes = (size_t)N * N * 8;
+    if (dH.bytes < bytes) fail(BKS_EINVAL, "Newton matrix not on the device");
     dA.ensure(bytes);
     db.ensure((size_t)N * 8 + 64);
     HIPCHECK(hipMemcpyAsync(dA.ptr, dH.ptr, bytes, hipMemcpyDeviceToDevice, s));
@@ -106,6 +112,8 @@ double *DevInner::stage(size_t count) {
 void DevInner::set_core(const double *C, int k1_, int k3_) {
     k1 = k1_;
     k3 = k3_;
+    rot_r = rot_r3 = -1;
+    newton_n = 0;
     const size_t n = (size_t)k1 * k1 * k3;
     dC.ensure(n * 8);
     HIPCHECK(hipMemcpyAsync(dC.ptr, C, n * 8, hipMemcpyHostToDevice, s));
@@ -242,6 +250,10 @@ void DevInner::rotate(const double *Qp, const double *Qs, int r, int r3, double 
     // (the upload has been consumed before the download lands: same stream)
     HIPCHECK(hipMemcpyAsync(hs, dYl, (ny + ny2) * 8, hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
+    // dY keeps [Y | Y2] of this rank for newton_matrix
+    rot_r = r;
+    rot_r3 = r3;
+    newton_n = 0;
     std::memcpy(Y, hs, ny * 8);
     if (C1 > 0) std::memcpy(Y2, hs + ny, ny2 * 8);
 }

@@ -499,6 +499,7 @@ void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, do
     // the Newton matrices (60 MB at rank (10,10,10)) are reused across calls
     static thread_local std::vector<double> tl_H, tl_Hs;
     std::vector<double> &H = tl_H, &Hs = tl_Hs;
+    std::vector<double> hdiag;
     double mu = 0.0;
     double prev = INFINITY;
     int stall = 0;
@@ -519,16 +520,24 @@ void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, do
         if (stall >= 2) break;
         prev = info.rel;
         if (B.A1 * r + B.C1 * r3 == 0) break;
-        t0 = clk();
-        newton_matrix(B, H);
-        info.t_hess += clk() - t0;
         const int nd = B.A1 * r, N = nd + B.C1 * r3;
+        t0 = clk();
+        // large systems: the matrix is formed and factorised on the device
+        // when the device provides it, else formed here
+        hdiag.resize(N);
+        const bool dev_h = big && V.dev && N >= device_solve_min() &&
+                           V.dev->newton_matrix(r, r3, hdiag.data());
+        if (!dev_h) {
+            newton_matrix(B, H);
+            for (int i = 0; i < N; ++i) hdiag[i] = H[(size_t)i * N + i];
+        }
+        info.t_hess += clk() - t0;
         // Safeguarded Newton step (a reading: the paper cites the method
         // only): solve (-2A + mu I) d = b with the smallest tried shift that
         // makes the matrix positive definite and the step increase g; mu = 0
         // near a maximum gives the plain Newton step.
         double hmax = 0.0;
-        for (int i = 0; i < N; ++i) hmax = std::max(hmax, std::fabs(H[(size_t)i * N + i]));
+        for (int i = 0; i < N; ++i) hmax = std::max(hmax, std::fabs(hdiag[i]));
         const double mu0 = 1e-8 * std::max(hmax, 1e-300);
         const double g0 = nf * nf;
         bool accepted = false;
@@ -547,7 +556,8 @@ void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, do
             for (int i = 0; i < N - nd; ++i) d[nd + i] = 2.0 * G3[i];
             t0 = clk();
             if (on_device) {
-                const bool pd = big(N, H.data(), mu, attempt == 0, d.data());
+                const bool pd = dev_h ? V.dev->newton_solve(mu, d.data())
+                                      : big(N, H.data(), mu, attempt == 0, d.data());
                 info.t_chol += clk() - t0;
                 if (!pd) {
                     // no pivot from the device factorisation: escalate by 10

@@ -37,6 +37,19 @@ struct InnerDevice {
     virtual void hooi3(const double *P, int r, double *M3) = 0;
     virtual void rotate(const double *Qp, const double *Qs, int r, int r3, double *Y,
                         double *Y2) = 0;
+    // The Newton matrix H of the last rotate() (the entries newton_matrix
+    // states) formed and kept on the device, its N diagonal entries copied
+    // to diag; false if the device does not provide it (the host forms H).
+    virtual bool newton_matrix(int r, int r3, double *diag) {
+        (void)r, (void)r3, (void)diag;
+        return false;
+    }
+    // Solve (H + mu I) x = b with that matrix, in place of b; false if the
+    // shifted matrix is not positive definite.
+    virtual bool newton_solve(double mu, double *b) {
+        (void)mu, (void)b;
+        return false;
+    }
 };
 // Cores with at least this many entries (k1^2 k3) use the device when given
 // (BKS_DEVICE_CORE_MIN overrides); Newton systems of at least
