@@ -874,12 +874,17 @@ __global__ __launch_bounds__(256) void sym_gram_reduce(const Fixup *__restrict__
 constexpr int kMfmaChunk = 32;
 typedef float f32x4v __attribute__((ext_vector_type(4)));
 
-template <typename VT, int T, int ROWS>
+// DIRECT: every item is a whole slice; instead of a partial slot the
+// workgroup writes the slice's output row, the upper triangle of M + M^T,
+// through LDS (the staging buffers are free once the chunks are done; the
+// launch gives at least p^2 floats of LDS).
+template <typename VT, int T, int ROWS, bool DIRECT>
 __global__ __launch_bounds__(512) void ttmc_sym_gram_mfma(const Item *__restrict__ items,
                                                           const int2 *__restrict__ c12,
                                                           const VT *__restrict__ val,
                                                           const float *__restrict__ Xp, int Wl,
-                                                          int p, float *__restrict__ part) {
+                                                          int p, float *__restrict__ part,
+                                                          float *__restrict__ out, int64_t ldo) {
     constexpr int W = 16 * T;  // packed row width of X
     constexpr int U = W / 4;   // 16-byte units per row
     constexpr int NW = (T + ROWS - 1) / ROWS;
@@ -989,6 +994,32 @@ __global__ __launch_bounds__(512) void ttmc_sym_gram_mfma(const Item *__restrict
         fetch_idx(ch + 3);
         __syncthreads();
     }
+    if constexpr (DIRECT) {
+        // the loop ended on a barrier: the staging LDS is free for M
+        float *Ms = reinterpret_cast<float *>(lds_raw);
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const int I = wave * ROWS + r;
+            if (I >= T) break;
+#pragma unroll
+            for (int J = 0; J < T; ++J)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = I * 16 + 4 * kq + i, col = J * 16 + rc;
+                    if (row < p && col < p) Ms[row * p + col] = acc[r][J][i];
+                }
+        }
+        __syncthreads();
+        // column beta (beta + 1) / 2 + alpha, alpha <= beta: M(alpha, beta) +
+        // M(beta, alpha), the sum the chunk reduction forms for one chunk
+        float *orow = out + (int64_t)it.seg * ldo;
+        for (int beta = wave; beta < p; beta += NW) {
+            const int c0 = beta * (beta + 1) / 2;
+            for (int alpha = lane; alpha <= beta; alpha += 64)
+                orow[c0 + alpha] = Ms[alpha * p + beta] + Ms[beta * p + alpha];
+        }
+        return;
+    }
     float *o = part + (int64_t)it.slot * p * p;
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
@@ -1010,8 +1041,14 @@ __global__ __launch_bounds__(512) void ttmc_sym_gram_mfma(const Item *__restrict
 // chunk and writes its part of the chunk's partial M (full p x p per slot,
 // summed and symmetrised by sym_gram_reduce as above).  Xp rows hold T16
 // tiles (16 T16 floats); tiles past T16 of the last blocks are skipped.
+// Wide products come with few, long chunks (the partials are p^2 each): a
+// chunk of a 1e6-row tensor holds ~4e5 entries, and one FP32 accumulator
+// chain that long loses ~1e-5 relative accuracy.  The matrix-core
+// accumulators are therefore added into a second set every kBlkFlush
+// chunks (blocked summation), which keeps the error near 1e-6.
+constexpr int kBlkFlush = 8;
 template <typename VT, int TR, int TC, int ROWS>
-__global__ __launch_bounds__(256) void ttmc_sym_gram_mfma_blk(
+__global__ __launch_bounds__(64 * ((TR + ROWS - 1) / ROWS)) void ttmc_sym_gram_mfma_blk(
     const Item *__restrict__ items, const int2 *__restrict__ c12, const VT *__restrict__ val,
     const float *__restrict__ Xp, int T16, int Wli, int Wlj, int p, float *__restrict__ part) {
     constexpr int UI = 4 * TR, UJ = 4 * TC;     // 16-byte units of the staged rows
@@ -1035,11 +1072,14 @@ __global__ __launch_bounds__(256) void ttmc_sym_gram_mfma_blk(
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int kq = lane >> 4, rc = lane & 15;
-    f32x4v acc[ROWS][TC];
+    f32x4v acc[ROWS][TC], tot[ROWS][TC];
 #pragma unroll
     for (int a = 0; a < ROWS; ++a)
 #pragma unroll
-        for (int J = 0; J < TC; ++J) acc[a][J] = f32x4v{0.f, 0.f, 0.f, 0.f};
+        for (int J = 0; J < TC; ++J) {
+            acc[a][J] = f32x4v{0.f, 0.f, 0.f, 0.f};
+            tot[a][J] = f32x4v{0.f, 0.f, 0.f, 0.f};
+        }
 
     i32x2 nidx = i32x2{0, 0};
     float nv = 0.f;
@@ -1060,6 +1100,15 @@ __global__ __launch_bounds__(256) void ttmc_sym_gram_mfma_blk(
             s_ij[buf * kMfmaChunk + tid] = nidx;
             s_v[buf * kMfmaChunk + tid] = v;
         }
+    };
+    auto flush = [&]() {
+#pragma unroll
+        for (int a = 0; a < ROWS; ++a)
+#pragma unroll
+            for (int J = 0; J < TC; ++J) {
+                tot[a][J] += acc[a][J];
+                acc[a][J] = f32x4v{0.f, 0.f, 0.f, 0.f};
+            }
     };
     // gather x: unit u of the staged part of row X(i,:) (u < UI, tiles
     // R0..) or of X(j,:) (u >= UI, tiles C0..) of entry e; units past the
@@ -1119,12 +1168,14 @@ __global__ __launch_bounds__(256) void ttmc_sym_gram_mfma_blk(
                 for (int J = 0; J < TC; ++J)
                     acc[r][J] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r], b[J], acc[r][J], 0, 0, 0);
         }
+        if (ch % kBlkFlush == kBlkFlush - 1) flush();
         __syncthreads();
         if (more) commit_rows();
         commit_idx(ch & 1);
         fetch_idx(ch + 3);
         __syncthreads();
     }
+    flush();
     float *o = part + (int64_t)it.slot * p * p;
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
@@ -1135,7 +1186,7 @@ __global__ __launch_bounds__(256) void ttmc_sym_gram_mfma_blk(
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int row = (R0 + I) * 16 + 4 * kq + i, col = (C0 + J) * 16 + rc;
-                if (row < p && col < p) o[(int64_t)row * p + col] = acc[r][J][i];
+                if (row < p && col < p) o[(int64_t)row * p + col] = tot[r][J][i];
             }
     }
 }
@@ -1244,33 +1295,61 @@ bool launch_gram_r(int R, dim3 grid, dim3 block, size_t lds, hipStream_t s, cons
     return false;
 }
 
-template <int T>
+template <int T, bool DIRECT>
 void launch_mfma_t(dim3 grid, size_t lds, hipStream_t s, const Item *items, const int2 *c12,
-                   const float *val, const float *Xp, int Wl, int p, float *part) {
+                   const float *val, const float *Xp, int Wl, int p, float *part, float *out,
+                   int64_t ldo) {
     constexpr int ROWS = T <= 8 ? 1 : 2;
     constexpr int NW = (T + ROWS - 1) / ROWS;
-    hipLaunchKernelGGL((ttmc_sym_gram_mfma<float, T, ROWS>), grid, dim3(64 * NW), lds, s, items,
-                       c12, val, Xp, Wl, p, part);
+    hipLaunchKernelGGL((ttmc_sym_gram_mfma<float, T, ROWS, DIRECT>), grid, dim3(64 * NW), lds, s,
+                       items, c12, val, Xp, Wl, p, part, out, ldo);
 }
 
-// FP32 Gram product on the matrix cores for 2 <= T = ceil(p / 16) <= 12.
-bool launch_gram_mfma(int T, dim3 grid, size_t lds, hipStream_t s, const Item *items,
-                      const int2 *c12, const float *val, const float *Xp, int Wl, int p,
-                      float *part) {
+// FP32 Gram product on the matrix cores for 2 <= T = ceil(p / 16) <= 12;
+// direct (one item per slice, output rows written by the kernel) for
+// T <= kDirectMaxT.
+constexpr int kDirectMaxT = 6;
+constexpr int64_t kDirectMinSlices = 1024;   // items: 4 per CU at least
+constexpr int64_t kDirectMaxLen = 16384;     // entries of the longest slice
+bool launch_gram_mfma(int T, bool direct, dim3 grid, size_t lds, hipStream_t s,
+                      const Item *items, const int2 *c12, const float *val, const float *Xp,
+                      int Wl, int p, float *part, float *out, int64_t ldo) {
+#define BKS_MFMA_CASE(TT)                                                                      \
+    case TT:                                                                                   \
+        if constexpr (TT <= kDirectMaxT) {                                                     \
+            if (direct) {                                                                      \
+                launch_mfma_t<TT, true>(grid, lds, s, items, c12, val, Xp, Wl, p, part, out,   \
+                                        ldo);                                                  \
+                return true;                                                                   \
+            }                                                                                  \
+        }                                                                                      \
+        if (direct) return false;                                                              \
+        launch_mfma_t<TT, false>(grid, lds, s, items, c12, val, Xp, Wl, p, part, out, ldo);    \
+        return true;
     switch (T) {
-    case 2: launch_mfma_t<2>(grid, lds, s, items, c12, val, Xp, Wl, p, part); return true;
-    case 3: launch_mfma_t<3>(grid, lds, s, items, c12, val, Xp, Wl, p, part); return true;
-    case 4: launch_mfma_t<4>(grid, lds, s, items, c12, val, Xp, Wl, p, part); return true;
-    case 5: launch_mfma_t<5>(grid, lds, s, items, c12, val, Xp, Wl, p, part); return true;
-    case 6: launch_mfma_t<6>(grid, lds, s, items, c12, val, Xp, Wl, p, part); return true;
-    case 7: launch_mfma_t<7>(grid, lds, s, items, c12, val, Xp, Wl, p, part); return true;
-    case 8: launch_mfma_t<8>(grid, lds, s, items, c12, val, Xp, Wl, p, part); return true;
-    case 9: launch_mfma_t<9>(grid, lds, s, items, c12, val, Xp, Wl, p, part); return true;
-    case 10: launch_mfma_t<10>(grid, lds, s, items, c12, val, Xp, Wl, p, part); return true;
-    case 11: launch_mfma_t<11>(grid, lds, s, items, c12, val, Xp, Wl, p, part); return true;
-    case 12: launch_mfma_t<12>(grid, lds, s, items, c12, val, Xp, Wl, p, part); return true;
+        BKS_MFMA_CASE(2)
+        BKS_MFMA_CASE(3)
+        BKS_MFMA_CASE(4)
+        BKS_MFMA_CASE(5)
+        BKS_MFMA_CASE(6)
+        BKS_MFMA_CASE(7)
+        BKS_MFMA_CASE(8)
+        BKS_MFMA_CASE(9)
+        BKS_MFMA_CASE(10)
+        BKS_MFMA_CASE(11)
+        BKS_MFMA_CASE(12)
     default: return false;
     }
+#undef BKS_MFMA_CASE
+}
+
+// Output rows of the slices with no entries (no item writes them in the
+// direct form): zero.
+__global__ void zero_empty_rows(const Fixup *__restrict__ fix, int q, float *__restrict__ out,
+                                int64_t ldo) {
+    const Fixup f = fix[blockIdx.x];
+    if (f.nslots != 0) return;
+    for (int c = threadIdx.x; c < q; c += blockDim.x) out[(int64_t)f.seg * ldo + c] = 0.f;
 }
 
 // Register tile R and thread grid T x T for width p: the fewest lane-FMAs
@@ -1654,10 +1733,21 @@ static void ttmc_launch(TtmcWs &ws, Tensor &t, int op, const void *B1, int64_t l
             const int64_t max_items = std::max<int64_t>(o.nseg + 1, (int64_t)(536870912.0 / per_item));
             int64_t cw64 = std::min<int64_t>(2048, std::max<int64_t>(256, t.nnz / kGramItems));
             cw64 = std::max<int64_t>(cw64, t.nnz / std::max<int64_t>(1, max_items - o.nseg) + 1);
-            const int CW = (int)std::min<int64_t>(cw64, 1 << 30);
+            // direct form (one workgroup per slice writes its output row, no
+            // partials): narrow enough for M in LDS, slices many enough to
+            // fill the chip and short enough for one FP32 accumulator chain
+            bool direct = false;
+            if (mfma && !blocked && T16 <= kDirectMaxT && o.nseg >= kDirectMinSlices) {
+                int64_t maxlen = 0;
+                for (int64_t k = 0; k < o.nseg; ++k)
+                    maxlen = std::max<int64_t>(maxlen, o.h_segptr[k + 1] - o.h_segptr[k]);
+                direct = maxlen <= kDirectMaxLen;
+            }
+            const int CW = direct ? (1 << 30) : (int)std::min<int64_t>(cw64, 1 << 30);
             const SchedView sc = ws.sched(t, kWideOrder, CW, s);
             void *fac = ws.get(0, (size_t)std::max<int64_t>(t.m, 1) * W * cts);
-            void *part = sc.nitems > 0 ? ws.get(2, (size_t)sc.nitems * px * px * cts) : nullptr;
+            void *part = sc.nitems > 0 && !direct ? ws.get(2, (size_t)sc.nitems * px * px * cts)
+                                                  : nullptr;
             {
                 const int64_t total = t.m * W;
                 const unsigned grid = (unsigned)std::max<int64_t>(
@@ -1680,9 +1770,9 @@ static void ttmc_launch(TtmcWs &ws, Tensor &t, int op, const void *B1, int64_t l
                                      (size_t)2 * kMfmaChunk * 8;
                 mark(0);
                 if (sc.nitems > 0) {
-                    hipLaunchKernelGGL((ttmc_sym_gram_mfma_blk<float, TB, TB, 2>),
+                    hipLaunchKernelGGL((ttmc_sym_gram_mfma_blk<float, TB, TB, 1>),
                                        dim3((unsigned)sc.nitems, (unsigned)(nb * nb)),
-                                       dim3(64 * (TB / 2)), lds_b, s, sc.items, o.c1.as<int2>(),
+                                       dim3(64 * TB), lds_b, s, sc.items, o.c1.as<int2>(),
                                        o.v32.as<float>(), static_cast<const float *>(fac), T16,
                                        Wb, Wb, px, static_cast<float *>(part));
                     HIPCHECK(hipGetLastError());
@@ -1700,18 +1790,29 @@ static void ttmc_launch(TtmcWs &ws, Tensor &t, int op, const void *B1, int64_t l
                 // row stride with (Wl * 4) % 256 == 64: the four 16-float rows a
                 // K-step reads fall in different banks
                 const int Wl = W + ((16 - W % 64) + 64) % 64;
-                const size_t lds_m = (size_t)(2 * kMfmaChunk * Wl + 2 * kMfmaChunk) * 4 +
-                                     (size_t)2 * kMfmaChunk * 8;
+                size_t lds_m = (size_t)(2 * kMfmaChunk * Wl + 2 * kMfmaChunk) * 4 +
+                               (size_t)2 * kMfmaChunk * 8;
+                if (direct) lds_m = std::max<size_t>(lds_m, (size_t)px * px * 4);
                 mark(0);
                 if (sc.nitems > 0) {
-                    if (!launch_gram_mfma(T, dim3((unsigned)sc.nitems), lds_m, s, sc.items,
+                    if (!launch_gram_mfma(T, direct, dim3((unsigned)sc.nitems), lds_m, s, sc.items,
                                           o.c1.as<int2>(), o.v32.as<float>(),
                                           static_cast<const float *>(fac), Wl, px,
-                                          static_cast<float *>(part)))
+                                          static_cast<float *>(part), static_cast<float *>(out),
+                                          ldo))
                         fail(BKS_EINVAL, "no matrix-core kernel for this width");
                     HIPCHECK(hipGetLastError());
                 }
                 mark(1);
+                if (direct) {
+                    if (sc.nfix > 0) {
+                        hipLaunchKernelGGL(zero_empty_rows, dim3((unsigned)sc.nfix), dim3(256), 0, s,
+                                           sc.fix, px * (px + 1) / 2, static_cast<float *>(out),
+                                           ldo);
+                        HIPCHECK(hipGetLastError());
+                    }
+                    return;
+                }
                 if (sc.nfix > 0) {
                     hipLaunchKernelGGL(sym_gram_reduce<float>, dim3((unsigned)sc.nfix), dim3(256), 0,
                                        s, sc.fix, static_cast<const float *>(part), px,

@@ -120,11 +120,47 @@ def test_free3_rect(ctx, tensors, idx, prec, px, py):
 
 @pytest.mark.parametrize("idx", range(len(CASES)))
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 8, 10, 20, 23, 24, 25, 40, 70, 130])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 8, 10, 20, 23, 24, 25, 40, 70, 130, 193, 260])
 def test_free3_sym(ctx, tensors, idx, prec, p):
     t, o = pick(tensors, idx, prec)
     X = factors(o.m, p, 13, prec)
     got = run(ctx, t, bks.FREE3, X, None, o.n, p * (p + 1) // 2, prec, sym=True)
+    check(got, ref.free3(o, X, sym_half=True), prec, absprod(o, "free3", X, sym=True))
+
+
+@pytest.fixture(scope="module")
+def many_slices(ctx):
+    """1200 slices (enough for the one-workgroup-per-slice form of the core
+    product), every seventh of them empty."""
+    c = workloads.sparse_sym(3000, 1200, 36_000, zipf=0.8, values="normal", seed=77,
+                             dtype=np.float64)
+    keep = c.k % 7 != 3
+    c = workloads.SymCOO(c.m, c.n, c.i[keep], c.j[keep], c.k[keep], c.val[keep])
+    c32 = c.astype(np.float32)
+    return ctx.upload_coo(c), ctx.upload_coo(c32), oracle_tensor(c), oracle_tensor(c32)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("p", [25, 40, 70, 96, 97])
+def test_free3_sym_many_slices(ctx, many_slices, prec, p):
+    """Widths up to 96 write each slice's row from one workgroup (FP32),
+    97 takes the chunked form; empty slices give zero rows."""
+    t64, t32, o64, o32 = many_slices
+    t, o = (t64, o64) if prec == bks.F64 else (t32, o32)
+    X = factors(o.m, p, 15, prec)
+    got = run(ctx, t, bks.FREE3, X, None, o.n, p * (p + 1) // 2, prec, sym=True)
+    assert np.all(got[3::7] == 0.0)
+    check(got, ref.free3(o, X, sym_half=True), prec, absprod(o, "free3", X, sym=True))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_free3_sym_580(ctx, tensors, prec):
+    """The core product's width at rank 20 (k1 = 580: 37 output tiles per
+    side, cut into blocks of workgroups on the matrix cores in FP32) on the
+    tensor with seven long slices."""
+    t, o = pick(tensors, 1, prec)
+    X = factors(o.m, 580, 14, prec)
+    got = run(ctx, t, bks.FREE3, X, None, o.n, 580 * 581 // 2, prec, sym=True)
     check(got, ref.free3(o, X, sym_half=True), prec, absprod(o, "free3", X, sym=True))
 
 
