@@ -266,12 +266,15 @@ def run_bks(args):
     coo = getattr(workloads, WORKLOAD_GEN[args.workload])()
     U0, W0 = workloads.random_start(coo.m, coo.n, rank, rank, 2024)
     t_gen = time.perf_counter() - t_gen
+    big = args.workload == "c5"
+    stage = (lambda s: print(f"[bench] {s}", file=sys.stderr, flush=True)) if big else (lambda s: None)
+    stage(f"generated {coo.nnz} stored entries in {t_gen:.1f} s")
     assert torch.cuda.is_available(), "bench needs a GPU"
     ctx = bks.Ctx(0)
     t_up = time.perf_counter()
     t = ctx.upload_coo(coo)
     t_up = time.perf_counter() - t_up
-    big = args.workload == "c5"
+    stage(f"uploaded in {t_up:.1f} s")
     max_outer = args.max_outer if args.max_outer else (4 if big else 200)
     kw = dict(U0=U0, W0=W0, p=4, s=2, max_outer=max_outer, tol=1e-11)
     # plain FP64 GPU solve: the accuracy reference, then the comparison
@@ -280,6 +283,7 @@ def run_bks(args):
     ref = ctx.solve(t, rank, rank, precision=bks.PREC_FP64, **kw)
     torch.cuda.synchronize()
     ref_s = time.perf_counter() - a
+    stage(f"FP64 reference solve: {ref_s:.1f} s, {ref[3].outer_iters} outer iterations")
     n64 = 0 if big else max(1, min(args.steps, 2))
     fp64_s = ref_s
     if n64:

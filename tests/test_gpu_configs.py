@@ -1,0 +1,173 @@
+"""The workloads as they are printed (no planted part where the workload has
+none), solved on the GPU.
+
+U, W and F are determined only as well as the S-value gaps separate the
+kept directions from the rest (section "Conditioning of the best
+approximation problem"), so subspace parity is claimed where the relative
+gaps gap_k / s_1 of modes 1 and 3 are at least 1e-3; below that the test
+checks what holds at any iterate and prints the gaps.
+
+- C1 (500 x 500 x 100, 5e4 uniform N(0,1) stored entries plus the planted
+  rank-(2,2,2) part the workload names): plain FP64 HOOI (section "Higher
+  Order Orthogonal Iteration") against the oracle's HOOI from the same
+  start, and mixed-precision HOOI against the oracle's HOOI of the
+  FP32-rounded tensor.
+- C2 law (20000 x 20000 x 2000, 2e6 stored, Zipf(1.3) modes 1-2, uniform
+  mode 3, |N(0,1)| FP32; rank (5,5,5), BKS(2,4)): the iteration converges
+  slowly (relative gradient ~3e-3 after 200 outer iterations in both
+  precisions), so the check is on the first outer iterations: the plain
+  FP64 GPU solve against the oracle's after 5 outer iterations from the same
+  start (the gaps there are about 1e-3 and above), ||F|| non-decreasing
+  (the paper's argument for Algorithm 5), sum s_i^2 = ||F||^2 in modes 1
+  and 3, ||F|| <= ||A||, and the mixed-precision iterate against the FP64
+  one after 40 outer iterations.
+- C4 requests without a plant: the 32 requests of the 512-request trace with
+  at most 3e5 stored entries, served together (8 sessions, mixed precision),
+  each against the plain FP64 GPU solve of the same tensor and start (both
+  capped at 60 outer iterations; a request that does not converge there is
+  reported, parity unpinned).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import bks as obks, hooi as ohooi, sptensor
+from paper_2012_07595_amd import bks, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = bks.Ctx(0)
+    yield c
+    c.close()
+
+
+def otensor(coo):
+    return sptensor.from_coo(coo.m, coo.n, coo.i, coo.j, coo.k, coo.val.astype(np.float64))
+
+
+def rel_gaps(s1, s3, r, r3):
+    """gap_k / s_1 of modes 1 and 3: (s_r - s_{r+1}) / s_1."""
+    return (s1[r - 1] - s1[r]) / s1[0], (s3[r3 - 1] - s3[r3]) / s3[0]
+
+
+def invariants(info, nA, what, mono_tol):
+    """What holds at every iterate: ||F|| <= ||A||, and ||F|| non-decreasing
+    over the outer iterations (to mono_tol, the relative accuracy of the core
+    the inner solve maximises)."""
+    nF = info.normF
+    assert nF <= nA * (1 + 1e-12), (what, nF, nA)
+    h = np.array(info.normF_hist[:info.n_hist])
+    drops = (h[:-1] - h[1:]) / h[1:]
+    assert drops.size == 0 or drops.max() <= mono_tol, (what, drops.max())
+    return h
+
+
+def test_c1_hooi_vs_oracle(ctx):
+    c = workloads.c1()
+    U0, W0 = workloads.random_start(c.m, c.n, 2, 2, 7)
+    ref = ohooi.hooi_solve(otensor(c), 2, 2, U0, W0)
+    t = ctx.upload_coo(c)
+    U, W, F, info, rc = ctx.hooi(t, 2, 2, U0=U0, W0=W0, precision=bks.PREC_FP64)
+    a = max(obks.subspace_distance(ref["U"], U), obks.subspace_distance(ref["W"], W))
+    nF, nref = float(np.linalg.norm(F)), float(np.linalg.norm(ref["F"]))
+    print(f"[configs] C1 HOOI FP64: iters {info.outer_iters} / oracle {ref['iters']}, "
+          f"converged {bool(info.converged)} / {ref['converged']}, angle {a:.1e}, "
+          f"|F| {nF:.12g} ref {nref:.12g}", flush=True)
+    assert info.outer_iters == ref["iters"] and bool(info.converged) == ref["converged"]
+    # the C1 noise is ~28x the plant in norm; the local maximum has S-value
+    # gaps of a few percent: converged points agree to ~1e-9
+    assert a <= 1e-8, a
+    assert abs(nF - nref) <= 1e-10 * nref
+    c32 = c.astype(np.float32)
+    ref32 = ohooi.hooi_solve(otensor(c32), 2, 2, U0, W0)
+    t32 = ctx.upload_coo(c32)
+    U, W, F, info, rc = ctx.hooi(t32, 2, 2, U0=U0, W0=W0, precision=bks.PREC_MIXED)
+    a = max(obks.subspace_distance(ref32["U"], U), obks.subspace_distance(ref32["W"], W))
+    print(f"[configs] C1 HOOI mixed: iters {info.outer_iters} / oracle {ref32['iters']}, "
+          f"angle {a:.1e}", flush=True)
+    assert bool(info.converged) == ref32["converged"]
+    if ref32["converged"]:
+        assert a <= 1e-8, a
+
+
+def test_c2_law_first_iterations(ctx):
+    coo = workloads.c2()
+    U0, W0 = workloads.random_start(coo.m, coo.n, 5, 5, 2024)
+    t = ctx.upload_coo(coo)
+    nA = t.frob
+    kw = dict(U0=U0, W0=W0, p=4, s=2, tol=1e-11)
+    # plain FP64 GPU against the oracle after 5 outer iterations
+    U, W, F, info, rc = ctx.solve(t, 5, 5, precision=bks.PREC_FP64, max_outer=5, **kw)
+    print("[configs] oracle FP64 BKS on the C2 law, 5 outer iterations", flush=True)
+    ref = obks.bks_solve(otensor(coo), 5, 5, U0, W0, p=4, s=2, tol=1e-11, max_outer=5)
+    g1, g3 = rel_gaps(ref["svals1"], ref["svals3"], 5, 5)
+    a = max(obks.subspace_distance(ref["U"], U), obks.subspace_distance(ref["W"], W))
+    h = invariants(info, nA, "fp64", 1e-12)
+    href = np.array(ref["normF_hist"])
+    print(f"[configs] C2 law FP64 vs oracle at 5 iterations: angle {a:.1e}, gaps {g1:.2e} "
+          f"{g3:.2e}, |F| hist {list(h)} ref {list(href)}", flush=True)
+    assert info.outer_iters == 5 and len(href) == 5
+    s1 = np.array(info.svals1[:6])
+    s3 = np.array(info.svals3[:6])
+    assert abs(np.sum(s1[:5] ** 2) - info.normF ** 2) <= 1e-10 * info.normF ** 2
+    assert abs(np.sum(s3[:5] ** 2) - info.normF ** 2) <= 1e-10 * info.normF ** 2
+    if min(g1, g3) >= 1e-3:
+        assert a <= 1e-8, a
+        np.testing.assert_allclose(h, href, rtol=1e-10)
+    else:
+        print("[configs] C2 law at 5 iterations: parity unpinned (gap below 1e-3)", flush=True)
+    # mixed against FP64 after 40 outer iterations
+    U64, W64, F64, i64, _ = ctx.solve(t, 5, 5, precision=bks.PREC_FP64, max_outer=40, **kw)
+    Um, Wm, Fm, im, _ = ctx.solve(t, 5, 5, precision=bks.PREC_MIXED, max_outer=40, **kw)
+    invariants(i64, nA, "fp64", 1e-12)
+    # the mixed core is formed in FP32 (relative accuracy ~1e-5 per product)
+    invariants(im, nA, "mixed", 1e-5)
+    am = max(obks.subspace_distance(U64, Um), obks.subspace_distance(W64, Wm))
+    print(f"[configs] C2 law at 40 iterations: rel grad FP64 {i64.rel_grad:.2e} mixed "
+          f"{im.rel_grad:.2e}, mixed vs FP64 angle {am:.1e}, |F| {i64.normF:.12g} / "
+          f"{im.normF:.12g}", flush=True)
+    assert abs(im.normF - i64.normF) <= 1e-6 * i64.normF
+
+
+def test_c4_unplanted_requests(ctx):
+    reqs = [q for q in workloads.c4_requests(count=512, rate_per_s=1.0,
+                                             nnz_range=(10_000, 5_000_000))
+            if q.nnz <= 300_000]
+    assert len(reqs) == 32
+    coos = [workloads.request_tensor(q, plant=False) for q in reqs]
+    starts = [workloads.random_start(q.m, q.n, q.r, q.r, q.seed + 1) for q in reqs]
+    srv = bks.Server(ctx, max_active=8, host_workers=8)
+    ids = [srv.submit(None, q.r, q.r, precision=bks.PREC_MIXED, U0=U0, W0=W0, coo=coo,
+                      tol=1e-11, max_outer=60)
+           for q, coo, (U0, W0) in zip(reqs, coos, starts)]
+    served = []
+    for rid in ids:
+        U, W, F, res = srv.wait(rid)
+        # not converging within the outer cap is a result here, not an error
+        assert res.done and res.status in (0, bks.ENOTCONV), (res.status, res.error)
+        served.append((U, W, res.info))
+    srv.close()
+    pinned = unpinned = 0
+    for q, coo, (U0, W0), (U, W, info) in zip(reqs, coos, starts, served):
+        t = ctx.upload_coo(coo)
+        U64, W64, F64, i64, rc = ctx.solve(t, q.r, q.r, U0=U0, W0=W0, p=4, s=2, tol=1e-11,
+                                           max_outer=60, precision=bks.PREC_FP64)
+        g1, g3 = rel_gaps(i64.svals1, i64.svals3, q.r, q.r)
+        a = max(obks.subspace_distance(U64, U), obks.subspace_distance(W64, W))
+        assert info.normF <= t.frob * (1 + 1e-12)
+        ok = info.converged and i64.converged and min(g1, g3) >= 1e-3
+        print(f"[configs] C4 unplanted request {q.rid} m={q.m} n={q.n} nnz={q.nnz} r={q.r}: "
+              f"outer {info.outer_iters}/{i64.outer_iters} converged {bool(info.converged)}/"
+              f"{bool(i64.converged)} gaps {g1:.1e} {g3:.1e} angle {a:.1e}"
+              + ("" if ok else "  parity unpinned"), flush=True)
+        if ok:
+            pinned += 1
+            assert a <= 1e-8, (q.rid, a)
+        else:
+            unpinned += 1
+        t.free()
+    print(f"[configs] C4 unplanted: {pinned} pinned, {unpinned} unpinned", flush=True)
