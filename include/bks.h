@@ -214,8 +214,8 @@ typedef struct {
 /* Block Krylov-Schur solve (Algorithm 5 with U = V, section "A Tensor Krylov-Schur like method"): outputs U
  * (m x r), W (n x r3) and F (r x r x r3, column-major) to host memory.
  * Requires 1 <= r <= m, 1 <= r3 <= n, r3 <= r(r+1)/2 (else W0 cannot be
- * spanned by the first products).  k1 > m or k3 > n is capped (Section
- * 3.3.4).  Returns BKS_ENOTCONV if max_outer is reached.  `info` may be NULL.
+ * spanned by the first products).  k1 > m or k3 > n is capped
+ * (section "BK method").  Returns BKS_ENOTCONV if max_outer is reached.  `info` may be NULL.
  * Runs on the ctx's stream with the ctx's workspaces (device buffers,
  * coherent pinned host staging buffers, 1 MiB plus the size of the inner
  * solve's transfers, the rocBLAS handle): solves on one ctx

@@ -6,8 +6,8 @@
 //
 // gram_dd forms B^T B in double-double (a compensated product/sum per term):
 // the in-block part of the orthogonalisation must resolve directions that
-// are ~1e-12 of the block's norm (the G-gradient near convergence, Section
-// 2.5), which an FP64 Gram matrix (error ~1e-16 of its largest entry) cannot.
+// are ~1e-12 of the block's norm (the G-gradient near convergence, Proposition
+// 3.2), which an FP64 Gram matrix (error ~1e-16 of its largest entry) cannot.
 #include <algorithm>
 
 #include "bks_internal.h"

@@ -1,7 +1,8 @@
 // Small dense FP64 linear algebra (host).  Textbook algorithms: Householder
 // reduction to tridiagonal form followed by the implicitly shifted QL
-// iteration for symmetric eigenproblems, blocked right-looking Cholesky,
-// Householder QR, and a register-blocked product on AVX2 FMA.
+// iteration (EISPACK IMTQL2) for symmetric eigenproblems, blocked
+// right-looking Cholesky, Householder QR, and a register-blocked product on
+// AVX2 FMA.
 #include "linalg.h"
 
 #include <immintrin.h>
@@ -96,9 +97,11 @@ void tridiagonalize(int n, std::vector<double> &Z, std::vector<double> &d,
     }
 }
 
-// Implicitly shifted QL on the tridiagonal (d, e); rotations accumulated
-// into the rows of Zt = Z^T (row i of Zt is column i of Z, so each rotation
-// updates two contiguous rows).
+// Implicitly shifted QL on the tridiagonal (d, e): the Martin-Wilkinson
+// implicit QL algorithm in the form EISPACK publishes as IMTQL2 (from
+// Wilkinson and Reinsch's Handbook, vol. II), with its step order and
+// underflow exit; rotations accumulated into the rows of Zt = Z^T (row i of
+// Zt is column i of Z, so each rotation updates two contiguous rows).
 void tridiag_ql(int n, std::vector<double> &d, std::vector<double> &e, std::vector<double> &Zt) {
     const double eps = std::numeric_limits<double>::epsilon();
     double anorm = 0.0;
