@@ -178,6 +178,27 @@ int bks_ttmc(bks_ctx ctx, bks_tensor t, int op, const void *B1, int64_t ld1, int
              const void *B2, int64_t ld2, int p2, int sym_half, int prec, void *out,
              int64_t ldo, void *stream);
 
+/* bks_ttmc for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * products, the same kernels and bit-identical results, but every device
+ * workspace of the call -- block-packed factor copies, the partial rows of
+ * split segments and the work schedule -- is carved out of a fixed scratch
+ * array that the library holds on each device it runs on, so no device
+ * memory is allocated or freed.  The scratch is 256 MiB per device, held
+ * until the process ends; a product that needs
+ * more returns BKS_EINVAL with a message, as do symmetric halves wider than
+ * 24 columns (the core product; use bks_ttmc).  The tensor's formats are
+ * those of bks_tensor_upload; B1, B2, out are as for bks_ttmc.  The schedule
+ * is copied from host memory kept by the tensor with hipMemcpyAsync on
+ * `stream`.  All calls on one device share its scratch: calls whose
+ * execution overlaps (other streams, other contexts, other threads) race
+ * and must be serialised by the caller; the scratch keeps the last call's
+ * contents and nothing in it needs clearing.
+ * Errors: BKS_EINVAL, BKS_EDEVICE. */
+int bks_ttmc_noalloc(bks_ctx ctx, bks_tensor t, int op, const void *B1, int64_t ld1, int p1,
+                     const void *B2, int64_t ld2, int p2, int sym_half, int prec, void *out,
+                     int64_t ldo, void *stream);
+
 typedef struct {
     int r, r3;          /* target multilinear rank (r, r, r3) */
     int s, p;           /* stages and block width: BKS(s, p; k1, k3); 0 = defaults 2, 4 */

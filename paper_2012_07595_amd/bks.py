@@ -29,7 +29,7 @@ SYMBOLS = [
     "bks_ctx_create", "bks_ctx_destroy", "bks_last_error", "bks_version",
     "bks_ctx_profile", "bks_ctx_profile_read",
     "bks_tensor_upload", "bks_tensor_info", "bks_tensor_pairs", "bks_tensor_free",
-    "bks_ttmc", "bks_solve", "hooi_solve",
+    "bks_ttmc", "bks_ttmc_noalloc", "bks_solve", "hooi_solve",
     "bks_gtensor_upload", "bks_gttmc", "bks_gsolve",
     "bks_server_create", "bks_server_submit", "bks_server_submit_coo", "bks_server_poll",
     "bks_server_wait", "bks_server_cancel", "bks_server_now", "bks_server_destroy",
@@ -119,6 +119,7 @@ def load(path: str = LIBPATH):
     lib.bks_tensor_free.restype = None
     lib.bks_ttmc.argtypes = [vp, vp, C.c_int, vp, i64, C.c_int, vp, i64, C.c_int, C.c_int,
                              C.c_int, vp, i64, vp]
+    lib.bks_ttmc_noalloc.argtypes = lib.bks_ttmc.argtypes
     lib.bks_gtensor_upload.argtypes = [vp, i64, i64, i64, i64, vp, vp, vp, vp, C.c_int, C.c_uint,
                                        C.POINTER(vp)]
     lib.bks_gttmc.argtypes = [vp, vp, C.c_int, vp, i64, C.c_int, vp, i64, C.c_int, C.c_int, vp,
@@ -242,9 +243,10 @@ class Ctx:
     def upload_coo(self, coo, flags=0):
         return self.upload(coo.m, coo.n, coo.i, coo.j, coo.k, coo.val, flags)
 
-    def ttmc(self, t, op, B1, B2, out, sym_half=False, prec=F32, stream=None):
+    def ttmc(self, t, op, B1, B2, out, sym_half=False, prec=F32, stream=None, noalloc=False):
         """out <- product; B1, B2, out are 2-D row-major device tensors (rows
-        with unit stride).  The shapes and dtypes are checked here against the
+        with unit stride).  noalloc: through bks_ttmc_noalloc (no device
+        allocation; workspace in the library's fixed scratch).  The shapes and dtypes are checked here against the
         tensor and the precision (ValueError), since the library sees raw
         pointers.  stream: a hipStream_t value; None means torch's current
         stream on out's device."""
@@ -281,7 +283,8 @@ class Ctx:
             import torch
             stream = torch.cuda.current_stream(out.device).cuda_stream
         s = C.c_void_p(stream) if stream else None
-        self.check(self.lib.bks_ttmc(self.h, t.h, op, _ptr(B1), ld1, p1, _ptr(B2), ld2, p2,
+        fn = self.lib.bks_ttmc_noalloc if noalloc else self.lib.bks_ttmc
+        self.check(fn(self.h, t.h, op, _ptr(B1), ld1, p1, _ptr(B2), ld2, p2,
                       1 if sym_half else 0, prec, _ptr(out), out.stride(0), s))
 
     def upload_general(self, l, m, n, i, j, k, val, flags=0):

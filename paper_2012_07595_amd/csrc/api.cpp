@@ -139,6 +139,15 @@ int bks_ctx_create(int device, size_t mem_budget_bytes, bks_ctx *out) {
         delete c;
         return BKS_EDEVICE;
     }
+    // the allocation-free product's scratch address on this device (once
+    // per device, with the device current)
+    try {
+        scratch_init(device);
+    } catch (const Error &) {
+        (void)hipStreamDestroy(c->stream);
+        delete c;
+        return BKS_EDEVICE;
+    }
     *out = c;
     return BKS_OK;
 }
@@ -351,6 +360,17 @@ int bks_gttmc(bks_ctx ctx, bks_tensor t, int mode, const void *B1, int64_t ld1, 
         HIPCHECK(hipSetDevice(ctx->device));
         gttmc(*ctx, *t, mode, B1, ld1, p1, B2, ld2, p2, prec, out, ldo,
               static_cast<hipStream_t>(stream));
+    });
+}
+
+int bks_ttmc_noalloc(bks_ctx ctx, bks_tensor t, int op, const void *B1, int64_t ld1, int p1,
+                     const void *B2, int64_t ld2, int p2, int sym_half, int prec, void *out,
+                     int64_t ldo, void *stream) {
+    if (!ctx || !t) return BKS_EINVAL;
+    return guard(ctx, [&] {
+        HIPCHECK(hipSetDevice(ctx->device));
+        ttmc_noalloc(*ctx, *t, op, B1, ld1, p1, B2, ld2, p2, sym_half != 0, prec, out, ldo,
+                     static_cast<hipStream_t>(stream));
     });
 }
 

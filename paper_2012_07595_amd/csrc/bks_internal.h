@@ -239,6 +239,18 @@ void gttmc(Ctx &c, Tensor &t, int mode, const void *B1, int64_t ld1, int p1, con
 void ttmc(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, int p1, const void *B2,
           int64_t ld2, int p2, bool sym_half, int prec, void *out, int64_t ldo,
           hipStream_t s);
+// The same product with every device workspace (packed factors, partial
+// rows, intermediate products, the schedule) carved out of the library's
+// fixed per-device scratch array: no device memory is allocated.  Narrow
+// products only (symmetric halves up to 24 columns); BKS_EINVAL beyond the
+// scratch size.
+void ttmc_noalloc(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, int p1,
+                  const void *B2, int64_t ld2, int p2, bool sym_half, int prec, void *out,
+                  int64_t ldo, hipStream_t s);
+// Look up (once per device, with that device current) the device address of
+// the scratch array used by ttmc_noalloc; called at context creation.
+void scratch_init(int device);
+size_t scratch_bytes();
 
 // ---------------------------------------------------------------- dense kernels (dense.hip)
 // out(k x q, ldo) = A^T B with A (rows x k, lda), B (rows x q, ldb); FP64 out.

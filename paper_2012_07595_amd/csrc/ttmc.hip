@@ -1411,6 +1411,68 @@ struct CtxWs final : TtmcWs {
     bool allow_wide() const override { return true; }
 };
 
+// ---------------------------------------------------------------- scratch
+// Fixed device scratch of the allocation-free product entry point: every
+// workspace of a call is carved out of it in order.  Each device that loads
+// the library holds its own copy for the life of the process.  Host code
+// never names the array as an address: the per-device address comes from
+// hipGetSymbolAddress at context creation (scratch_init).
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static std::vector<void *> g_scratch_ptr;  // by device id
+
+static void *scratch_ptr(int device) {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (device < 0 || device >= (int)g_scratch_ptr.size() || !g_scratch_ptr[device])
+        fail(BKS_EDEVICE, "scratch not initialised on this device");
+    return g_scratch_ptr[device];
+}
+
+struct ScratchWs final : TtmcWs {
+    unsigned char *base;
+    size_t off = 0;
+    explicit ScratchWs(void *b) : base(static_cast<unsigned char *>(b)) {}
+    void *take(size_t bytes) {
+        const size_t at = (off + 255) & ~(size_t)255;
+        if (at + bytes > kScratchBytes || at + bytes < at)
+            fail(BKS_EINVAL, "the product needs " + std::to_string((at + bytes) >> 20) +
+                                 " MiB of workspace, beyond the " +
+                                 std::to_string(kScratchBytes >> 20) +
+                                 " MiB scratch of the allocation-free entry point");
+        off = at + bytes;
+        return base + at;
+    }
+    void *get(int, size_t bytes) override { return take(bytes); }
+    SchedView sched(Tensor &t, int order, int E, hipStream_t s) override {
+        const HostSchedule *h;
+        {
+            std::lock_guard<std::mutex> g(t.sched_mu);
+            h = &t.host_schedule(order, E);
+        }
+        SchedView v;
+        v.nitems = (int64_t)h->items.size();
+        v.nfix = (int64_t)h->fix.size();
+        v.nslots = h->nslots;
+        auto put = [&](const void *src, size_t bytes) -> void * {
+            if (!bytes) return nullptr;
+            void *d = take(bytes);
+            // the host schedule is kept by the tensor, so the source outlives
+            // the copy
+            HIPCHECK(hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, s));
+            return d;
+        };
+        v.items = static_cast<const Item *>(put(h->items.data(), h->items.size() * sizeof(Item)));
+        v.fix = static_cast<const Fixup *>(put(h->fix.data(), h->fix.size() * sizeof(Fixup)));
+        for (const auto &l : h->levels)
+            v.levels.emplace_back((int64_t)l.size(),
+                                  static_cast<const Fixup *>(put(l.data(), l.size() * sizeof(Fixup))));
+        return v;
+    }
+    bool allow_wide() const override { return false; }
+};
+
 static void ttmc_launch(TtmcWs &ws, Tensor &t, int op, const void *B1, int64_t ld1, int p1,
                         const void *B2, int64_t ld2, int p2, bool sym_half, int prec, void *out,
                         int64_t ldo, hipStream_t s, hipEvent_t *mk = nullptr);
@@ -1609,6 +1671,26 @@ void gttmc(Ctx &c, Tensor &t, int mode, const void *B1, int64_t ld1, int p1, con
         c.prof_record(name + "_call", a, b, bytes, flops);
     }
 }
+
+void ttmc_noalloc(Ctx &c, Tensor &t, int op, const void *B1, int64_t ld1, int p1,
+                  const void *B2, int64_t ld2, int p2, bool sym_half, int prec, void *out,
+                  int64_t ldo, hipStream_t s) {
+    ScratchWs ws(scratch_ptr(c.device));
+    ttmc_launch(ws, t, op, B1, ld1, p1, B2, ld2, p2, sym_half, prec, out, ldo, s);
+}
+
+void scratch_init(int device) {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (device >= (int)g_scratch_ptr.size()) g_scratch_ptr.resize(device + 1, nullptr);
+    if (g_scratch_ptr[device]) return;
+    void *p = nullptr;
+    // the caller made `device` current; each device has its own copy
+    HIPCHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) fail(BKS_EDEVICE, "no device address for the scratch array");
+    g_scratch_ptr[device] = p;
+}
+
+size_t scratch_bytes() { return kScratchBytes; }
 
 void Ctx::prof_record(const std::string &name, hipEvent_t a, hipEvent_t b, double bytes,
                       double flops) {
