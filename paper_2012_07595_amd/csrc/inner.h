@@ -12,7 +12,7 @@ namespace bks {
 // positive definite.  `new_matrix` is false when H is the same as in the
 // previous call (only mu changed).
 using BigSolve = std::function<bool(int N, const double *H, double mu, bool new_matrix, double *b)>;
-constexpr int kDeviceSolveMin = 512;
+constexpr int kDeviceSolveMin = 256;
 
 // Optional device for the dense products of large cores.  After set_core
 // (C uploaded, layout as below) every call is synchronous and returns host
