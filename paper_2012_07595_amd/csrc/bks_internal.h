@@ -130,6 +130,9 @@ struct DevSolver {
     // The same with H already in dH (formed on the device).
     bool solve_resident(hipStream_t s, int N, double mu, double *b);
 };
+// x <- (L L^T)^{-1} x on the device for a lower Cholesky factor L (N x N,
+// column-major, leading dimension N), one right-hand side (trisolve.hip).
+void chol_solve_dev(hipStream_t s, const double *L, int N, double *x);
 
 // Device products of the inner solve for large cores (devsolve.cpp):
 // rocBLAS FP64 on the ctx stream, sharing the DevSolver's handle.
