@@ -340,6 +340,19 @@ def run_bks(args):
         el, latp, resp = timed_solves(ctx, tp, rank, bks.PREC_MIXED, max(args.steps, 5), kw)
         out["c2p"] = {"workload": WORKLOAD_TEXT["c2p"], **solve_summary(el, latp, resp, refp, rank)}
         tp.free()
+    if big and not args.no_extra:
+        # the comparison method on the same tensor and start (the C5
+        # configuration names it): mixed-precision HOOI for as many
+        # iterations as fit in the BKS solve's time, ||F|| beside BKS's
+        stage("HOOI, same start")
+        a = time.perf_counter()
+        Uh, Wh, Fh, ih, _ = ctx.hooi(t, rank, rank, U0=U0, W0=W0, precision=bks.PREC_MIXED,
+                                     max_iter=args.hooi_iters, grad_every=5)
+        torch.cuda.synchronize()
+        out["hooi"] = {"precision": "mixed", "iters": ih.outer_iters,
+                       "seconds": round(time.perf_counter() - a, 2),
+                       "normF": float(np.linalg.norm(Fh)), "rel_grad": ih.rel_grad,
+                       "bks_normF": info.normF}
     if args.copy_ref_mb:
         copy_reference(args.copy_ref_mb)
     if not args.no_cpu and not big:
@@ -598,6 +611,8 @@ def main():
     ap.add_argument("--max-outer", type=int, default=0,
                     help="outer iteration cap (default 200; 4 for c5)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--hooi-iters", type=int, default=10,
+                    help="HOOI iterations of the c5 comparison")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the planted C2 variant reported beside the C2 line")
     ap.add_argument("--ttmc-sweep", action="store_true")

@@ -131,7 +131,9 @@ struct DevSolver {
     bool solve_resident(hipStream_t s, int N, double mu, double *b);
 };
 // x <- (L L^T)^{-1} x on the device for a lower Cholesky factor L (N x N,
-// column-major, leading dimension N), one right-hand side (trisolve.hip).
+// column-major, leading dimension N), one right-hand side (trisolve.hip);
+// used above order kPotrsMax, rocSOLVER's potrs below.
+constexpr int kPotrsMax = 8192;
 void chol_solve_dev(hipStream_t s, const double *L, int N, double *x);
 
 // Device products of the inner solve for large cores (devsolve.cpp):

@@ -1,9 +1,10 @@
 // Device help for the inner solve (Algorithm 5 step (i)) of large cores:
 //  - Cholesky solve of the (shifted) Newton system, for systems too large for
 //    the host (N = r(k1 - r) + r3(k3 - r3) reaches 2750 at rank (10,10,10),
-//    17000 at rank 20): rocSOLVER's FP64 potrf on the ctx's stream, then the
-//    blocked triangular solves of trisolve.hip; the matrix is symmetric, so
-//    row-major input is its own column-major transpose;
+//    17000 at rank 20): rocSOLVER's FP64 potrf, then its potrs up to order
+//    kPotrsMax and the blocked triangular solves of trisolve.hip beyond, on
+//    the ctx's stream; the matrix is symmetric, so row-major input is its
+//    own column-major transpose;
 //  - the dense products of the core (HOSVD Grams, mode-3 products, the
 //    rotation into [P P_perp], [S S_perp] coordinates) as rocBLAS FP64
 //    GEMMs.  Device matrices are column-major; a row-major host matrix
@@ -78,9 +79,17 @@ bool DevSolver::solve_resident(hipStream_t s, int N, double mu, double *b) {
     HIPCHECK(hipMemcpyAsync(&info, dinfo, sizeof(info), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
     if (info != 0) return false;
-    // the two triangular solves in 64-row blocks (rocSOLVER's potrs ran its
-    // triangular solves at ~20 ms each for order 17000)
-    chol_solve_dev(s, dA.as<double>(), N, db.as<double>());
+    // the two triangular solves: rocSOLVER's potrs, or for large orders the
+    // 64-row blocked solves (potrs ran its triangular solves at ~20 ms each
+    // at order 17000; below order 8192 potrs is the faster, e.g. 0.22 against
+    // 0.31 ms at order 500 and 2.0 against 3.9 ms at order 4096)
+    if (N <= kPotrsMax) {
+        if (rocsolver_dpotrs(h, rocblas_fill_lower, N, 1, dA.as<double>(), N, db.as<double>(),
+                             N) != rocblas_status_success)
+            fail(BKS_EDEVICE, "rocsolver_dpotrs");
+    } else {
+        chol_solve_dev(s, dA.as<double>(), N, db.as<double>());
+    }
     HIPCHECK(hipMemcpyAsync(b, db.ptr, (size_t)N * 8, hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
     return true;
