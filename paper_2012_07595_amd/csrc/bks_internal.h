@@ -135,6 +135,12 @@ struct DevSolver {
 // used above order kPotrsMax, rocSOLVER's potrs below.
 constexpr int kPotrsMax = 8192;
 void chol_solve_dev(hipStream_t s, const double *L, int N, double *x);
+// A = L L^T in place on the device (lower triangle, column-major, leading
+// dimension N); *info (device) gets 0, or the 1-based index of the first
+// non-positive pivot (cholesky.hip).  Used up to order kSmallCholMax,
+// rocSOLVER's potrf beyond.
+constexpr int kSmallCholMax = 4096;
+void chol_factor_dev(hipStream_t s, double *A, int N, int *info);
 
 // Device products of the inner solve for large cores (devsolve.cpp):
 // rocBLAS FP64 on the ctx stream, sharing the DevSolver's handle.
