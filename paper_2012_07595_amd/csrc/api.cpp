@@ -84,7 +84,7 @@ void PinnedBuf::ensure(size_t b) {
 
 void Ctx::release_workspaces() {
     for (DevBuf *b : {&ws_partial, &ws_pack1, &ws_pack2, &ws_fac1, &ws_fac2, &devsolve.dH,
-                      &devsolve.dA, &devsolve.db, &devsolve.dones, &devinner.dC, &devinner.dA,
+                      &devsolve.dA, &devsolve.db, &devinner.dC, &devinner.dA,
                       &devinner.dOut, &devinner.dT, &devinner.dY, &devinner.dOnes})
         b->release();
 }

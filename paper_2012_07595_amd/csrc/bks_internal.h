@@ -118,22 +118,31 @@ struct Tensor;
 struct DevSolver {
     void *handle = nullptr;  // rocblas_handle
     void *get_handle(hipStream_t s);  // created on first use, bound to s
-    DevBuf dH, dA, db, dones;
+    DevBuf dH, dA, db;
+    PinnedBuf pin;           // staging of the right-hand side and the result
     DevSolver() = default;
     DevSolver(const DevSolver &) = delete;
     DevSolver &operator=(const DevSolver &) = delete;
     ~DevSolver();
     // Solve (H + mu I) x = b (H N x N symmetric, row-major host) in place of
-    // b; false if it is not positive definite.  H is uploaded only when
-    // new_matrix (it stays on the device between calls).
+    // b; false if it is not positive definite (b is then unchanged).  H is
+    // uploaded only when new_matrix (it stays on the device between calls).
     bool solve(hipStream_t s, int N, const double *H, double mu, bool new_matrix, double *b);
     // The same with H already in dH (formed on the device).
     bool solve_resident(hipStream_t s, int N, double mu, double *b);
 };
+// dst = src + mu I for N x N matrices on the device (cholesky.hip).
+void shift_copy_dev(hipStream_t s, double *dst, const double *src, int N, double mu);
 // x <- (L L^T)^{-1} x on the device for a lower Cholesky factor L (N x N,
-// column-major, leading dimension N), one right-hand side (trisolve.hip);
-// used above order kPotrsMax, rocSOLVER's potrs below.
+// column-major, leading dimension N), one right-hand side (trisolve.hip):
+// chol_solve_small in one workgroup (x staged in LDS; it returns at once
+// when the device int *info is non-zero; orders up to kSolveWgLimit fit),
+// the multi-launch chol_solve_dev for the largest orders; in between
+// rocSOLVER's potrs is the faster.
+constexpr int kSolveWgLimit = 8192;
+constexpr int kSolveWgMax = 640;
 constexpr int kPotrsMax = 8192;
+void chol_solve_small(hipStream_t s, const double *L, int N, double *x, const int *info);
 void chol_solve_dev(hipStream_t s, const double *L, int N, double *x);
 // A = L L^T in place on the device (lower triangle, column-major, leading
 // dimension N); *info (device) gets 0, or the 1-based index of the first

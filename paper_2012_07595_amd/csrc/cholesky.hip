@@ -1,20 +1,17 @@
 // Cholesky factorisation A = L L^T on the device for the Newton systems of
 // the inner solve up to order kSmallCholMax (rocSOLVER's potrf is slower
 // there: its small kernels are launch-bound).  Right-looking in 32-column
-// blocks with two launches per block column:
-//   chol_panel   every workgroup factors the 32 x 32 diagonal block itself
-//                (one wave, a row per lane in registers, pivots broadcast
-//                by lane shuffles), then solves its 256 rows of the panel,
-//                x L_kk^T = a (a row per thread, in registers); workgroup 0
-//                also writes the diagonal block back;
-//   chol_update  the trailing lower triangle -= P P^T in 32 x 32 tiles.
-// A is column-major with leading dimension N (the symmetric Newton matrix,
-// whose row-major layout reads the same); only its lower triangle is read
-// and L overwrites it.  A non-positive (or NaN) pivot stops the
-// factorisation: its 1-based index goes to *info and every later kernel
-// returns at once.  Every sum has a fixed order, and the diagonal block is
-// factored by the same code in every workgroup, so all of them use the same
-// L_kk.
+// blocks with one launch per block column (chol_step): the panel of block
+// column k, into which the update by panel k-1 is folded, and, in other
+// workgroups of the same launch, the update by panel k-1 of the trailing
+// columns beyond block k (in a launch of its own, chol_trail, where those
+// tiles are too many for one round of the compute units).  A is column-major with leading dimension N (the
+// symmetric Newton matrix, whose row-major layout reads the same); only its
+// lower triangle is read and L overwrites it.  A non-positive (or NaN)
+// pivot stops the factorisation: its 1-based index goes to *info and every
+// later kernel returns at once.  Every sum has a fixed order, and the
+// diagonal block is factored by the same code in every workgroup, so all of
+// them use the same L_kk.
 #include <algorithm>
 
 #include "bks_internal.h"
@@ -25,94 +22,164 @@ namespace {
 
 constexpr int kCB = 32;  // block columns (= trailing-update tile)
 
-__global__ __launch_bounds__(256) void chol_panel(double *__restrict__ A, int64_t N, int64_t k0,
-                                                  int nb, int *__restrict__ info) {
-    __shared__ double Lk[kCB][kCB + 1];
-    __shared__ int bad;
-    if (*info != 0) return;
+// lane `l` (the same for every lane) of a wave's double
+__device__ inline double lane_read(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// 1 / sqrt(p) for p > 0: the hardware estimate and two Newton steps
+// y <- y + y (1 - p y^2) / 2 (each about doubles the correct bits; the
+// result is within an ulp or two, which the factorisation's backward
+// stability does not notice)
+__device__ inline double rsqrt_nr(double p) {
+    double y = __builtin_amdgcn_rsq(p);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) y = fma(0.5 * y, fma(-p * y, y, 1.0), y);
+    return y;
+}
+
+constexpr int kRowsPerWg = 192;  // panel rows per workgroup (waves 1-3)
+constexpr int kFuseMaxWg = 512;  // one fused step's workgroups: two per compute unit
+
+// A block column's panel with the previous panel's update folded in (the
+// workgroups of one launch below the panel count): the diagonal block
+// D = A_kk - P_k-1,k P_k-1,k^T is formed in LDS by all threads and
+// factored by wave 0 (a row per lane in registers, column entries
+// broadcast by lane reads, pivots from a refined reciprocal square root);
+// waves 1-3 meanwhile subtract the previous panel from their rows of the
+// block column (loaded at the start), then solve x L_kk^T = a (a row per
+// thread, times the pivots' reciprocals).  Workgroup 0 writes the diagonal
+// block back.
+__device__ __forceinline__ void panel_part(double *__restrict__ A, int64_t N, int64_t k0, int nb, int64_t p,
+                           int *__restrict__ info, double (*Lp)[kCB + 1],
+                           double (*Lk)[kCB + 1], double *rd, int *bad) {
     const int tid = threadIdx.x;
+    const bool fuse = k0 > 0;  // the previous block column's panel to apply
+    const int64_t kp = k0 - kCB;
+    // this thread's panel row.  Panel rows exist only below a full block
+    // (nb = kCB): a block with nb < kCB is the last one and has none.
+    const int64_t r = k0 + nb + p * kRowsPerWg + (tid - 64);
+    const bool has_row = tid >= 64 && r < N && nb == kCB;
+    double x[kCB], xp[kCB];
+    if (has_row) {
+#pragma unroll
+        for (int j = 0; j < kCB; ++j) x[j] = A[(k0 + j) * N + r];
+        if (fuse) {
+#pragma unroll
+            for (int l = 0; l < kCB; ++l) xp[l] = A[(kp + l) * N + r];
+        }
+    }
+    if (fuse) {
+        for (int idx = tid; idx < kCB * kCB; idx += 256) {
+            const int i = idx % kCB, l = idx / kCB;
+            Lp[i][l] = i < nb ? A[(kp + l) * N + k0 + i] : 0.0;
+        }
+    }
+    __syncthreads();
+    // D into Lk (lower triangle; wave 0 reads it before it writes L_kk there)
+    for (int idx = tid; idx < kCB * kCB; idx += 256) {
+        const int i = idx % kCB, j = idx / kCB;
+        double v = 0.0;
+        if (i < nb && j <= i) {
+            v = A[(k0 + j) * N + k0 + i];
+            if (fuse) {
+#pragma unroll 8
+                for (int l = 0; l < kCB; ++l) v = fma(-Lp[i][l], Lp[j][l], v);
+            }
+        }
+        Lk[i][j] = v;
+    }
+    __syncthreads();
     if (tid < 64) {
-        // wave 0: lane i < nb holds row i of the diagonal block
+        // lane i < nb holds row i of D, lanes nb <= i < kCB an identity
+        // row (they leave the block unchanged)
         const int i = tid;
         double row[kCB];
 #pragma unroll
         for (int j = 0; j < kCB; ++j)
-            row[j] = (i < nb && j <= i) ? A[(k0 + j) * N + k0 + i] : (i == j ? 1.0 : 0.0);
-        // no branches on the pivot inside the unrolled loop: a bad pivot is
-        // recorded and the (then meaningless) arithmetic runs on; columns
-        // past nb are identity rows and leave the block unchanged
+            row[j] = (i < nb && j <= i) ? Lk[i][j] : (i == j ? 1.0 : 0.0);
+        // Step j takes the pivot from lane j and column j's entries from
+        // lanes l > j; those are lower-triangle values.  The updates run on
+        // every lane without a mask, so a lane's entries right of its
+        // diagonal turn to garbage, which no lane ever reads.  No branches
+        // on the pivot inside the unrolled loop: a bad one is recorded and
+        // the (then meaningless) arithmetic runs on.
         int fail = 0;
+        double myrd = 1.0;
 #pragma unroll
         for (int j = 0; j < kCB; ++j) {
-            const double p = __shfl(row[j], j);
-            fail = (fail == 0 && j < nb && !(p > 0.0)) ? j + 1 : fail;
-            const double d = sqrt(p);
-            row[j] = i == j ? d : (i > j ? row[j] / d : row[j]);
+            const double pv = lane_read(row[j], j);
+            fail = (fail == 0 && j < nb && !(pv > 0.0)) ? j + 1 : fail;
+            const double rj = rsqrt_nr(pv);
+            row[j] = i == j ? pv * rj : row[j] * rj;
+            myrd = i == j ? rj : myrd;
 #pragma unroll
-            for (int l = j + 1; l < kCB; ++l) {
-                const double c = __shfl(row[j], l);  // L(l, j)
-                row[l] = i >= l ? row[l] - row[j] * c : row[l];
-            }
+            for (int l = j + 1; l < kCB; ++l) row[l] = fma(-row[j], lane_read(row[j], l), row[l]);
         }
         if (i < kCB) {
 #pragma unroll
             for (int j = 0; j < kCB; ++j) Lk[i][j] = row[j];
+            rd[i] = myrd;
         }
-        if (i == 0) bad = fail;
+        if (i == 0) *bad = fail;
+    } else if (has_row && fuse) {
+#pragma unroll
+        for (int j = 0; j < kCB; ++j) {
+            double v = x[j];
+#pragma unroll
+            for (int l = 0; l < kCB; ++l) v = fma(-xp[l], Lp[j][l], v);
+            x[j] = v;
+        }
     }
     __syncthreads();
-    if (bad != 0) {
-        if (blockIdx.x == 0 && tid == 0) *info = (int)(k0 + bad);
+    if (*bad != 0) {
+        if (p == 0 && tid == 0) *info = (int)(k0 + *bad);
         return;
     }
-    if (blockIdx.x == 0) {
+    if (p == 0) {
         for (int idx = tid; idx < nb * nb; idx += 256) {
             const int i = idx % nb, j = idx / nb;
             if (i >= j) A[(k0 + j) * N + k0 + i] = Lk[i][j];
         }
     }
-    // panel rows exist only below a full block (nb = kCB): a block with
-    // nb < kCB is the last one and has none
-    const int64_t r = k0 + nb + (int64_t)blockIdx.x * 256 + tid;
-    if (r >= N || nb != kCB) return;
-    double x[kCB];
-#pragma unroll
-    for (int j = 0; j < kCB; ++j) x[j] = A[(k0 + j) * N + r];
+    if (!has_row) return;
 #pragma unroll
     for (int j = 0; j < kCB; ++j) {
         double v = x[j];
 #pragma unroll
-        for (int l = 0; l < j; ++l) v -= x[l] * Lk[j][l];
-        x[j] = v / Lk[j][j];
+        for (int l = 0; l < j; ++l) v = fma(-x[l], Lk[j][l], v);
+        x[j] = v * rd[j];
     }
 #pragma unroll
     for (int j = 0; j < kCB; ++j) A[(k0 + j) * N + r] = x[j];
 }
 
-// trailing lower triangle: A[i, j] -= sum_l A[i, k0 + l] A[j, k0 + l] for
-// j0 <= j <= i < N, j0 = k0 + nb; one 32 x 32 tile (ti >= tj) per workgroup
-__global__ __launch_bounds__(256) void chol_update(double *__restrict__ A, int64_t N, int64_t k0,
-                                                   int nb, const int *__restrict__ info) {
-    __shared__ double Pi[kCB][kCB + 1], Pj[kCB][kCB + 1];
-    if (*info != 0) return;
-    const int64_t b = blockIdx.x;
+// One 32 x 32 tile (ti >= tj; b = ti (ti + 1) / 2 + tj) of the trailing
+// update with the panel of block column kp: A[i, j] -= sum_l A[i, kp + l]
+// A[j, kp + l] for j0 <= j <= i < N.
+__device__ __forceinline__ void update_tile(double *__restrict__ A, int64_t N, int64_t kp, int64_t j0, int64_t b,
+                            double (*Pi)[kCB + 1], double (*Pj)[kCB + 1]) {
     int64_t ti = (int64_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
     while (ti * (ti + 1) / 2 > b) --ti;
     while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
     const int64_t tj = b - ti * (ti + 1) / 2;
-    const int64_t j0 = k0 + nb;
     const int64_t i0 = j0 + ti * kCB, c0 = j0 + tj * kCB;
     const int tid = threadIdx.x;
     for (int idx = tid; idx < kCB * kCB; idx += 256) {
         const int rr = idx % kCB, l = idx / kCB;
         const int64_t ri = i0 + rr, rj = c0 + rr;
-        Pi[l][rr] = (l < nb && ri < N) ? A[(k0 + l) * N + ri] : 0.0;
-        Pj[l][rr] = (l < nb && rj < N) ? A[(k0 + l) * N + rj] : 0.0;
+        Pi[l][rr] = ri < N ? A[(kp + l) * N + ri] : 0.0;
+        Pj[l][rr] = rj < N ? A[(kp + l) * N + rj] : 0.0;
     }
     __syncthreads();
     const int ty = tid / 16, tx = tid % 16;  // 2 x 2 outputs per thread
     double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-    for (int l = 0; l < nb; ++l) {
+    // partly unrolled: fully unrolled, the LDS reads of all 32 steps are
+    // hoisted and take every register
+#pragma unroll 4
+    for (int l = 0; l < kCB; ++l) {
         const double a0 = Pi[l][2 * ty], a1 = Pi[l][2 * ty + 1];
         const double b0 = Pj[l][2 * tx], b1 = Pj[l][2 * tx + 1];
         acc[0][0] = fma(a0, b0, acc[0][0]);
@@ -129,7 +196,47 @@ __global__ __launch_bounds__(256) void chol_update(double *__restrict__ A, int64
         }
 }
 
+// Step k of the factorisation (k0 = 32 k): workgroups [0, gp) factor block
+// column k with panel k-1 folded in (panel_part); the rest apply panel k-1
+// to the trailing columns beyond block k (update_tile), which panel k does
+// not touch.  Every column thus receives every earlier panel's update before
+// its own step.
+__global__ __launch_bounds__(256) void chol_step(double *__restrict__ A, int64_t N, int64_t k0,
+                                                 int nb, int64_t gp, int *__restrict__ info) {
+    __shared__ double sm[2][kCB][kCB + 1];
+    __shared__ double rd[kCB];  // 1 / L(j, j)
+    __shared__ int bad;
+    if (*info != 0) return;
+    const int64_t w = blockIdx.x;
+    if (w < gp)
+        panel_part(A, N, k0, nb, w, info, sm[0], sm[1], rd, &bad);
+    else
+        update_tile(A, N, k0 - kCB, k0 + nb, w - gp, sm[0], sm[1]);
+}
+
+// The trailing update alone (the tiles of a step too many for one round of
+// the fused kernel, whose register use allows one workgroup per compute unit)
+__global__ __launch_bounds__(256) void chol_trail(double *__restrict__ A, int64_t N, int64_t kp,
+                                                  int64_t j0, const int *__restrict__ info) {
+    __shared__ double sm[2][kCB][kCB + 1];
+    if (*info != 0) return;
+    update_tile(A, N, kp, j0, blockIdx.x, sm[0], sm[1]);
+}
+
 __global__ void clear_info(int *info) { *info = 0; }
+
+// dst = src + mu I (N x N, leading dimension N): columns over grid.y,
+// rows over threads
+__global__ __launch_bounds__(256) void shift_copy(double *__restrict__ dst,
+                                                  const double *__restrict__ src, int64_t N,
+                                                  double mu) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= N) return;
+    for (int64_t j = blockIdx.y; j < N; j += gridDim.y) {
+        const int64_t e = j * N + i;
+        dst[e] = i == j ? src[e] + mu : src[e];
+    }
+}
 
 }  // namespace
 
@@ -139,13 +246,26 @@ void chol_factor_dev(hipStream_t s, double *A, int N, int *info) {
     for (int64_t k0 = 0; k0 < n; k0 += kCB) {
         const int nb = (int)std::min<int64_t>(kCB, n - k0);
         const int64_t rest = n - k0 - nb;
-        hipLaunchKernelGGL(chol_panel, dim3((unsigned)std::max<int64_t>(1, (rest + 255) / 256)),
-                           dim3(256), 0, s, A, n, k0, nb, info);
-        if (rest <= 0) continue;
-        const int64_t T = (rest + kCB - 1) / kCB;
-        hipLaunchKernelGGL(chol_update, dim3((unsigned)(T * (T + 1) / 2)), dim3(256), 0, s, A, n,
-                           k0, nb, info);
+        const int64_t gp = std::max<int64_t>(1, (rest + kRowsPerWg - 1) / kRowsPerWg);
+        // tiles of panel k-1's update beyond block column k: in the same
+        // launch while the whole grid fits one round of the compute units,
+        // else in a launch of their own
+        const int64_t T = k0 > 0 ? (rest + kCB - 1) / kCB : 0;
+        const int64_t tiles = T * (T + 1) / 2;
+        const bool fused = gp + tiles <= kFuseMaxWg;
+        hipLaunchKernelGGL(chol_step, dim3((unsigned)(gp + (fused ? tiles : 0))), dim3(256), 0, s,
+                           A, n, k0, nb, gp, info);
+        if (!fused)
+            hipLaunchKernelGGL(chol_trail, dim3((unsigned)tiles), dim3(256), 0, s, A, n, k0 - kCB,
+                               k0 + nb, info);
     }
+    HIPCHECK(hipGetLastError());
+}
+
+void shift_copy_dev(hipStream_t s, double *dst, const double *src, int N, double mu) {
+    const int64_t n = N;
+    hipLaunchKernelGGL(shift_copy, dim3((unsigned)((n + 255) / 256), (unsigned)std::min<int64_t>(n, 4096)),
+                       dim3(256), 0, s, dst, src, n, mu);
     HIPCHECK(hipGetLastError());
 }
 

@@ -2,10 +2,12 @@
 //  - Cholesky solve of the (shifted) Newton system, for systems too large for
 //    the host (N = r(k1 - r) + r3(k3 - r3) reaches 2750 at rank (10,10,10),
 //    17000 at rank 20): the blocked factorisation of cholesky.hip up to
-//    order kSmallCholMax and rocSOLVER's FP64 potrf beyond, then rocSOLVER's
-//    potrs up to order kPotrsMax and the blocked triangular solves of
-//    trisolve.hip beyond, on the ctx's stream; the matrix is symmetric, so
-//    row-major input is its own column-major transpose;
+//    order kSmallCholMax and rocSOLVER's FP64 potrf beyond, then the
+//    triangular solves (one workgroup of trisolve.hip up to order
+//    kSolveWgMax, rocSOLVER's potrs up to kPotrsMax, the multi-launch
+//    blocked solves of trisolve.hip beyond), all on the ctx's stream with
+//    one synchronisation per solve; the matrix is symmetric, so row-major
+//    input is its own column-major transpose;
 //  - the dense products of the core (HOSVD Grams, mode-3 products, the
 //    rotation into [P P_perp], [S S_perp] coordinates) as rocBLAS FP64
 //    GEMMs.  Device matrices are column-major; a row-major host matrix
@@ -50,55 +52,50 @@ bool DevSolver::solve(hipStream_t s, int N, const double *H, double mu, bool new
 }
 
 bool DevSolver::solve_resident(hipStream_t s, int N, double mu, double *b) {
-    rocblas_handle h = static_cast<rocblas_handle>(get_handle(s));
     const size_t bytes = (size_t)N * N * 8;
     if (dH.bytes < bytes) fail(BKS_EINVAL, "Newton matrix not on the device");
     dA.ensure(bytes);
     db.ensure((size_t)N * 8 + 64);
-    HIPCHECK(hipMemcpyAsync(dA.ptr, dH.ptr, bytes, hipMemcpyDeviceToDevice, s));
-    if (mu != 0.0) {
-        // A += mu I: an AXPY of a vector of ones onto the diagonal (stride N + 1)
-        if (dones.bytes < (size_t)N * 8) {
-            // ones over the whole allocation (ensure adds slack): a later,
-            // larger order that fits finds them written.  The upload runs on
-            // the solve's own stream, which does not wait for the null stream.
-            dones.ensure((size_t)N * 8);
-            std::vector<double> ones(dones.bytes / 8, 1.0);
-            HIPCHECK(hipMemcpyAsync(dones.ptr, ones.data(), ones.size() * 8, hipMemcpyHostToDevice, s));
-            HIPCHECK(hipStreamSynchronize(s));
-        }
-        if (rocblas_daxpy(h, N, &mu, dones.as<double>(), 1, dA.as<double>(), N + 1) !=
-            rocblas_status_success)
-            fail(BKS_EDEVICE, "rocblas_daxpy");
-    }
-    HIPCHECK(hipMemcpyAsync(db.ptr, b, (size_t)N * 8, hipMemcpyHostToDevice, s));
-    rocblas_int *dinfo = reinterpret_cast<rocblas_int *>(db.as<char>() + (size_t)N * 8);
+    pin.ensure((size_t)N * 8 + 64);
+    double *st = reinterpret_cast<double *>(pin.ptr);
+    shift_copy_dev(s, dA.as<double>(), dH.as<double>(), N, mu);
+    std::memcpy(st, b, (size_t)N * 8);
+    HIPCHECK(hipMemcpyAsync(db.ptr, st, (size_t)N * 8, hipMemcpyHostToDevice, s));
+    int *dinfo = reinterpret_cast<int *>(db.as<char>() + (size_t)N * 8);
     // our blocked factorisation up to kSmallCholMax (0.70 against 1.19 ms at
     // order 500, 4.6 against 7.8 ms at 2750), rocSOLVER's potrf beyond
     if (N <= kSmallCholMax) {
+        chol_factor_dev(s, dA.as<double>(), N, dinfo);
+    } else {
         static_assert(sizeof(rocblas_int) == sizeof(int), "info is an int");
-        chol_factor_dev(s, dA.as<double>(), N, reinterpret_cast<int *>(dinfo));
-    } else if (rocsolver_dpotrf(h, rocblas_fill_lower, N, dA.as<double>(), N, dinfo) !=
-               rocblas_status_success) {
-        fail(BKS_EDEVICE, "rocsolver_dpotrf");
+        rocblas_handle h = static_cast<rocblas_handle>(get_handle(s));
+        if (rocsolver_dpotrf(h, rocblas_fill_lower, N, dA.as<double>(), N,
+                             reinterpret_cast<rocblas_int *>(dinfo)) != rocblas_status_success)
+            fail(BKS_EDEVICE, "rocsolver_dpotrf");
     }
-    rocblas_int info = 0;
-    HIPCHECK(hipMemcpyAsync(&info, dinfo, sizeof(info), hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipStreamSynchronize(s));
-    if (info != 0) return false;
-    // the two triangular solves: rocSOLVER's potrs, or for large orders the
-    // 64-row blocked solves (potrs ran its triangular solves at ~20 ms each
-    // at order 17000; below order 8192 potrs is the faster, e.g. 0.22 against
-    // 0.31 ms at order 500 and 2.0 against 3.9 ms at order 4096)
-    if (N <= kPotrsMax) {
+    // the two triangular solves, enqueued behind the factorisation: the
+    // one-workgroup solve for small orders (it skips itself after a failed
+    // factorisation), rocSOLVER's potrs up to kPotrsMax, the multi-launch
+    // blocked solves beyond (potrs ran each triangular solve at ~15-20 ms at
+    // order 17000); the latter two run on after a failure and their result
+    // is dropped
+    if (N <= kSolveWgMax) {
+        chol_solve_small(s, dA.as<double>(), N, db.as<double>(), dinfo);
+    } else if (N <= kPotrsMax) {
+        rocblas_handle h = static_cast<rocblas_handle>(get_handle(s));
         if (rocsolver_dpotrs(h, rocblas_fill_lower, N, 1, dA.as<double>(), N, db.as<double>(),
                              N) != rocblas_status_success)
             fail(BKS_EDEVICE, "rocsolver_dpotrs");
     } else {
         chol_solve_dev(s, dA.as<double>(), N, db.as<double>());
     }
-    HIPCHECK(hipMemcpyAsync(b, db.ptr, (size_t)N * 8, hipMemcpyDeviceToHost, s));
+    // the solution and info in one transfer, one synchronisation
+    HIPCHECK(hipMemcpyAsync(st, db.ptr, (size_t)N * 8 + sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
+    int info = 0;
+    std::memcpy(&info, st + N, sizeof(int));
+    if (info != 0) return false;
+    std::memcpy(b, st, (size_t)N * 8);
     return true;
 }
 
