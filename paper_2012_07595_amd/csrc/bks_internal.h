@@ -140,16 +140,20 @@ void shift_copy_dev(hipStream_t s, double *dst, const double *src, int N, double
 // the multi-launch chol_solve_dev for the largest orders; in between
 // rocSOLVER's potrs is the faster.
 constexpr int kSolveWgLimit = 8192;
-constexpr int kSolveWgMax = 640;
+constexpr int kSolveWgMax = 1024;
 constexpr int kPotrsMax = 8192;
-void chol_solve_small(hipStream_t s, const double *L, int N, double *x, const int *info);
+// forward = false: only the backward solve L^T x = x (after a factorisation
+// that substituted forward already)
+void chol_solve_small(hipStream_t s, const double *L, int N, double *x, const int *info,
+                      bool forward = true);
 void chol_solve_dev(hipStream_t s, const double *L, int N, double *x);
 // A = L L^T in place on the device (lower triangle, column-major, leading
 // dimension N); *info (device) gets 0, or the 1-based index of the first
-// non-positive pivot (cholesky.hip).  Used up to order kSmallCholMax,
-// rocSOLVER's potrf beyond.
+// non-positive pivot (cholesky.hip).  With b (device, N) the forward
+// substitution runs along and b becomes L^{-1} b.  Used up to order
+// kSmallCholMax, rocSOLVER's potrf beyond.
 constexpr int kSmallCholMax = 4096;
-void chol_factor_dev(hipStream_t s, double *A, int N, int *info);
+void chol_factor_dev(hipStream_t s, double *A, int N, int *info, double *b = nullptr);
 
 // Device products of the inner solve for large cores (devsolve.cpp):
 // rocBLAS FP64 on the ctx stream, sharing the DevSolver's handle.

@@ -7,8 +7,10 @@
 // columns beyond block k (in a launch of its own, chol_trail, where those
 // tiles are too many for one round of the compute units).  A is column-major with leading dimension N (the
 // symmetric Newton matrix, whose row-major layout reads the same); only its
-// lower triangle is read and L overwrites it.  A non-positive (or NaN)
-// pivot stops the factorisation: its 1-based index goes to *info and every
+// lower triangle is read and L overwrites it.  Given a right-hand side b,
+// the forward substitution L y = b rides along: step k solves block k of y
+// with L_kk and subtracts its terms from the rows below, so b holds y at
+// the end.  A non-positive (or NaN) pivot stops the factorisation: its 1-based index goes to *info and every
 // later kernel returns at once.  Every sum has a fixed order, and the
 // diagonal block is factored by the same code in every workgroup, so all of
 // them use the same L_kk.
@@ -50,11 +52,12 @@ constexpr int kFuseMaxWg = 512;  // one fused step's workgroups: two per compute
 // broadcast by lane reads, pivots from a refined reciprocal square root);
 // waves 1-3 meanwhile subtract the previous panel from their rows of the
 // block column (loaded at the start), then solve x L_kk^T = a (a row per
-// thread, times the pivots' reciprocals).  Workgroup 0 writes the diagonal
+// thread, right-looking, times the pivots' reciprocals).  Workgroup 0 writes the diagonal
 // block back.
-__device__ __forceinline__ void panel_part(double *__restrict__ A, int64_t N, int64_t k0, int nb, int64_t p,
+__device__ __forceinline__ void panel_part(double *__restrict__ A, int64_t N, int64_t k0, int nb,
+                                           int64_t p, double *__restrict__ bvec,
                            int *__restrict__ info, double (*Lp)[kCB + 1],
-                           double (*Lk)[kCB + 1], double *rd, int *bad) {
+                           double (*Lk)[kCB + 1], double *rd, double *yb, int *bad) {
     const int tid = threadIdx.x;
     const bool fuse = k0 > 0;  // the previous block column's panel to apply
     const int64_t kp = k0 - kCB;
@@ -62,7 +65,11 @@ __device__ __forceinline__ void panel_part(double *__restrict__ A, int64_t N, in
     // (nb = kCB): a block with nb < kCB is the last one and has none.
     const int64_t r = k0 + nb + p * kRowsPerWg + (tid - 64);
     const bool has_row = tid >= 64 && r < N && nb == kCB;
+    const bool solve_b = bvec != nullptr;
     double x[kCB], xp[kCB];
+    double bv = 0.0;  // b at this thread's panel row, or (wave 0) at row k0 + tid of the block
+    if (solve_b && (has_row || (tid < nb)))
+        bv = bvec[has_row ? r : k0 + tid];
     if (has_row) {
 #pragma unroll
         for (int j = 0; j < kCB; ++j) x[j] = A[(k0 + j) * N + r];
@@ -70,6 +77,13 @@ __device__ __forceinline__ void panel_part(double *__restrict__ A, int64_t N, in
 #pragma unroll
             for (int l = 0; l < kCB; ++l) xp[l] = A[(kp + l) * N + r];
         }
+    }
+    // the diagonal block's entries this thread forms (idx = tid + 256 m)
+    double dk[kCB * kCB / 256];
+#pragma unroll
+    for (int m = 0; m < kCB * kCB / 256; ++m) {
+        const int idx = tid + 256 * m, i = idx % kCB, j = idx / kCB;
+        dk[m] = (i < nb && j <= i) ? A[(k0 + j) * N + k0 + i] : 0.0;
     }
     if (fuse) {
         for (int idx = tid; idx < kCB * kCB; idx += 256) {
@@ -79,15 +93,13 @@ __device__ __forceinline__ void panel_part(double *__restrict__ A, int64_t N, in
     }
     __syncthreads();
     // D into Lk (lower triangle; wave 0 reads it before it writes L_kk there)
-    for (int idx = tid; idx < kCB * kCB; idx += 256) {
-        const int i = idx % kCB, j = idx / kCB;
-        double v = 0.0;
-        if (i < nb && j <= i) {
-            v = A[(k0 + j) * N + k0 + i];
-            if (fuse) {
+#pragma unroll
+    for (int m = 0; m < kCB * kCB / 256; ++m) {
+        const int idx = tid + 256 * m, i = idx % kCB, j = idx / kCB;
+        double v = dk[m];
+        if (fuse && i < nb && j <= i) {
 #pragma unroll 8
-                for (int l = 0; l < kCB; ++l) v = fma(-Lp[i][l], Lp[j][l], v);
-            }
+            for (int l = 0; l < kCB; ++l) v = fma(-Lp[i][l], Lp[j][l], v);
         }
         Lk[i][j] = v;
     }
@@ -125,12 +137,12 @@ __device__ __forceinline__ void panel_part(double *__restrict__ A, int64_t N, in
         }
         if (i == 0) *bad = fail;
     } else if (has_row && fuse) {
+        // x_j -= sum_l xp_l Lp[j][l], term by term over l (32 independent
+        // updates per term)
 #pragma unroll
-        for (int j = 0; j < kCB; ++j) {
-            double v = x[j];
+        for (int l = 0; l < kCB; ++l) {
 #pragma unroll
-            for (int l = 0; l < kCB; ++l) v = fma(-xp[l], Lp[j][l], v);
-            x[j] = v;
+            for (int j = 0; j < kCB; ++j) x[j] = fma(-xp[l], Lp[j][l], x[j]);
         }
     }
     __syncthreads();
@@ -144,16 +156,44 @@ __device__ __forceinline__ void panel_part(double *__restrict__ A, int64_t N, in
             if (i >= j) A[(k0 + j) * N + k0 + i] = Lk[i][j];
         }
     }
-    if (!has_row) return;
+    if (tid < 64) {
+        if (solve_b) {
+            // forward substitution of the block: y = L_kk^{-1} b_k, b_k final
+            // (every earlier step has subtracted its terms); lane i holds
+            // unknown i, lanes past nb hold zero
+            const int i = tid, ic = min(i, kCB - 1);
+            double yi = i < nb ? bv : 0.0;
 #pragma unroll
-    for (int j = 0; j < kCB; ++j) {
-        double v = x[j];
+            for (int j = 0; j < kCB; ++j) {
+                const double yj = lane_read(yi, j) * rd[j];
+                yi = i == j ? yj : ((i > j && i < nb) ? fma(-Lk[ic][j], yj, yi) : yi);
+            }
+            if (i < kCB) yb[i] = yi;
+            if (p == 0 && i < nb) bvec[k0 + i] = yi;
+        }
+    } else if (has_row) {
+        // right-looking: once x_j is final, its terms leave the later
+        // unknowns (independent updates, where a per-unknown sum is one
+        // dependent chain)
 #pragma unroll
-        for (int l = 0; l < j; ++l) v = fma(-x[l], Lk[j][l], v);
-        x[j] = v * rd[j];
+        for (int j = 0; j < kCB; ++j) {
+            x[j] *= rd[j];
+#pragma unroll
+            for (int l = j + 1; l < kCB; ++l) x[l] = fma(-x[j], Lk[l][j], x[l]);
+        }
+#pragma unroll
+        for (int j = 0; j < kCB; ++j) A[(k0 + j) * N + r] = x[j];
     }
+    if (solve_b) {
+        // the block's solved unknowns leave the rows below: b_r -= L(r, k) y
+        __syncthreads();
+        if (has_row) {
+            double sb = bv;
 #pragma unroll
-    for (int j = 0; j < kCB; ++j) A[(k0 + j) * N + r] = x[j];
+            for (int j = 0; j < kCB; ++j) sb = fma(-x[j], yb[j], sb);
+            bvec[r] = sb;
+        }
+    }
 }
 
 // One 32 x 32 tile (ti >= tj; b = ti (ti + 1) / 2 + tj) of the trailing
@@ -202,14 +242,16 @@ __device__ __forceinline__ void update_tile(double *__restrict__ A, int64_t N, i
 // not touch.  Every column thus receives every earlier panel's update before
 // its own step.
 __global__ __launch_bounds__(256) void chol_step(double *__restrict__ A, int64_t N, int64_t k0,
-                                                 int nb, int64_t gp, int *__restrict__ info) {
+                                                 int nb, int64_t gp, double *__restrict__ bvec,
+                                                 int *__restrict__ info) {
     __shared__ double sm[2][kCB][kCB + 1];
     __shared__ double rd[kCB];  // 1 / L(j, j)
+    __shared__ double yb[kCB];  // the block's forward-substituted unknowns
     __shared__ int bad;
     if (*info != 0) return;
     const int64_t w = blockIdx.x;
     if (w < gp)
-        panel_part(A, N, k0, nb, w, info, sm[0], sm[1], rd, &bad);
+        panel_part(A, N, k0, nb, w, bvec, info, sm[0], sm[1], rd, yb, &bad);
     else
         update_tile(A, N, k0 - kCB, k0 + nb, w - gp, sm[0], sm[1]);
 }
@@ -240,7 +282,7 @@ __global__ __launch_bounds__(256) void shift_copy(double *__restrict__ dst,
 
 }  // namespace
 
-void chol_factor_dev(hipStream_t s, double *A, int N, int *info) {
+void chol_factor_dev(hipStream_t s, double *A, int N, int *info, double *b) {
     const int64_t n = N;
     hipLaunchKernelGGL(clear_info, dim3(1), dim3(1), 0, s, info);
     for (int64_t k0 = 0; k0 < n; k0 += kCB) {
@@ -254,7 +296,7 @@ void chol_factor_dev(hipStream_t s, double *A, int N, int *info) {
         const int64_t tiles = T * (T + 1) / 2;
         const bool fused = gp + tiles <= kFuseMaxWg;
         hipLaunchKernelGGL(chol_step, dim3((unsigned)(gp + (fused ? tiles : 0))), dim3(256), 0, s,
-                           A, n, k0, nb, gp, info);
+                           A, n, k0, nb, gp, b, info);
         if (!fused)
             hipLaunchKernelGGL(chol_trail, dim3((unsigned)tiles), dim3(256), 0, s, A, n, k0 - kCB,
                                k0 + nb, info);

@@ -2,11 +2,12 @@
 //  - Cholesky solve of the (shifted) Newton system, for systems too large for
 //    the host (N = r(k1 - r) + r3(k3 - r3) reaches 2750 at rank (10,10,10),
 //    17000 at rank 20): the blocked factorisation of cholesky.hip up to
-//    order kSmallCholMax and rocSOLVER's FP64 potrf beyond, then the
-//    triangular solves (one workgroup of trisolve.hip up to order
-//    kSolveWgMax, rocSOLVER's potrs up to kPotrsMax, the multi-launch
-//    blocked solves of trisolve.hip beyond), all on the ctx's stream with
-//    one synchronisation per solve; the matrix is symmetric, so row-major
+//    order kSmallCholMax (the forward substitution riding along) and
+//    rocSOLVER's FP64 potrf beyond, then the remaining triangular solves
+//    (one workgroup of trisolve.hip up to order kSolveWgMax, rocBLAS's trsv,
+//    rocSOLVER's potrs after potrf up to kPotrsMax, the multi-launch blocked
+//    solves of trisolve.hip beyond), all on the ctx's stream with one
+//    synchronisation per solve; the matrix is symmetric, so row-major
 //    input is its own column-major transpose;
 //  - the dense products of the core (HOSVD Grams, mode-3 products, the
 //    rotation into [P P_perp], [S S_perp] coordinates) as rocBLAS FP64
@@ -62,10 +63,12 @@ bool DevSolver::solve_resident(hipStream_t s, int N, double mu, double *b) {
     std::memcpy(st, b, (size_t)N * 8);
     HIPCHECK(hipMemcpyAsync(db.ptr, st, (size_t)N * 8, hipMemcpyHostToDevice, s));
     int *dinfo = reinterpret_cast<int *>(db.as<char>() + (size_t)N * 8);
-    // our blocked factorisation up to kSmallCholMax (0.70 against 1.19 ms at
-    // order 500, 4.6 against 7.8 ms at 2750), rocSOLVER's potrf beyond
-    if (N <= kSmallCholMax) {
-        chol_factor_dev(s, dA.as<double>(), N, dinfo);
+    // our blocked factorisation up to kSmallCholMax (0.30 against 1.18 ms at
+    // order 500, 2.7 against 7.8 ms at 2750), with the forward substitution
+    // riding along (db becomes L^{-1} b); rocSOLVER's potrf beyond
+    const bool own = N <= kSmallCholMax;
+    if (own) {
+        chol_factor_dev(s, dA.as<double>(), N, dinfo, db.as<double>());
     } else {
         static_assert(sizeof(rocblas_int) == sizeof(int), "info is an int");
         rocblas_handle h = static_cast<rocblas_handle>(get_handle(s));
@@ -73,14 +76,21 @@ bool DevSolver::solve_resident(hipStream_t s, int N, double mu, double *b) {
                              reinterpret_cast<rocblas_int *>(dinfo)) != rocblas_status_success)
             fail(BKS_EDEVICE, "rocsolver_dpotrf");
     }
-    // the two triangular solves, enqueued behind the factorisation: the
-    // one-workgroup solve for small orders (it skips itself after a failed
-    // factorisation), rocSOLVER's potrs up to kPotrsMax, the multi-launch
-    // blocked solves beyond (potrs ran each triangular solve at ~15-20 ms at
-    // order 17000); the latter two run on after a failure and their result
-    // is dropped
-    if (N <= kSolveWgMax) {
-        chol_solve_small(s, dA.as<double>(), N, db.as<double>(), dinfo);
+    // the remaining triangular solves, enqueued behind the factorisation:
+    // after our factorisation only L^T x = y, in one workgroup for small
+    // orders (it skips itself after a failed factorisation) or rocBLAS's
+    // trsv; after potrf both, by potrs up to kPotrsMax and by the
+    // multi-launch blocked solves beyond (potrs ran each triangular solve
+    // at ~15-20 ms at order 17000).  All but the one-workgroup solve run on
+    // after a failure and their result is dropped.
+    if (own && N <= kSolveWgMax) {
+        chol_solve_small(s, dA.as<double>(), N, db.as<double>(), dinfo, false);
+    } else if (own) {
+        rocblas_handle h = static_cast<rocblas_handle>(get_handle(s));
+        if (rocblas_dtrsv(h, rocblas_fill_lower, rocblas_operation_transpose,
+                          rocblas_diagonal_non_unit, N, dA.as<double>(), N, db.as<double>(),
+                          1) != rocblas_status_success)
+            fail(BKS_EDEVICE, "rocblas_dtrsv");
     } else if (N <= kPotrsMax) {
         rocblas_handle h = static_cast<rocblas_handle>(get_handle(s));
         if (rocsolver_dpotrs(h, rocblas_fill_lower, N, 1, dA.as<double>(), N, db.as<double>(),

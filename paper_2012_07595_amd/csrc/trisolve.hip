@@ -157,7 +157,7 @@ __device__ inline void fwd_apply(double *xs, int64_t N, int64_t k0, int64_t base
 
 __global__ __launch_bounds__(512) void chol_solve_wg(const double *__restrict__ L, int64_t N,
                                                      double *__restrict__ x,
-                                                     const int *__restrict__ info) {
+                                                     const int *__restrict__ info, int forward) {
     extern __shared__ double xs[];  // N
     __shared__ double Ld[kWgB][kWgB + 1];
     __shared__ double dinv[kWgB];
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(512) void chol_solve_wg(const double *__restrict__ 
     // forward: L y = x.  The first pass's panel entries are loaded before
     // the diagonal block is solved (they do not depend on it).  A block
     // with rows below it is a full one (nb = kWgB).
-    for (int64_t b = 0; b < nblk; ++b) {
+    for (int64_t b = 0; forward && b < nblk; ++b) {
         const int64_t k0 = b * kWgB;
         const int nb = (int)min((int64_t)kWgB, N - k0);
         __syncthreads();
@@ -274,10 +274,11 @@ void chol_solve_dev(hipStream_t s, const double *L, int N, double *x) {
     HIPCHECK(hipGetLastError());
 }
 
-void chol_solve_small(hipStream_t s, const double *L, int N, double *x, const int *info) {
+void chol_solve_small(hipStream_t s, const double *L, int N, double *x, const int *info,
+                      bool forward) {
     if (N < 1 || N > kSolveWgLimit) fail(BKS_EINVAL, "chol_solve_small: order out of range");
     hipLaunchKernelGGL(chol_solve_wg, dim3(1), dim3(kWgT), (size_t)N * sizeof(double), s, L,
-                       (int64_t)N, x, info);
+                       (int64_t)N, x, info, forward ? 1 : 0);
     HIPCHECK(hipGetLastError());
 }
 
