@@ -230,6 +230,9 @@ typedef struct {
     double rel_hist[512];  /* per outer iteration */
     double normF_hist[512];
     double svals2[65];  /* s_1..s_r2, s_{r2+1} of mode 2 (general tensors; = svals1 when U = V) */
+    int fp64_from;      /* mixed precision: the first outer iteration (HOOI: iteration) whose
+                           products ran in FP64 because the FP32 ones had reached their
+                           rounding floor; -1: none */
 } bks_info;
 
 /* Block Krylov-Schur solve (Algorithm 5 with U = V, section "A Tensor Krylov-Schur like method"): outputs U

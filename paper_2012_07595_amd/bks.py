@@ -63,7 +63,7 @@ class Info(C.Structure):
                 ("t_expand", C.c_double), ("t_core", C.c_double), ("t_inner", C.c_double),
                 ("t_step", C.c_double), ("t_total", C.c_double), ("n_hist", C.c_int),
                 ("rel_hist", C.c_double * 512), ("normF_hist", C.c_double * 512),
-                ("svals2", C.c_double * 65)]
+                ("svals2", C.c_double * 65), ("fp64_from", C.c_int)]
 
 
 class GParams(C.Structure):

@@ -33,6 +33,7 @@ struct View {
     const double *C;
     int k1, k3;
     InnerDevice *dev = nullptr;  // large cores: dense products on the device
+    bool hooi_dev = true;        // the HOOI and objective products too
     double at(int a, int b, int c) const { return C[a + (size_t)k1 * (b + (size_t)k1 * c)]; }
 };
 
@@ -101,7 +102,7 @@ void hooi_step(const View &V, int r, int r3, std::vector<double> &P, std::vector
     // M1(a, j + r*l) = sum_b CS(a, b, l) P(b, j), CS = C x_3 S (k1 x k1 x r3)
     const int w1 = r * r3;
     std::vector<double> M1((size_t)k1 * w1);
-    if (V.dev) {
+    if (V.dev && V.hooi_dev) {
         std::vector<double> out((size_t)k1 * w1);
         V.dev->mode3p(S.data(), r3, 0, r3, P.data(), r, out.data());
         for (int a = 0; a < k1; ++a)
@@ -118,7 +119,7 @@ void hooi_step(const View &V, int r, int r3, std::vector<double> &P, std::vector
     // M3(c, i + r*j) = sum_{a,b} C(a,b,c) P(a,i) P(b,j)
     const int w3 = r * r;
     std::vector<double> M3((size_t)k3 * w3);
-    if (V.dev) {
+    if (V.dev && V.hooi_dev) {
         V.dev->hooi3(P.data(), r, M3.data());
         lead_left(M3, k3, w3, r3, S);
         return;
@@ -407,7 +408,7 @@ double objective(const View &V, const std::vector<double> &P, const std::vector<
     const int k1 = V.k1;
     const size_t sl = (size_t)k1 * k1;
     std::vector<double> gl(r3, 0.0);
-    if (V.dev) {
+    if (V.dev && V.hooi_dev) {
         // M_l = CS_l P on the device; g = sum_l ||P^T M_l||^2
         std::vector<double> M((size_t)k1 * r * r3);
         V.dev->mode3p(S.data(), r3, 0, r3, P.data(), r, M.data());
@@ -460,6 +461,14 @@ double device_core_min() {
     return v;
 }
 
+double device_hooi_min() {
+    static const double v = [] {
+        const char *e = std::getenv("BKS_DEVICE_HOOI_MIN");
+        return e ? std::atof(e) : kDeviceHooiMin;
+    }();
+    return v;
+}
+
 int device_solve_min() {
     static const int v = [] {
         const char *e = std::getenv("BKS_DEVICE_SOLVE_MIN");
@@ -482,6 +491,7 @@ void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, do
     if (dev && (double)k1 * k1 * k3 >= dev_min) {
         dev->set_core(C.data(), k1, k3);
         V.dev = dev;
+        V.hooi_dev = (double)k1 * k1 * k3 >= device_hooi_min();
     }
     info = InnerInfo{};
     auto clk = [] {

@@ -57,6 +57,10 @@ struct InnerDevice {
 // (BKS_DEVICE_SOLVE_MIN overrides).
 constexpr double kDeviceCoreMin = 1.0e5;
 double device_core_min();
+// ... of which those with k1^2 k3 >= device_hooi_min() (BKS_DEVICE_HOOI_MIN)
+// also run the HOOI steps' and the objective's products there
+constexpr double kDeviceHooiMin = kDeviceCoreMin;
+double device_hooi_min();
 int device_solve_min();
 
 struct InnerInfo {

@@ -22,12 +22,38 @@ namespace la {
 
 namespace {
 
+// sum_j a[j] b[j] with 16 partial sums in AVX2 registers (fixed order:
+// lane sums, then the four registers, then the tail), where a plain loop
+// would be one dependent chain of FMAs
+inline double dot_avx(const double *a, const double *b, int n) {
+    __m256d s0 = _mm256_setzero_pd(), s1 = _mm256_setzero_pd();
+    __m256d s2 = _mm256_setzero_pd(), s3 = _mm256_setzero_pd();
+    int j = 0;
+    for (; j + 16 <= n; j += 16) {
+        s0 = _mm256_fmadd_pd(_mm256_loadu_pd(a + j), _mm256_loadu_pd(b + j), s0);
+        s1 = _mm256_fmadd_pd(_mm256_loadu_pd(a + j + 4), _mm256_loadu_pd(b + j + 4), s1);
+        s2 = _mm256_fmadd_pd(_mm256_loadu_pd(a + j + 8), _mm256_loadu_pd(b + j + 8), s2);
+        s3 = _mm256_fmadd_pd(_mm256_loadu_pd(a + j + 12), _mm256_loadu_pd(b + j + 12), s3);
+    }
+    for (; j + 4 <= n; j += 4) s0 = _mm256_fmadd_pd(_mm256_loadu_pd(a + j), _mm256_loadu_pd(b + j), s0);
+    const __m256d s = _mm256_add_pd(_mm256_add_pd(s0, s1), _mm256_add_pd(s2, s3));
+    alignas(32) double l[4];
+    _mm256_store_pd(l, s);
+    double r = (l[0] + l[1]) + (l[2] + l[3]);
+    for (; j < n; ++j) r += a[j] * b[j];
+    return r;
+}
+// orders from which top_eigvecs takes the reduced path
+constexpr int kTopEigMin = 24;
+
 // Reduce symmetric A (n x n, row-major, in Z) to tridiagonal T = Q^T A Q;
 // on return Z holds Q, d the diagonal and e[i] = T(i, i+1), e[n-1] = 0.
-void tridiagonalize(int n, std::vector<double> &Z, std::vector<double> &d,
-                    std::vector<double> &e) {
-    std::vector<double> A = Z;
-    std::vector<std::vector<double>> vs;
+// The reduction alone: the reflectors H_k = I - 2 v_k v_k^T (acting on
+// indices k+1 .. n-1; empty where the column was already reduced) in vs,
+// T in (d, e); A is overwritten.
+void tridiag_reduce(int n, std::vector<double> &A, std::vector<double> &d, std::vector<double> &e,
+                    std::vector<std::vector<double>> &vs) {
+    vs.clear();
     vs.reserve(n);
     std::vector<double> p(n), q(n);
     for (int k = 0; k + 2 < n; ++k) {
@@ -54,14 +80,9 @@ void tridiagonalize(int n, std::vector<double> &Z, std::vector<double> &d,
         const double inv = 1.0 / std::sqrt(vn2);
         for (int i = 0; i < len; ++i) v[i] *= inv;
         // A22 <- H A22 H with H = I - 2 v v^T
+        for (int i = 0; i < len; ++i) p[i] = dot_avx(&A[(size_t)(k + 1 + i) * n + k + 1], v.data(), len);
         double K = 0.0;
-        for (int i = 0; i < len; ++i) {
-            double s = 0.0;
-            const double *row = &A[(size_t)(k + 1 + i) * n + k + 1];
-            for (int j = 0; j < len; ++j) s += row[j] * v[j];
-            p[i] = s;
-            K += v[i] * s;
-        }
+        for (int i = 0; i < len; ++i) K += v[i] * p[i];
         for (int i = 0; i < len; ++i) q[i] = p[i] - K * v[i];
         for (int i = 0; i < len; ++i) {
             double *row = &A[(size_t)(k + 1 + i) * n + k + 1];
@@ -80,6 +101,13 @@ void tridiagonalize(int n, std::vector<double> &Z, std::vector<double> &d,
     e.assign(n, 0.0);
     for (int i = 0; i < n; ++i) d[i] = A[(size_t)i * n + i];
     for (int i = 0; i + 1 < n; ++i) e[i] = A[(size_t)i * n + i + 1];
+}
+
+void tridiagonalize(int n, std::vector<double> &Z, std::vector<double> &d,
+                    std::vector<double> &e) {
+    std::vector<double> A = Z;
+    std::vector<std::vector<double>> vs;
+    tridiag_reduce(n, A, d, e, vs);
     // Q = H_0 H_1 ... : start from I and apply each reflector on the right
     Z.assign((size_t)n * n, 0.0);
     for (int i = 0; i < n; ++i) Z[(size_t)i * n + i] = 1.0;
@@ -102,11 +130,27 @@ void tridiagonalize(int n, std::vector<double> &Z, std::vector<double> &d,
 // Wilkinson and Reinsch's Handbook, vol. II), with its step order and
 // underflow exit; rotations accumulated into the rows of Zt = Z^T (row i of
 // Zt is column i of Z, so each rotation updates two contiguous rows).
-void tridiag_ql(int n, std::vector<double> &d, std::vector<double> &e, std::vector<double> &Zt) {
+void tridiag_ql(int n, std::vector<double> &d, std::vector<double> &e, std::vector<double> &Zt,
+                bool vectors = true) {
     const double eps = std::numeric_limits<double>::epsilon();
     double anorm = 0.0;
     for (int i = 0; i < n; ++i) anorm = std::max(anorm, std::fabs(d[i]) + std::fabs(e[i]));
     if (!std::isfinite(anorm)) throw std::runtime_error("eigensolver: non-finite input");
+    // Without vectors: T scaled to unit norm (the eigenvalues scale back),
+    // so that sqrt(a^2 + b^2) cannot overflow and replaces the slower
+    // library hypot.
+    double unscale = 1.0;
+    if (!vectors && anorm > 0.0) {
+        for (int i = 0; i < n; ++i) {
+            d[i] /= anorm;
+            e[i] /= anorm;
+        }
+        unscale = anorm;
+        anorm = 1.0;
+    }
+    auto pyth = [vectors](double a, double b) {
+        return vectors ? std::hypot(a, b) : std::sqrt(a * a + b * b);
+    };
     // an off-diagonal entry is negligible relative to its neighbours or, for
     // clusters of (near-)zero eigenvalues, relative to the matrix norm (and
     // always below the smallest normal number: a tiny matrix whose relative
@@ -123,7 +167,7 @@ void tridiag_ql(int n, std::vector<double> &d, std::vector<double> &e, std::vect
             if (m != l) {
                 if (++iter > 300) throw std::runtime_error("eigensolver did not converge");
                 double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-                double r = std::hypot(g, 1.0);
+                double r = pyth(g, 1.0);
                 g = d[m] - d[l] + e[l] / (g + std::copysign(r, g));
                 double s = 1.0, c = 1.0, p = 0.0;
                 int i;
@@ -131,7 +175,7 @@ void tridiag_ql(int n, std::vector<double> &d, std::vector<double> &e, std::vect
                 for (i = m - 1; i >= l; --i) {
                     double f = s * e[i];
                     const double b = c * e[i];
-                    r = std::hypot(f, g);
+                    r = pyth(f, g);
                     e[i + 1] = r;
                     if (r == 0.0) {
                         d[i + 1] -= p;
@@ -146,6 +190,7 @@ void tridiag_ql(int n, std::vector<double> &d, std::vector<double> &e, std::vect
                     p = s * r;
                     d[i + 1] = g + p;
                     g = c * r - b;
+                    if (!vectors) continue;
                     double *zi = &Zt[(size_t)i * n], *zi1 = &Zt[(size_t)(i + 1) * n];
                     for (int k = 0; k < n; ++k) {
                         const double a0 = zi[k], a1 = zi1[k];
@@ -160,6 +205,8 @@ void tridiag_ql(int n, std::vector<double> &d, std::vector<double> &e, std::vect
             }
         } while (m != l);
     }
+    if (unscale != 1.0)
+        for (int q = 0; q < n; ++q) d[q] *= unscale;
 }
 
 }  // namespace
@@ -274,13 +321,191 @@ void sym_eig(int n, const double *A, double *w, double *V) {
     }
 }
 
-void top_eigvecs(int n, const double *A, int r, double *Vr, double *wr) {
-    std::vector<double> w(n), V((size_t)n * n);
-    sym_eig(n, A, w.data(), V.data());
+namespace {
+
+// Eigenvectors of the symmetric tridiagonal T (d0, e0; e0[i] = T(i, i+1))
+// for the eigenvalues lam0[0..r) by inverse iteration: (T - sigma I) x = b by
+// Gaussian elimination with partial pivoting (U with two superdiagonals),
+// three solves from a fixed start vector.  Eigenvalues closer than 1e-3 |T|
+// form a cluster: their shifts are kept apart by 10 eps |T| and each solve
+// is orthogonalised against the cluster's earlier vectors (modified
+// Gram-Schmidt).  Y is n x r row-major.
+void tridiag_inverse_iteration(int n, const std::vector<double> &d0, const std::vector<double> &e0,
+                               const double *lam0, int r, std::vector<double> &Y) {
+    const double eps = std::numeric_limits<double>::epsilon();
+    double tnorm = 0.0;
     for (int i = 0; i < n; ++i)
-        for (int j = 0; j < r; ++j) Vr[(size_t)i * r + j] = V[(size_t)i * n + j];
+        tnorm = std::max(tnorm, std::fabs(d0[i]) + (i > 0 ? std::fabs(e0[i - 1]) : 0.0) +
+                                    (i + 1 < n ? std::fabs(e0[i]) : 0.0));
+    // T / |T| (the vectors do not change), so that the solves' growth of up
+    // to 1 / eps cannot overflow a sum of squares
+    const double sc = tnorm > 0.0 ? 1.0 / tnorm : 1.0;
+    std::vector<double> d(n), e(n), lamv(r);
+    for (int i = 0; i < n; ++i) {
+        d[i] = d0[i] * sc;
+        e[i] = e0[i] * sc;
+    }
+    for (int j = 0; j < r; ++j) lamv[j] = lam0[j] * sc;
+    const double *lam = lamv.data();
+    const double eps3 = eps;
+    const double ortol = 1e-3;
+    Y.assign((size_t)n * r, 0.0);
+    std::vector<double> u0(n), u1(n), u2(n), mult(n), x(n), b(n);
+    std::vector<char> swp(n);
+    double sigma_prev = 0.0;
+    int c0 = 0;  // first index of the current cluster
+    for (int j = 0; j < r; ++j) {
+        double sigma = lam[j];
+        if (j > 0 && lam[j - 1] - lam[j] < ortol) {
+            sigma = std::min(sigma, sigma_prev - 10.0 * eps3);
+        } else {
+            c0 = j;
+        }
+        sigma_prev = sigma;
+        // T - sigma I = P L U
+        double a = d[0] - sigma, bb = n > 1 ? e[0] : 0.0;
+        for (int i = 0; i + 1 < n; ++i) {
+            const double ei = e[i], dn = d[i + 1] - sigma, en = i + 2 < n ? e[i + 1] : 0.0;
+            if (std::fabs(a) >= std::fabs(ei)) {
+                swp[i] = 0;
+                if (a == 0.0) a = eps3;
+                u0[i] = a;
+                u1[i] = bb;
+                u2[i] = 0.0;
+                mult[i] = ei / a;
+                a = dn - mult[i] * bb;
+                bb = en;
+            } else {
+                swp[i] = 1;
+                u0[i] = ei;
+                u1[i] = dn;
+                u2[i] = en;
+                mult[i] = a / ei;
+                a = bb - mult[i] * dn;
+                bb = -mult[i] * en;
+            }
+        }
+        if (a == 0.0) a = eps3;
+        u0[n - 1] = a;
+        // fixed start vector (a small linear congruential sequence)
+        uint64_t st = 0x9e3779b97f4a7c15ull * (uint64_t)(j + 1);
+        for (int i = 0; i < n; ++i) {
+            st = st * 6364136223846793005ull + 1442695040888963407ull;
+            b[i] = (double)(st >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+        }
+        for (int it = 0; it < 3; ++it) {
+            // L^{-1} with the row swaps, then U x = y
+            for (int i = 0; i + 1 < n; ++i) {
+                if (swp[i]) std::swap(b[i], b[i + 1]);
+                b[i + 1] -= mult[i] * b[i];
+            }
+            for (int i = n - 1; i >= 0; --i) {
+                double s = b[i];
+                if (i + 1 < n) s -= u1[i] * x[i + 1];
+                if (i + 2 < n) s -= u2[i] * x[i + 2];
+                x[i] = s / u0[i];
+            }
+            for (int k = c0; k < j; ++k) {
+                double dot = 0.0;
+                for (int i = 0; i < n; ++i) dot += x[i] * Y[(size_t)i * r + k];
+                for (int i = 0; i < n; ++i) x[i] -= dot * Y[(size_t)i * r + k];
+            }
+            double nrm = 0.0;
+            for (int i = 0; i < n; ++i) nrm += x[i] * x[i];
+            nrm = std::sqrt(nrm);
+            if (!(nrm > 0.0) || !std::isfinite(nrm)) break;
+            for (int i = 0; i < n; ++i) b[i] = x[i] / nrm;
+        }
+        for (int i = 0; i < n; ++i) Y[(size_t)i * r + j] = b[i];
+    }
+}
+
+}  // namespace
+
+void top_eigvecs(int n, const double *A, int r, double *Vr, double *wr) {
+    auto full = [&] {
+        std::vector<double> w(n), V((size_t)n * n);
+        sym_eig(n, A, w.data(), V.data());
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < r; ++j) Vr[(size_t)i * r + j] = V[(size_t)i * n + j];
+        if (wr)
+            for (int j = 0; j < r; ++j) wr[j] = w[j];
+    };
+    // small orders, or most of the spectrum wanted: the full decomposition
+    if (n < kTopEigMin || 2 * r > n) return full();
+    // Householder reduction (reflectors kept), eigenvalues alone by the QL
+    // iteration, the r wanted vectors of T by inverse iteration, then back
+    // through the reflectors: 4/3 n^3 + O(n^2 r) instead of the ~6 n^3 of
+    // accumulating every rotation into n vectors
+    std::vector<double> Z(A, A + (size_t)n * n);
+    for (double x : Z)
+        if (!std::isfinite(x)) throw std::runtime_error("eigensolver: non-finite input");
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            const double s = 0.5 * (Z[(size_t)i * n + j] + Z[(size_t)j * n + i]);
+            Z[(size_t)i * n + j] = Z[(size_t)j * n + i] = s;
+        }
+    const std::vector<double> Asym = Z;
+    std::vector<double> d, e, none;
+    std::vector<std::vector<double>> vs;
+    tridiag_reduce(n, Z, d, e, vs);
+    std::vector<double> dq = d, eq = e;
+    try {
+        tridiag_ql(n, dq, eq, none, false);
+    } catch (const std::runtime_error &) {
+        return full();
+    }
+    std::sort(dq.begin(), dq.end(), std::greater<double>());
+    std::vector<double> Y;
+    tridiag_inverse_iteration(n, d, e, dq.data(), r, Y);
+    // X = H_0 (H_1 (... H_{n-3} Y)), a reflector at a time over whole rows
+    std::vector<double> sv(r);
+    for (int k = (int)vs.size() - 1; k >= 0; --k) {
+        const auto &v = vs[k];
+        if (v.empty()) continue;
+        const int len = n - k - 1;
+        std::fill(sv.begin(), sv.end(), 0.0);
+        for (int i = 0; i < len; ++i) {
+            const double vi = v[i];
+            const double *yr = &Y[(size_t)(k + 1 + i) * r];
+            for (int j = 0; j < r; ++j) sv[j] += vi * yr[j];
+        }
+        for (int i = 0; i < len; ++i) {
+            const double vi2 = 2.0 * v[i];
+            double *yr = &Y[(size_t)(k + 1 + i) * r];
+            for (int j = 0; j < r; ++j) yr[j] -= vi2 * sv[j];
+        }
+    }
+    // accept only eigenpairs of the input to working accuracy: residuals
+    // |A x - lam x| and the departure from orthonormality within
+    // 64 n eps (relative to max_i sum_j |A(i, j)|); else the full solver
+    const double eps = std::numeric_limits<double>::epsilon();
+    double anorm = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) s += std::fabs(Asym[(size_t)i * n + j]);
+        anorm = std::max(anorm, s);
+    }
+    const double tol = 64.0 * n * eps;
+    std::vector<double> AY((size_t)n * r);
+    dgemm(false, false, n, r, n, 1.0, Asym.data(), n, Y.data(), r, 0.0, AY.data(), r);
+    for (int j = 0; j < r; ++j) {
+        double rn = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const double ri = AY[(size_t)i * r + j] - dq[j] * Y[(size_t)i * r + j];
+            rn += ri * ri;
+        }
+        if (!(std::sqrt(rn) <= tol * std::max(anorm, std::numeric_limits<double>::min())))
+            return full();
+        for (int k = 0; k <= j; ++k) {
+            double o = 0.0;
+            for (int i = 0; i < n; ++i) o += Y[(size_t)i * r + j] * Y[(size_t)i * r + k];
+            if (!(std::fabs(o - (k == j ? 1.0 : 0.0)) <= tol)) return full();
+        }
+    }
+    std::copy(Y.begin(), Y.end(), Vr);
     if (wr)
-        for (int j = 0; j < r; ++j) wr[j] = w[j];
+        for (int j = 0; j < r; ++j) wr[j] = dq[j];
 }
 
 bool cholesky(int n, double *A, double *fail_pivot) {

@@ -20,7 +20,11 @@ void sym_eig(int n, const double *A, double *w, double *V);
 // sym_eig falls back to it if the QL iteration stalls.
 void sym_eig_jacobi(int n, const double *A, double *w, double *V);
 
-// Leading r eigenvectors (descending eigenvalues) as an n x r row-major matrix.
+// Leading r eigenvectors (descending eigenvalues) as an n x r row-major
+// matrix.  From order 24, with r <= n / 2: Householder reduction, the
+// eigenvalues alone by the QL iteration, the r vectors by inverse iteration
+// on the tridiagonal and back through the reflectors, accepted when the
+// residuals and orthonormality are within 64 n eps (else sym_eig).
 void top_eigvecs(int n, const double *A, int r, double *Vr, double *wr = nullptr);
 
 // Cholesky A = U^T U in place (row-major: U in the upper triangle, the

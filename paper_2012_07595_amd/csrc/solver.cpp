@@ -16,7 +16,11 @@
 //          ones: a stationary point of the full problem is then an exact
 //          fixed point of the mixed iteration.  The basis itself is always
 //          kept and orthogonalised in FP64 (with an FP32 shadow copy feeding
-//          the FP32 products).
+//          the FP32 products).  The other slices carry FP32 rounding, which
+//          leaves the gradient wandering at a floor (~1e-11 relative at the
+//          C3 shape); once it is below 1e-9 and an outer iteration fails to
+//          halve the best value so far, the remaining iterations run their
+//          products in FP64 (bks_info.fp64_from).
 #include <algorithm>
 #include <array>
 #include <chrono>
@@ -148,6 +152,7 @@ struct Solver {
     int64_t m, n;
     int r, r3, p, stages, variant;
     bool mixed;
+    bool fp32;  // expansion and core products in FP32 (mixed, until the floor)
     double tau64 = 1e-14, tau32 = 1e-5;
 
     int k1cap = 0, k3cap = 0, qcap = 0;
@@ -164,7 +169,7 @@ struct Solver {
 
     Solver(Ctx &c_, Tensor &t_, hipStream_t s_, int r_, int r3_, int p_, int st, int var, bool mx)
         : c(c_), t(t_), s(s_), m(t_.m), n(t_.n), r(r_), r3(r3_), p(p_), stages(st),
-          variant(var), mixed(mx) {}
+          variant(var), mixed(mx), fp32(mx) {}
 
     // Pinned staging for the small host <-> device copies of the
     // orthogonalisation: uploads are queued without a wait (their staging
@@ -314,7 +319,9 @@ struct Solver {
         T1.alloc((size_t)m * r * r3 * 8);
         T3h.alloc((size_t)n * (r * (r + 1) / 2) * 8);
         const size_t Q = (size_t)k1cap * (k1cap + 1) / 2;
-        T3core.alloc((size_t)n * Q * (mixed ? 4 : 8));
+        // FP64 wide even in mixed mode: its last iterations may form the
+        // core in FP64
+        T3core.alloc((size_t)n * Q * 8);
         Cdev.alloc((size_t)k3cap * Q * 8);
         const size_t small = (size_t)std::max(k1cap, k3cap) * std::max(qcap, 64) * 8 + 4096;
         Hd.alloc(small);
@@ -605,8 +612,8 @@ struct Solver {
                     ws.push_back({1, pr[1], pr[2]});
                 }
             }
-            const int prec = mixed ? BKS_F32 : BKS_F64;
-            const double tau = mixed ? tau32 : tau64;
+            const int prec = fp32 ? BKS_F32 : BKS_F64;
+            const double tau = fp32 ? tau32 : tau64;
             double *B = P64.as<double>();
             for (auto &pr : us) {
                 int q = 0;
@@ -628,7 +635,7 @@ struct Solver {
     // C = A.(X, X, Z) as a k1 x k1 x k3 column-major host array.
     void form_core(std::vector<double> &C) {
         const int Q = k1 * (k1 + 1) / 2;
-        if (mixed) {
+        if (fp32) {
             ttmc(c, t, BKS_FREE3, X32.ptr, k1cap, k1, nullptr, 0, 0, true, BKS_F32, T3core.ptr, Q, s);
             gemm_tn_f32f64(Zcol(0), k3cap, T3core.as<float>(), Q, n, k3, Q, Cdev.as<double>(), Q, c, s);
         } else {
@@ -718,6 +725,7 @@ void draw_start(uint64_t seed, int64_t rows, int w, std::vector<double> &out) {
 void fill_info(bks_info *info, const Solver::StepOut &o, int iters, bool conv, int k1, int k3,
                double normA) {
     if (!info) return;
+    info->fp64_from = -1;
     info->outer_iters = iters;
     info->converged = conv ? 1 : 0;
     info->k1 = k1;
@@ -751,7 +759,7 @@ size_t solve_footprint(int64_t m, int64_t n, int64_t nnz, const bks_params &prm)
     if (mixed) b += (size_t)m * k1 * 4 + (size_t)n * k3 * 4 + rows * q * 4;
     b += rows * q * 8 + 2 * rows * std::max<size_t>(q, std::max(prm.r, prm.r3)) * 8;
     b += (size_t)m * prm.r * prm.r3 * 8 + (size_t)n * (prm.r * (prm.r + 1) / 2) * 8;
-    b += (size_t)n * Q * (mixed ? 4 : 8) + k3 * Q * 8;
+    b += (size_t)n * Q * 8 + k3 * Q * 8;
     b += 2 * std::max(k1, k3) * std::max<size_t>(q, 64) * 8 + 64 * 64 * 16;
     // product partials and the split reductions (grow-only workspaces, 25%
     // slack each): a core product wider than 24 columns keeps one k1 x k1
@@ -759,7 +767,7 @@ size_t solve_footprint(int64_t m, int64_t n, int64_t nnz, const bks_params &prm)
     // (chunk width clamp(nnz / 4096, 256, 2048), widened so that at most
     // max(n + 1, 512 MB / partial) chunks exist, every slice at least one),
     // plus a block-packed copy of X
-    const size_t cts = mixed ? 4 : 8;
+    const size_t cts = 8;  // FP64 partials also in mixed mode (its last iterations)
     if (k1 > 24) {
         const double per_item = (double)k1 * k1 * cts;
         const int64_t max_items = std::max<int64_t>(n + 1, (int64_t)(536870912.0 / per_item));
@@ -827,6 +835,7 @@ int run_bks(Ctx &c, Tensor &t, const bks_params &prm, double *U, double *W, doub
     bool conv = false;
     std::vector<double> C, P, Sm;
     std::vector<double> rel_hist, f_hist;
+    int fp64_from = -1;
     long inner_newton = 0;
     int last_k1 = S.k1, last_k3 = S.k3;
     bool cancelled = false;
@@ -913,6 +922,16 @@ int run_bks(Ctx &c, Tensor &t, const bks_params &prm, double *U, double *W, doub
             break;
         }
         if (it >= max_outer) break;
+        // mixed precision at its floor: below 1e-9 an outer iteration that
+        // does not halve the best gradient so far switches the remaining
+        // expansion and core products to FP64
+        if (S.fp32 && o.rel < 1e-9 && rel_hist.size() >= 2) {
+            const double best_before = *std::min_element(rel_hist.begin(), rel_hist.end() - 1);
+            if (o.rel > 0.5 * best_before) {
+                S.fp32 = false;
+                fp64_from = it;
+            }
+        }
         // stagnation at the rounding floor above tol: once below 1e-10, 30
         // outer iterations without halving the best gradient end the solve
         // (not converged; the iterate is returned).  Slow linear convergence
@@ -932,6 +951,7 @@ int run_bks(Ctx &c, Tensor &t, const bks_params &prm, double *U, double *W, doub
     S.outputs(U, W, F, o.F1);
     fill_info(info, o, it, conv, last_k1, last_k3, std::sqrt(t.frob2));
     if (info) {
+        info->fp64_from = fp64_from;
         info->t_expand = te;
         info->t_core = tc;
         info->t_inner = ti;
@@ -1080,8 +1100,10 @@ int run_hooi(Ctx &c, Tensor &t, const hooi_params &prm, double *U, double *W, do
     int it = 0;
     std::vector<double> rel_hist;
     bool conv = rel <= tol;
+    int fp64_from = -1;
     while (!conv && it < max_iter) {
         const bool fp32 = mixed && rel > 1e-4;
+        if (mixed && !fp32 && fp64_from < 0) fp64_from = it;
         const int prec = fp32 ? BKS_F32 : BKS_F64;
         double *T = S.P64.as<double>();
         if (fp32) {
@@ -1113,6 +1135,7 @@ int run_hooi(Ctx &c, Tensor &t, const hooi_params &prm, double *U, double *W, do
                     F[a + (size_t)r * (b + (size_t)r * cc)] = F1[(size_t)a * q1 + b + r * cc];
     if (info) {
         std::memset(info, 0, sizeof(*info));
+        info->fp64_from = fp64_from;
         info->outer_iters = it;
         info->converged = conv ? 1 : 0;
         info->rel_grad = rel;
@@ -1716,6 +1739,7 @@ int run_gbks(Ctx &c, Tensor &t, const bks_gparams &prm, double *U, double *V, do
     S.outputs(U, V, W);
     if (F) std::copy(o.F.begin(), o.F.end(), F);
     if (info) {
+        info->fp64_from = -1;
         info->outer_iters = it;
         info->converged = conv ? 1 : 0;
         info->k1 = last_k[0];

@@ -434,6 +434,107 @@ static void check_eig() {
     std::printf("ok sym_eig\n");
 }
 
+// The leading r eigenvectors (reduced path: tridiagonal eigenvalues, inverse
+// iteration, back-transformation) against the full decomposition: the same
+// eigenvalues, the same projector onto the leading subspace, orthonormal
+// columns, small residuals; clustered spectra with the cut beside and inside
+// a cluster; extreme scales.
+static void check_top_eigvecs() {
+    std::mt19937_64 g(31);
+    std::normal_distribution<double> nd;
+    auto residual_ok = [](int n, const std::vector<double> &A, int r, const std::vector<double> &V,
+                          const std::vector<double> &w, double tol) {
+        double an = 0.0;
+        for (int i = 0; i < n; ++i) {
+            double s = 0.0;
+            for (int j = 0; j < n; ++j) s += std::fabs(A[(size_t)i * n + j]);
+            an = std::max(an, s);
+        }
+        for (int c = 0; c < r; ++c) {
+            double rn = 0.0;
+            for (int i = 0; i < n; ++i) {
+                double s = -w[c] * V[(size_t)i * r + c];
+                for (int j = 0; j < n; ++j) s += A[(size_t)i * n + j] * V[(size_t)j * r + c];
+                rn += s * s;
+            }
+            if (!(std::sqrt(rn) <= tol * an)) return false;
+            for (int c2 = 0; c2 <= c; ++c2) {
+                double o = 0.0;
+                for (int i = 0; i < n; ++i) o += V[(size_t)i * r + c] * V[(size_t)i * r + c2];
+                if (!(std::fabs(o - (c == c2 ? 1.0 : 0.0)) <= tol)) return false;
+            }
+        }
+        return true;
+    };
+    auto projector_gap = [](int n, int r, const std::vector<double> &V1, int ld1,
+                            const std::vector<double> &V2) {
+        double m = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) {
+                double a = 0.0, b = 0.0;
+                for (int j = 0; j < r; ++j) {
+                    a += V1[(size_t)i * ld1 + j] * V1[(size_t)k * ld1 + j];
+                    b += V2[(size_t)i * r + j] * V2[(size_t)k * r + j];
+                }
+                m = std::max(m, std::fabs(a - b));
+            }
+        return m;
+    };
+    // random symmetric matrices
+    for (int n : {24, 31, 70, 190})
+        for (int r : {1, 5, 10}) {
+            std::vector<double> A((size_t)n * n), w(n), V((size_t)n * n), wr(r), Vr((size_t)n * r);
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j <= i; ++j) A[(size_t)i * n + j] = A[(size_t)j * n + i] = nd(g);
+            la::sym_eig(n, A.data(), w.data(), V.data());
+            la::top_eigvecs(n, A.data(), r, Vr.data(), wr.data());
+            const double scale = std::max(std::fabs(w[0]), std::fabs(w[n - 1]));
+            for (int j = 0; j < r; ++j)
+                require(std::fabs(wr[j] - w[j]) <= 1e-13 * n * scale, "top_eigvecs: eigenvalues");
+            require(residual_ok(n, A, r, Vr, wr, 1e-12 * n), "top_eigvecs: residual");
+            // the leading subspace is determined up to rounding / gap
+            const double gap = (w[r - 1] - w[r]) / scale;
+            require(projector_gap(n, r, V, n, Vr) <= 1e-13 * n / std::max(gap, 1e-3),
+                    "top_eigvecs: leading subspace");
+        }
+    // clustered spectra: Q diag(5, 5, 5, 3, 3, 1, ...) Q^T
+    for (int n : {40, 100}) {
+        std::vector<double> M((size_t)n * n), Q((size_t)n * n), A((size_t)n * n, 0.0);
+        for (auto &x : M) x = nd(g);
+        la::qr_full(n, n, M.data(), Q.data());
+        std::vector<double> lam(n);
+        for (int i = 0; i < n; ++i) lam[i] = i < 3 ? 5.0 : i < 5 ? 3.0 : 1.0 / (1.0 + i);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double s = 0.0;
+                for (int k = 0; k < n; ++k) s += Q[(size_t)i * n + k] * lam[k] * Q[(size_t)j * n + k];
+                A[(size_t)i * n + j] = s;
+            }
+        for (int r : {2, 3, 5}) {
+            std::vector<double> wr(r), Vr((size_t)n * r);
+            la::top_eigvecs(n, A.data(), r, Vr.data(), wr.data());
+            for (int j = 0; j < r; ++j)
+                require(std::fabs(wr[j] - lam[j]) <= 1e-13 * n * 5.0, "top_eigvecs: cluster values");
+            require(residual_ok(n, A, r, Vr, wr, 1e-12 * n), "top_eigvecs: cluster residual");
+            if (r != 2)  // a cut between clusters fixes the subspace: Q(:, :r)
+                require(projector_gap(n, r, Q, n, Vr) <= 1e-12 * n, "top_eigvecs: cluster subspace");
+        }
+    }
+    // far-from-unit scales
+    for (double scale : {1e-150, 1e150}) {
+        const int n = 60, r = 4;
+        std::vector<double> A((size_t)n * n), wr(r), Vr((size_t)n * r), w(n), V((size_t)n * n);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j <= i; ++j) A[(size_t)i * n + j] = A[(size_t)j * n + i] = scale * nd(g);
+        la::sym_eig(n, A.data(), w.data(), V.data());
+        la::top_eigvecs(n, A.data(), r, Vr.data(), wr.data());
+        for (int j = 0; j < r; ++j)
+            require(std::fabs(wr[j] - w[j]) <= 1e-13 * n * std::fabs(w[0]), "top_eigvecs: scaled values");
+        require(residual_ok(n, A, r, Vr, wr, 1e-12 * n), "top_eigvecs: scaled residual");
+    }
+    std::printf("ok top_eigvecs\n");
+}
+
 // The device interface of the inner solve, implemented with plain loops from
 // its contract (inner.h): the inner solve must reach the same point through
 // it as through its own host products.
@@ -575,6 +676,7 @@ int main() {
     check_dgemm();
     check_cholesky_and_threads();
     check_eig();
+    check_top_eigvecs();
     check_inner_device();
     return 0;
 }

@@ -149,6 +149,32 @@ def test_bks_mixed_vs_oracle_c2_shaped(ctx):
     compare(ref, U2, W2, F2, info2, 1e-9)
 
 
+def test_bks_mixed_finishes_in_fp64(ctx):
+    """Asked for a gradient below every rounding floor, the mixed solver
+    switches its expansion and core products to FP64 once an outer
+    iteration below 1e-9 fails to halve the best gradient so far, and then
+    reaches the FP64 solver's floor; FP64 solves never report a switch."""
+    c = c2_small()
+    U0, W0 = workloads.random_start(c.m, c.n, 5, 5, 11)
+    ref = obks.bks_solve(otensor(c), 5, 5, U0, W0, tol=1e-11, inner_tol=1e-13)
+    t = ctx.upload_coo(c)
+    kw = dict(U0=U0, W0=W0, tol=1e-15, inner_tol=1e-13, max_outer=25)
+    U, W, F, info, rc = ctx.solve(t, 5, 5, precision=bks.PREC_MIXED, **kw)
+    U2, W2, F2, info2, rc2 = ctx.solve(t, 5, 5, precision=bks.PREC_FP64, **kw)
+    hist = [info.rel_hist[i] for i in range(info.outer_iters)]
+    hist2 = [info2.rel_hist[i] for i in range(info2.outer_iters)]
+    print("mixed: fp64_from", info.fp64_from, "rel_hist", " ".join(f"{x:.1e}" for x in hist))
+    print("fp64: rel_hist", " ".join(f"{x:.1e}" for x in hist2))
+    assert rc in (0, bks.ENOTCONV) and rc2 in (0, bks.ENOTCONV)
+    assert 1 <= info.fp64_from <= info.outer_iters
+    # the switch follows the rule: below 1e-9, no halving of the best so far
+    k = info.fp64_from
+    assert hist[k - 1] < 1e-9 and hist[k - 1] > 0.5 * min(hist[:k - 1])
+    assert min(hist[k:]) <= 10 * min(hist2)
+    assert info2.fp64_from == -1
+    compare(ref, U, W, F, info, 1e-9, tol_f=1e-12)
+
+
 _RANK8 = {}
 
 

@@ -2,7 +2,8 @@
 tensor-times-block kernels (every stored entry processed exactly once, split
 segments summed through the fixed-order tree) and the host dense kernels of
 the inner solve (register-blocked product, blocked Cholesky, symmetric
-eigensolver; results independent of the thread count), and the inner
+eigensolver and its leading-eigenvector path; results independent of the
+thread count), and the inner
 solve's device interface (a plain-loop implementation of its contract gives
 the same solution as the host products).  Compiles
 tests/cpp/host_logic.cpp with the library's host sources and runs it."""
@@ -43,7 +44,7 @@ def test_host_logic(tmp_path, build):
     print(r.stdout)
     assert r.returncode == 0, r.stdout + r.stderr
     for name in ("schedule", "group_schedule", "scale", "wide_schedule", "fix_tree", "dgemm",
-                 "cholesky_threads", "sym_eig", "inner_device"):
+                 "cholesky_threads", "sym_eig", "top_eigvecs", "inner_device"):
         assert f"ok {name}" in r.stdout
 
 
