@@ -275,9 +275,11 @@ void DevInner::rotate(const double *Qp, const double *Qs, int r, int r3, double 
     HIPCHECK(hipMemcpyAsync(hs, dYl, (ny + ny2) * 8, hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
     // dY keeps [Y | Y2] of this rank for newton_matrix
+    // (the Newton matrix in ds->dH stays: the inner solve forms it once per
+    // iteration and rotates trial points before it solves again with
+    // another shift)
     rot_r = r;
     rot_r3 = r3;
-    newton_n = 0;
     std::memcpy(Y, hs, ny * 8);
     if (C1 > 0) std::memcpy(Y2, hs + ny, ny2 * 8);
 }

@@ -504,7 +504,11 @@ void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, do
         for (int it = 0; it < hooi_warm; ++it) hooi_step(V, r, r3, P, S);
     }
     info.t_start = clk() - t0;
-    Blocks B;
+    Blocks B, Bn;
+    // with the products on the device, a trial point is judged from its
+    // rotation (g = ||F||^2 of the rotated core, the same sum of squares the
+    // objective forms), which an accepted step keeps for the next iteration
+    bool have_B = false;
     std::vector<double> G1, G3, d, Pn, Sn;
     // the Newton matrices (60 MB at rank (10,10,10)) are reused across calls
     static thread_local std::vector<double> tl_H, tl_Hs;
@@ -516,7 +520,8 @@ void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, do
     bool last_plain = false;
     while (true) {
         t0 = clk();
-        rotate(V, P, S, r, r3, B);
+        if (!have_B) rotate(V, P, S, r, r3, B);
+        have_B = false;
         double nf;
         info.rel = local_gradient(B, G1, G3, nf);
         info.t_rotate += clk() - t0;
@@ -587,7 +592,16 @@ void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, do
             }
             retract(k1, r, B.Qp, d.data(), Pn);
             retract(k3, r3, B.Qs, d.data() + nd, Sn);
-            const double g1 = objective(V, Pn, Sn, r, r3);
+            double g1;
+            if (V.dev) {
+                t0 = clk();
+                rotate(V, Pn, Sn, r, r3, Bn);
+                info.t_rotate += clk() - t0;
+                g1 = 0.0;
+                for (double v : Bn.F) g1 += v * v;
+            } else {
+                g1 = objective(V, Pn, Sn, r, r3);
+            }
             // g is a sum of ~k1^2 k3 rounded products: changes below 1e-13
             // relative are rounding noise, not descent
             if (g1 >= g0 * (1.0 - 1e-13)) {
@@ -595,6 +609,10 @@ void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, do
                 last_plain = (mu == 0.0);
                 P.swap(Pn);
                 S.swap(Sn);
+                if (V.dev) {
+                    std::swap(B, Bn);
+                    have_B = true;
+                }
                 mu = mu > mu0 ? mu / 4.0 : 0.0;
             } else {
                 mu = std::max(4.0 * mu, mu0);
