@@ -16,6 +16,8 @@
 // them use the same L_kk.
 #include <algorithm>
 
+#include <rocblas/rocblas.h>
+
 #include "bks_internal.h"
 
 namespace bks {
@@ -44,6 +46,8 @@ __device__ inline double rsqrt_nr(double p) {
 
 constexpr int kRowsPerWg = 192;  // panel rows per workgroup (waves 1-3)
 constexpr int kFuseMaxWg = 512;  // one fused step's workgroups: two per compute unit
+constexpr int64_t kPanel = 256;     // panel width of the large-order form
+constexpr int64_t kHybridMin = 8192;  // orders from which it is used
 
 // A block column's panel with the previous panel's update folded in (the
 // workgroups of one launch below the panel count): the diagonal block
@@ -55,11 +59,13 @@ constexpr int kFuseMaxWg = 512;  // one fused step's workgroups: two per compute
 // thread, right-looking, times the pivots' reciprocals).  Workgroup 0 writes the diagonal
 // block back.
 __device__ __forceinline__ void panel_part(double *__restrict__ A, int64_t N, int64_t k0, int nb,
-                                           int64_t p, double *__restrict__ bvec,
+                                           int64_t p, bool fold, double *__restrict__ bvec,
                            int *__restrict__ info, double (*Lp)[kCB + 1],
                            double (*Lk)[kCB + 1], double *rd, double *yb, int *bad) {
     const int tid = threadIdx.x;
-    const bool fuse = k0 > 0;  // the previous block column's panel to apply
+    // the previous block column's panel to apply (not when a panel's first
+    // step follows the rank-kPanel update of the whole trailing matrix)
+    const bool fuse = fold && k0 > 0;
     const int64_t kp = k0 - kCB;
     // this thread's panel row.  Panel rows exist only below a full block
     // (nb = kCB): a block with nb < kCB is the last one and has none.
@@ -196,15 +202,24 @@ __device__ __forceinline__ void panel_part(double *__restrict__ A, int64_t N, in
     }
 }
 
-// One 32 x 32 tile (ti >= tj; b = ti (ti + 1) / 2 + tj) of the trailing
-// update with the panel of block column kp: A[i, j] -= sum_l A[i, kp + l]
-// A[j, kp + l] for j0 <= j <= i < N.
-__device__ __forceinline__ void update_tile(double *__restrict__ A, int64_t N, int64_t kp, int64_t j0, int64_t b,
-                            double (*Pi)[kCB + 1], double (*Pj)[kCB + 1]) {
-    int64_t ti = (int64_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
-    while (ti * (ti + 1) / 2 > b) --ti;
-    while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
-    const int64_t tj = b - ti * (ti + 1) / 2;
+// One 32 x 32 tile of the trailing update with the panel of block column
+// kp: A[i, j] -= sum_l A[i, kp + l] A[j, kp + l] for j0 <= j <= i < N, j in
+// the first cp tile columns: tiles (ti >= tj, tj < cp) numbered by rows of
+// the triangle while ti < cp (b = ti (ti + 1) / 2 + tj), then cp per row.
+__device__ __forceinline__ void update_tile(double *__restrict__ A, int64_t N, int64_t kp, int64_t j0,
+                                            int64_t b, int64_t cp, double (*Pi)[kCB + 1],
+                                            double (*Pj)[kCB + 1]) {
+    int64_t ti, tj;
+    const int64_t tri = cp * (cp + 1) / 2;
+    if (b < tri) {
+        ti = (int64_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+        while (ti * (ti + 1) / 2 > b) --ti;
+        while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
+        tj = b - ti * (ti + 1) / 2;
+    } else {
+        ti = cp + (b - tri) / cp;
+        tj = (b - tri) % cp;
+    }
     const int64_t i0 = j0 + ti * kCB, c0 = j0 + tj * kCB;
     const int tid = threadIdx.x;
     for (int idx = tid; idx < kCB * kCB; idx += 256) {
@@ -242,7 +257,8 @@ __device__ __forceinline__ void update_tile(double *__restrict__ A, int64_t N, i
 // not touch.  Every column thus receives every earlier panel's update before
 // its own step.
 __global__ __launch_bounds__(256) void chol_step(double *__restrict__ A, int64_t N, int64_t k0,
-                                                 int nb, int64_t gp, double *__restrict__ bvec,
+                                                 int nb, int64_t gp, int fold, int64_t cp,
+                                                 double *__restrict__ bvec,
                                                  int *__restrict__ info) {
     __shared__ double sm[2][kCB][kCB + 1];
     __shared__ double rd[kCB];  // 1 / L(j, j)
@@ -251,18 +267,19 @@ __global__ __launch_bounds__(256) void chol_step(double *__restrict__ A, int64_t
     if (*info != 0) return;
     const int64_t w = blockIdx.x;
     if (w < gp)
-        panel_part(A, N, k0, nb, w, bvec, info, sm[0], sm[1], rd, yb, &bad);
+        panel_part(A, N, k0, nb, w, fold != 0, bvec, info, sm[0], sm[1], rd, yb, &bad);
     else
-        update_tile(A, N, k0 - kCB, k0 + nb, w - gp, sm[0], sm[1]);
+        update_tile(A, N, k0 - kCB, k0 + nb, w - gp, cp, sm[0], sm[1]);
 }
 
 // The trailing update alone (the tiles of a step too many for one round of
 // the fused kernel, whose register use allows one workgroup per compute unit)
 __global__ __launch_bounds__(256) void chol_trail(double *__restrict__ A, int64_t N, int64_t kp,
-                                                  int64_t j0, const int *__restrict__ info) {
+                                                  int64_t j0, int64_t cp,
+                                                  const int *__restrict__ info) {
     __shared__ double sm[2][kCB][kCB + 1];
     if (*info != 0) return;
-    update_tile(A, N, kp, j0, blockIdx.x, sm[0], sm[1]);
+    update_tile(A, N, kp, j0, blockIdx.x, cp, sm[0], sm[1]);
 }
 
 __global__ void clear_info(int *info) { *info = 0; }
@@ -282,24 +299,43 @@ __global__ __launch_bounds__(256) void shift_copy(double *__restrict__ dst,
 
 }  // namespace
 
-void chol_factor_dev(hipStream_t s, double *A, int N, int *info, double *b) {
+void chol_factor_dev(hipStream_t s, double *A, int N, int *info, double *b, void *blas) {
     const int64_t n = N;
+    // large orders: panels of kPanel columns factored by the steps below
+    // (their trailing tiles restricted to the panel's columns), each followed
+    // by one rank-kPanel update of the rest of the matrix on rocBLAS (dsyrk)
+    const int64_t panel = (blas && n >= kHybridMin) ? kPanel : n;
     hipLaunchKernelGGL(clear_info, dim3(1), dim3(1), 0, s, info);
-    for (int64_t k0 = 0; k0 < n; k0 += kCB) {
-        const int nb = (int)std::min<int64_t>(kCB, n - k0);
-        const int64_t rest = n - k0 - nb;
-        const int64_t gp = std::max<int64_t>(1, (rest + kRowsPerWg - 1) / kRowsPerWg);
-        // tiles of panel k-1's update beyond block column k: in the same
-        // launch while the whole grid fits one round of the compute units,
-        // else in a launch of their own
-        const int64_t T = k0 > 0 ? (rest + kCB - 1) / kCB : 0;
-        const int64_t tiles = T * (T + 1) / 2;
-        const bool fused = gp + tiles <= kFuseMaxWg;
-        hipLaunchKernelGGL(chol_step, dim3((unsigned)(gp + (fused ? tiles : 0))), dim3(256), 0, s,
-                           A, n, k0, nb, gp, b, info);
-        if (!fused)
-            hipLaunchKernelGGL(chol_trail, dim3((unsigned)tiles), dim3(256), 0, s, A, n, k0 - kCB,
-                               k0 + nb, info);
+    for (int64_t p0 = 0; p0 < n; p0 += panel) {
+        const int64_t p1 = std::min(n, p0 + panel);
+        for (int64_t k0 = p0; k0 < p1; k0 += kCB) {
+            const int nb = (int)std::min<int64_t>(kCB, n - k0);
+            const int64_t rest = n - k0 - nb;
+            const int64_t gp = std::max<int64_t>(1, (rest + kRowsPerWg - 1) / kRowsPerWg);
+            // panel k-1 folded into block column k, and its update of the
+            // columns beyond block k within this panel: in the same launch
+            // while the whole grid fits one round of the compute units, else
+            // in a launch of their own.  A panel's first step has neither
+            // (the rank-kPanel update covered them).
+            const bool fold = k0 > p0;
+            const int64_t T = fold ? (rest + kCB - 1) / kCB : 0;
+            const int64_t cp = std::min<int64_t>(T, (p1 - k0 - nb + kCB - 1) / kCB);
+            const int64_t tiles = cp * (cp + 1) / 2 + (T - cp) * cp;
+            const bool fused = gp + tiles <= kFuseMaxWg;
+            hipLaunchKernelGGL(chol_step, dim3((unsigned)(gp + (fused ? tiles : 0))), dim3(256), 0,
+                               s, A, n, k0, nb, gp, fold ? 1 : 0, cp, b, info);
+            if (!fused && tiles > 0)
+                hipLaunchKernelGGL(chol_trail, dim3((unsigned)tiles), dim3(256), 0, s, A, n,
+                                   k0 - kCB, k0 + nb, cp, info);
+        }
+        if (p1 < n) {
+            const double alpha = -1.0, beta = 1.0;
+            if (rocblas_dsyrk(static_cast<rocblas_handle>(blas), rocblas_fill_lower,
+                              rocblas_operation_none, (rocblas_int)(n - p1), (rocblas_int)(p1 - p0),
+                              &alpha, A + p0 * n + p1, (rocblas_int)n, &beta, A + p1 * n + p1,
+                              (rocblas_int)n) != rocblas_status_success)
+                fail(BKS_EDEVICE, "rocblas_dsyrk");
+        }
     }
     HIPCHECK(hipGetLastError());
 }

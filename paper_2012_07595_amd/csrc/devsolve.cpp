@@ -68,7 +68,7 @@ bool DevSolver::solve_resident(hipStream_t s, int N, double mu, double *b) {
     // riding along (db becomes L^{-1} b); rocSOLVER's potrf beyond
     const bool own = N <= kSmallCholMax;
     if (own) {
-        chol_factor_dev(s, dA.as<double>(), N, dinfo, db.as<double>());
+        chol_factor_dev(s, dA.as<double>(), N, dinfo, db.as<double>(), get_handle(s));
     } else {
         static_assert(sizeof(rocblas_int) == sizeof(int), "info is an int");
         rocblas_handle h = static_cast<rocblas_handle>(get_handle(s));
@@ -85,6 +85,8 @@ bool DevSolver::solve_resident(hipStream_t s, int N, double mu, double *b) {
     // after a failure and their result is dropped.
     if (own && N <= kSolveWgMax) {
         chol_solve_small(s, dA.as<double>(), N, db.as<double>(), dinfo, false);
+    } else if (own && N > kPotrsMax) {
+        chol_solve_dev(s, dA.as<double>(), N, db.as<double>(), false);
     } else if (own) {
         rocblas_handle h = static_cast<rocblas_handle>(get_handle(s));
         if (rocblas_dtrsv(h, rocblas_fill_lower, rocblas_operation_transpose,

@@ -251,10 +251,10 @@ __global__ __launch_bounds__(512) void chol_solve_wg(const double *__restrict__ 
 
 }  // namespace
 
-void chol_solve_dev(hipStream_t s, const double *L, int N, double *x) {
+void chol_solve_dev(hipStream_t s, const double *L, int N, double *x, bool forward) {
     const int64_t n = N;
     const int64_t nblk = (n + kTriB - 1) / kTriB;
-    for (int64_t b = 0; b < nblk; ++b) {
+    for (int64_t b = 0; forward && b < nblk; ++b) {
         const int64_t k0 = b * kTriB;
         const int nb = (int)std::min<int64_t>(kTriB, n - k0);
         hipLaunchKernelGGL(tri_block_lower, dim3(1), dim3(64), 0, s, L, n, k0, nb, x);
