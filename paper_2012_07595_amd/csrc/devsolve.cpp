@@ -2,11 +2,13 @@
 //  - Cholesky solve of the (shifted) Newton system, for systems too large for
 //    the host (N = r(k1 - r) + r3(k3 - r3) reaches 2750 at rank (10,10,10),
 //    17000 at rank 20): the blocked factorisation of cholesky.hip up to
-//    order kSmallCholMax (the forward substitution riding along) and
-//    rocSOLVER's FP64 potrf beyond, then the remaining triangular solves
-//    (one workgroup of trisolve.hip up to order kSolveWgMax, rocBLAS's trsv,
-//    rocSOLVER's potrs after potrf up to kPotrsMax, the multi-launch blocked
-//    solves of trisolve.hip beyond), all on the ctx's stream with one
+//    order kSmallCholMax (the forward substitution riding along; 256-column
+//    panels with a rocBLAS dsyrk update from order 8192) and rocSOLVER's
+//    FP64 potrf beyond, then the remaining triangular solves (after ours
+//    only the backward one: one workgroup of trisolve.hip up to order
+//    kSolveWgMax, rocBLAS's trsv up to kPotrsMax, the multi-launch blocked
+//    solve beyond; after potrf, potrs up to kPotrsMax and the blocked
+//    solves beyond), all on the ctx's stream with one
 //    synchronisation per solve; the matrix is symmetric, so row-major
 //    input is its own column-major transpose;
 //  - the dense products of the core (HOSVD Grams, mode-3 products, the
@@ -63,9 +65,10 @@ bool DevSolver::solve_resident(hipStream_t s, int N, double mu, double *b) {
     std::memcpy(st, b, (size_t)N * 8);
     HIPCHECK(hipMemcpyAsync(db.ptr, st, (size_t)N * 8, hipMemcpyHostToDevice, s));
     int *dinfo = reinterpret_cast<int *>(db.as<char>() + (size_t)N * 8);
-    // our blocked factorisation up to kSmallCholMax (0.30 against 1.18 ms at
-    // order 500, 2.7 against 7.8 ms at 2750), with the forward substitution
-    // riding along (db becomes L^{-1} b); rocSOLVER's potrf beyond
+    // our blocked factorisation up to kSmallCholMax (0.30 against 1.18 ms on
+    // potrf at order 500, 2.6 against 7.8 ms at 2750, 61 against 106 ms at
+    // 17000), with the forward substitution riding along (db becomes
+    // L^{-1} b); rocSOLVER's potrf beyond
     const bool own = N <= kSmallCholMax;
     if (own) {
         chol_factor_dev(s, dA.as<double>(), N, dinfo, db.as<double>(), get_handle(s));
