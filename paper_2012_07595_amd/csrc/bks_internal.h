@@ -136,9 +136,10 @@ void shift_copy_dev(hipStream_t s, double *dst, const double *src, int N, double
 // x <- (L L^T)^{-1} x on the device for a lower Cholesky factor L (N x N,
 // column-major, leading dimension N), one right-hand side (trisolve.hip):
 // chol_solve_small in one workgroup (x staged in LDS; it returns at once
-// when the device int *info is non-zero; orders up to kSolveWgLimit fit),
-// the multi-launch chol_solve_dev for the largest orders; in between
-// rocSOLVER's potrs is the faster.
+// when the device int *info is non-zero; orders up to kSolveWgLimit fit;
+// used up to kSolveWgMax), the multi-launch chol_solve_dev beyond
+// kPotrsMax; in between rocBLAS's trsv (rocSOLVER's potrs after potrf) is
+// the faster.
 constexpr int kSolveWgLimit = 8192;
 constexpr int kSolveWgMax = 1024;
 constexpr int kPotrsMax = 8192;

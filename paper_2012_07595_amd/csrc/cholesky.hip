@@ -1,19 +1,24 @@
 // Cholesky factorisation A = L L^T on the device for the Newton systems of
 // the inner solve up to order kSmallCholMax (rocSOLVER's potrf is slower
-// there: its small kernels are launch-bound).  Right-looking in 32-column
+// at every order measured, 256 to 17000: its small kernels are launch-bound
+// at small orders, its panel work at large ones).  Right-looking in 32-column
 // blocks with one launch per block column (chol_step): the panel of block
 // column k, into which the update by panel k-1 is folded, and, in other
 // workgroups of the same launch, the update by panel k-1 of the trailing
 // columns beyond block k (in a launch of its own, chol_trail, where those
-// tiles are too many for one round of the compute units).  A is column-major with leading dimension N (the
-// symmetric Newton matrix, whose row-major layout reads the same); only its
-// lower triangle is read and L overwrites it.  Given a right-hand side b,
-// the forward substitution L y = b rides along: step k solves block k of y
-// with L_kk and subtracts its terms from the rows below, so b holds y at
-// the end.  A non-positive (or NaN) pivot stops the factorisation: its 1-based index goes to *info and every
-// later kernel returns at once.  Every sum has a fixed order, and the
-// diagonal block is factored by the same code in every workgroup, so all of
-// them use the same L_kk.
+// tiles are too many for one round of the compute units).  From order
+// kHybridMin the blocks are grouped in panels of kPanel columns: the steps
+// update only the panel's columns and one rank-kPanel dsyrk (rocBLAS)
+// updates the rest of the matrix after each panel.  A is column-major with
+// leading dimension N (the symmetric Newton matrix, whose row-major layout
+// reads the same); only its lower triangle is read and L overwrites it.
+// Given a right-hand side b, the forward substitution L y = b rides along:
+// step k solves block k of y with L_kk and subtracts its terms from the
+// rows below, so b holds y at the end.  A non-positive (or NaN) pivot
+// stops the factorisation: its 1-based index goes to *info and every later
+// kernel returns at once.  Every sum has a fixed order, and the diagonal
+// block is factored by the same code in every workgroup, so all of them
+// use the same L_kk.
 #include <algorithm>
 
 #include <rocblas/rocblas.h>

@@ -10,7 +10,9 @@
 //    the block's panel.  One launch for both solves, so no gaps between
 //    kernels.
 //  - chol_solve_dev: the same blocking over several launches, with
-//    multi-workgroup panel passes, for larger orders.
+//    multi-workgroup panel passes, for the largest orders.
+// Both can skip the forward solve (after a factorisation that substituted
+// forward already).
 // Every sum runs in a fixed order (no atomics), so the result does not
 // change from run to run.
 #include <algorithm>
