@@ -178,8 +178,9 @@ struct DevInner : InnerDevice {
     void mode3p(const double *Sv, int ldS, int l0, int nl, const double *P, int r,
                 double *out) override;
     void hooi3(const double *P, int r, double *M3) override;
-    void rotate(const double *Qp, const double *Qs, int r, int r3, double *Y,
-                double *Y2) override;
+    void rotate(const double *Qp, const double *Qs, int r, int r3, double *Y, double *Y2,
+                bool partial) override;
+    bool forms_newton() const override { return true; }
     bool newton_matrix(int r, int r3, double *diag) override;  // newton.hip
     bool newton_solve(double mu, double *b) override;
 };

@@ -242,7 +242,8 @@ void DevInner::hooi3(const double *P, int r, double *M3) {
     std::memcpy(M3, hs + np, no * 8);
 }
 
-void DevInner::rotate(const double *Qp, const double *Qs, int r, int r3, double *Y, double *Y2) {
+void DevInner::rotate(const double *Qp, const double *Qs, int r, int r3, double *Y, double *Y2,
+                      bool partial) {
     rocblas_handle h = static_cast<rocblas_handle>(ds->get_handle(s));
     const int64_t sl = (int64_t)k1 * k1;
     const int C1 = k3 - r3;
@@ -277,7 +278,18 @@ void DevInner::rotate(const double *Qp, const double *Qs, int r, int r3, double 
                  dT.as<double>(), k1, (int64_t)k1 * r, dY2, k1, (int64_t)k1 * r, C1);
     }
     // (the upload has been consumed before the download lands: same stream)
-    HIPCHECK(hipMemcpyAsync(hs, dYl, (ny + ny2) * 8, hipMemcpyDeviceToHost, s));
+    const size_t py = (size_t)k1 * r * r3, py2 = (size_t)r * r * C1;
+    if (partial) {
+        // the first r columns of each Y_l and the first r rows of each Y2
+        // column: the gradient's blocks (the Newton matrix reads dY here)
+        HIPCHECK(hipMemcpy2DAsync(hs, (size_t)k1 * r * 8, dYl, (size_t)sl * 8, (size_t)k1 * r * 8,
+                                  (size_t)r3, hipMemcpyDeviceToHost, s));
+        if (C1 > 0)
+            HIPCHECK(hipMemcpy2DAsync(hs + py, (size_t)r * 8, dY2, (size_t)k1 * 8, (size_t)r * 8,
+                                      (size_t)r * C1, hipMemcpyDeviceToHost, s));
+    } else {
+        HIPCHECK(hipMemcpyAsync(hs, dYl, (ny + ny2) * 8, hipMemcpyDeviceToHost, s));
+    }
     HIPCHECK(hipStreamSynchronize(s));
     // dY keeps [Y | Y2] of this rank for newton_matrix
     // (the Newton matrix in ds->dH stays: the inner solve forms it once per
@@ -285,8 +297,13 @@ void DevInner::rotate(const double *Qp, const double *Qs, int r, int r3, double 
     // another shift)
     rot_r = r;
     rot_r3 = r3;
-    std::memcpy(Y, hs, ny * 8);
-    if (C1 > 0) std::memcpy(Y2, hs + ny, ny2 * 8);
+    if (partial) {
+        std::memcpy(Y, hs, py * 8);
+        if (C1 > 0) std::memcpy(Y2, hs + py, py2 * 8);
+    } else {
+        std::memcpy(Y, hs, ny * 8);
+        if (C1 > 0) std::memcpy(Y2, hs + ny, ny2 * 8);
+    }
 }
 
 }  // namespace bks

@@ -142,10 +142,13 @@ struct Blocks {
     std::vector<double> B110;     // A1 x A1 x r3   (x,y,c)    at x + A1*(y + A1*c)
     std::vector<double> B001;     // r x r x C1     (a,b,z)    at a + r*(b + r*z)
     std::vector<double> B101;     // A1 x r x C1    (x,b,z)    at x + A1*(b + r*z)
+    bool partial = false;         // B110, B101 left on the device (not filled)
 };
 
+// `partial` (device path only): the device keeps B110 and B101, which only
+// the Newton matrix reads, and forms that matrix itself.
 void rotate(const View &V, const std::vector<double> &P, const std::vector<double> &S, int r,
-            int r3, Blocks &B) {
+            int r3, Blocks &B, bool partial = false) {
     const int k1 = V.k1, k3 = V.k3;
     B.r = r;
     B.r3 = r3;
@@ -158,12 +161,28 @@ void rotate(const View &V, const std::vector<double> &P, const std::vector<doubl
     const int A1 = B.A1, C1 = B.C1;
     B.F.assign((size_t)r * r * r3, 0.0);
     B.B100.assign((size_t)A1 * r * r3, 0.0);
-    B.B110.assign((size_t)A1 * A1 * r3, 0.0);
     B.B001.assign((size_t)r * r * C1, 0.0);
+    B.partial = partial && V.dev;
+    if (B.partial) {
+        B.B110.clear();
+        B.B101.clear();
+        std::vector<double> Y((size_t)k1 * r * r3), Y2((size_t)r * r * C1);
+        V.dev->rotate(B.Qp.data(), B.Qs.data(), r, r3, Y.data(), Y2.data(), true);
+        for (int l = 0; l < r3; ++l)
+            for (int y = 0; y < r; ++y)
+                for (int x = 0; x < k1; ++x) {
+                    const double v = Y[x + (size_t)k1 * (y + (size_t)r * l)];
+                    if (x < r) B.F[x + r * (y + (size_t)r * l)] = v;
+                    else B.B100[(x - r) + (size_t)A1 * (y + (size_t)r * l)] = v;
+                }
+        std::copy(Y2.begin(), Y2.end(), B.B001.begin());
+        return;
+    }
+    B.B110.assign((size_t)A1 * A1 * r3, 0.0);
     B.B101.assign((size_t)A1 * r * C1, 0.0);
     if (V.dev) {
         std::vector<double> Y((size_t)k1 * k1 * r3), Y2((size_t)k1 * r * C1);
-        V.dev->rotate(B.Qp.data(), B.Qs.data(), r, r3, Y.data(), Y2.data());
+        V.dev->rotate(B.Qp.data(), B.Qs.data(), r, r3, Y.data(), Y2.data(), false);
         for (int l = 0; l < r3; ++l)
             for (int y = 0; y < k1; ++y)
                 for (int x = 0; x < k1; ++x) {
@@ -509,6 +528,10 @@ void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, do
     // rotation (g = ||F||^2 of the rotated core, the same sum of squares the
     // objective forms), which an accepted step keeps for the next iteration
     bool have_B = false;
+    // a device that forms the Newton matrix itself returns only the blocks
+    // the gradient reads from each rotation
+    const int n_newton = (k1 - r) * r + (k3 - r3) * r3;
+    const bool partial = big && V.dev && V.dev->forms_newton() && n_newton >= device_solve_min();
     std::vector<double> G1, G3, d, Pn, Sn;
     // the Newton matrices (60 MB at rank (10,10,10)) are reused across calls
     static thread_local std::vector<double> tl_H, tl_Hs;
@@ -520,7 +543,7 @@ void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, do
     bool last_plain = false;
     while (true) {
         t0 = clk();
-        if (!have_B) rotate(V, P, S, r, r3, B);
+        if (!have_B) rotate(V, P, S, r, r3, B, partial);
         have_B = false;
         double nf;
         info.rel = local_gradient(B, G1, G3, nf);
@@ -543,6 +566,8 @@ void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, do
         const bool dev_h = big && V.dev && N >= device_solve_min() &&
                            V.dev->newton_matrix(r, r3, hdiag.data());
         if (!dev_h) {
+            // the host forms H: it needs the whole rotation
+            if (B.partial) rotate(V, P, S, r, r3, B, false);
             newton_matrix(B, H);
             for (int i = 0; i < N; ++i) hdiag[i] = H[(size_t)i * N + i];
         }
@@ -595,7 +620,7 @@ void inner_solve(const std::vector<double> &C, int k1, int k3, int r, int r3, do
             double g1;
             if (V.dev) {
                 t0 = clk();
-                rotate(V, Pn, Sn, r, r3, Bn);
+                rotate(V, Pn, Sn, r, r3, Bn, partial);
                 info.t_rotate += clk() - t0;
                 g1 = 0.0;
                 for (double v : Bn.F) g1 += v * v;

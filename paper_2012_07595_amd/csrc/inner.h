@@ -25,7 +25,10 @@ constexpr int kDeviceSolveMin = 256;
 //   rotate: with Qp (k1 x k1) and Qs (k3 x k3) row-major orthogonal,
 //           X_l = C.(I, I, Qs(:,l)); Y(x, y, l) = (Qp^T X_l Qp)(x, y) for l < r3
 //           at x + k1*(y + k1*l), Y2(x, j, z) = (Qp^T X_{r3+z} Qp(:, :r))(x, j)
-//           at x + k1*(j + r*z), z < k3 - r3
+//           at x + k1*(j + r*z), z < k3 - r3; with `partial`, only the
+//           blocks the gradient reads: Y(x, y, l) for y < r at
+//           x + k1*(y + r*l) and Y2(x, j, z) for x < r at x + r*(j + r*z)
+//           (a device that forms the Newton matrix keeps the rest)
 // Results equal the host products up to rounding order.
 struct InnerDevice {
     virtual ~InnerDevice() = default;
@@ -36,7 +39,10 @@ struct InnerDevice {
                         double *out) = 0;
     virtual void hooi3(const double *P, int r, double *M3) = 0;
     virtual void rotate(const double *Qp, const double *Qs, int r, int r3, double *Y,
-                        double *Y2) = 0;
+                        double *Y2, bool partial) = 0;
+    // true if newton_matrix forms the Newton matrix on the device (the inner
+    // solve then asks rotate for partial results)
+    virtual bool forms_newton() const { return false; }
     // The Newton matrix H of the last rotate() (the entries newton_matrix
     // states) formed and kept on the device, its N diagonal entries copied
     // to diag; false if the device does not provide it (the host forms H).

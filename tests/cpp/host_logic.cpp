@@ -541,7 +541,7 @@ static void check_top_eigvecs() {
 struct LoopDevice : InnerDevice {
     std::vector<double> C;
     int k1 = 0, k3 = 0;
-    int calls = 0;
+    int calls = 0, partial_calls = 0;
     double at(int a, int b, int c) const { return C[a + (size_t)k1 * (b + (size_t)k1 * c)]; }
     void set_core(const double *Cp, int k1_, int k3_) override {
         k1 = k1_;
@@ -594,8 +594,24 @@ struct LoopDevice : InnerDevice {
                     M3[(size_t)c * r * r + i + r * j] = s;
                 }
     }
-    void rotate(const double *Qp, const double *Qs, int r, int r3, double *Y, double *Y2) override {
+    void rotate(const double *Qp, const double *Qs, int r, int r3, double *Y, double *Y2,
+                bool partial) override {
         ++calls;
+        if (partial) {
+            // the whole rotation, then the blocks the contract returns
+            ++partial_calls;
+            std::vector<double> Yf((size_t)k1 * k1 * r3), Y2f((size_t)k1 * r * (k3 - r3));
+            rotate(Qp, Qs, r, r3, Yf.data(), Y2f.data(), false);
+            for (int l = 0; l < r3; ++l)
+                for (int y = 0; y < r; ++y)
+                    for (int x = 0; x < k1; ++x)
+                        Y[x + (size_t)k1 * (y + (size_t)r * l)] = Yf[x + (size_t)k1 * (y + (size_t)k1 * l)];
+            for (int z = 0; z < k3 - r3; ++z)
+                for (int j = 0; j < r; ++j)
+                    for (int x = 0; x < r; ++x)
+                        Y2[x + (size_t)r * (j + (size_t)r * z)] = Y2f[x + (size_t)k1 * (j + (size_t)r * z)];
+            return;
+        }
         std::vector<double> X((size_t)k1 * k1), T((size_t)k1 * k1);
         for (int l = 0; l < k3; ++l) {
             for (int b = 0; b < k1; ++b)
@@ -620,6 +636,13 @@ struct LoopDevice : InnerDevice {
                 }
         }
     }
+};
+
+// claims to form the Newton matrix itself (so the inner solve asks for
+// partial rotations) but declines each time: the inner solve must then
+// rotate again in full and form the matrix on the host
+struct DecliningNewtonDevice : LoopDevice {
+    bool forms_newton() const override { return true; }
 };
 
 static void check_inner_device() {
@@ -664,7 +687,37 @@ static void check_inner_device() {
             d2 += s * s;
         }
     require(std::sqrt(d2) <= 1e-10, "same subspace through the device interface");
-    std::printf("ok inner_device calls=%d\n", dev.calls);
+    // partial rotations (Newton systems from order 1, a host solver as the
+    // large-system solve) give the same solution
+    setenv("BKS_DEVICE_SOLVE_MIN", "1", 1);
+    const BigSolve hostbig = [](int N, const double *H, double mu, bool, double *b) {
+        std::vector<double> A(H, H + (size_t)N * N);
+        for (int q = 0; q < N; ++q) A[(size_t)q * N + q] += mu;
+        if (!la::cholesky(N, A.data())) return false;
+        la::chol_solve(N, A.data(), b);
+        return true;
+    };
+    std::vector<double> P2, S2;
+    InnerInfo i2;
+    DecliningNewtonDevice devp;
+    inner_solve(C, k1, k3, r, r3, 1e-13, 5, 50, false, P2, S2, i2, hostbig, &devp, 0.0);
+    require(devp.partial_calls > 0, "partial rotations taken");
+    require(i2.rel <= 1e-12, "partial-rotation path converges");
+    const double g2 = inner_objective(C, k1, k3, P2, S2, r, r3);
+    require(std::fabs(g0 - g2) <= 1e-12 * g0, "same objective with partial rotations");
+    double d3 = 0.0;
+    for (int j = 0; j < r; ++j)
+        for (int q = 0; q < k1; ++q) {
+            double s = P2[(size_t)q * r + j];
+            for (int u = 0; u < r; ++u) {
+                double pt = 0.0;
+                for (int x = 0; x < k1; ++x) pt += P0[(size_t)x * r + u] * P2[(size_t)x * r + j];
+                s -= P0[(size_t)q * r + u] * pt;
+            }
+            d3 += s * s;
+        }
+    require(std::sqrt(d3) <= 1e-10, "same subspace with partial rotations");
+    std::printf("ok inner_device calls=%d partial=%d\n", dev.calls, devp.partial_calls);
 }
 
 int main() {
