@@ -48,3 +48,42 @@ def test_ctx_create_fails_cleanly_without_gpu():
     h = ctypes.c_void_p()
     rc = lib.bks_ctx_create(0, 0, ctypes.byref(h))
     assert rc == bks.EDEVICE
+
+
+STRUCTS = [("bks_params", bks.Params), ("bks_info", bks.Info), ("hooi_params", bks.HooiParams),
+           ("bks_gparams", bks.GParams), ("bks_server_params", bks.ServerParams),
+           ("bks_result", bks.Result)]
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every struct the binding mirrors has the header's size and field
+    offsets (a C program built against include/bks.h prints them): a field
+    added on one side only would shift everything after it."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "bks.h"', "int main(void) {"]
+    for cname, py in STRUCTS:
+        lines.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            cf = fname.lstrip("_")
+            lines.append(f'    printf("{cname} {fname} %zu\\n", offsetof({cname}, {cf}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    r = subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            cname, field, value = line.split()
+            got[(cname, field)] = int(value)
+    for cname, py in STRUCTS:
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
