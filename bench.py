@@ -250,9 +250,10 @@ def solve_summary(elapsed, lat, results, ref, rank):
         "fp64_converged": bool(info_r.converged), "fp64_outer_iters": info_r.outer_iters,
         "fp64_rel_grad": info_r.rel_grad,
         "rel_gap_mode1": g1, "rel_gap_mode3": g3,
-        # SURVEY-style reading of the paper's conditioning: parity is claimed
-        # for converged solves on subspaces whose relative S-value gap is at
-        # least 1e-3; otherwise the gaps are reported beside the angle
+        # a reading of the section "Conditioning of the best approximation
+        # problem": parity is claimed for converged solves on subspaces whose
+        # relative S-value gap is at least 1e-3; otherwise the gaps are
+        # reported beside the angle
         "parity": ("pinned" if conv and max(au, aw) <= 1e-8 and min(g1, g3) >= 1e-3 else
                    "not converged in max_outer" if not conv else
                    "unpinned (ill-conditioned)" if min(g1, g3) < 1e-3 else "angle above 1e-8"),
