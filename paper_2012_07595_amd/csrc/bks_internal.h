@@ -151,12 +151,14 @@ void chol_solve_dev(hipStream_t s, const double *L, int N, double *x, bool forwa
 // A = L L^T in place on the device (lower triangle, column-major, leading
 // dimension N); *info (device) gets 0, or the 1-based index of the first
 // non-positive pivot (cholesky.hip).  With b (device, N) the forward
-// substitution runs along and b becomes L^{-1} b.  Given a rocBLAS handle
-// bound to s, large orders take panels of 256 columns with a dsyrk update
-// of the rest after each.  Used up to order kSmallCholMax, rocSOLVER's
-// potrf beyond.
+// substitution runs along and b becomes L^{-1} b.  work (device,
+// kCholWork doubles, required) holds a diagonal block between two steps.
+// Given a rocBLAS handle bound to s, large orders take panels of 256
+// columns with a dsyrk update of the rest after each.  Used up to order
+// kSmallCholMax, rocSOLVER's potrf beyond.
 constexpr int kSmallCholMax = 32768;
-void chol_factor_dev(hipStream_t s, double *A, int N, int *info, double *b = nullptr,
+constexpr int kCholWork = 32 * 32 + 32;
+void chol_factor_dev(hipStream_t s, double *A, int N, int *info, double *b, double *work,
                      void *blas = nullptr);
 
 // Device products of the inner solve for large cores (devsolve.cpp):

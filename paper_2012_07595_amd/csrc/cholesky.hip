@@ -30,6 +30,7 @@ namespace bks {
 namespace {
 
 constexpr int kCB = 32;  // block columns (= trailing-update tile)
+static_assert(kCholWork == kCB * kCB + kCB, "a diagonal block and its unknowns");
 
 // lane `l` (the same for every lane) of a wave's double
 __device__ inline double lane_read(double v, int l) {
@@ -62,11 +63,17 @@ constexpr int64_t kHybridMin = 8192;  // orders from which it is used
 // waves 1-3 meanwhile subtract the previous panel from their rows of the
 // block column (loaded at the start), then solve x L_kk^T = a (a row per
 // thread, right-looking, times the pivots' reciprocals).  Workgroup 0 writes the diagonal
-// block back.
+// block's factor L_kk and the block's forward-substituted unknowns: in place
+// when it is the step's only panel workgroup (`direct`), else to `work`,
+// since the other panel workgroups read A_kk and b_k at their own start,
+// which may come after workgroup 0 has finished (nothing orders workgroups
+// of one launch); the next step's workgroup 0 moves them into place.
 __device__ __forceinline__ void panel_part(double *__restrict__ A, int64_t N, int64_t k0, int nb,
-                                           int64_t p, bool fold, double *__restrict__ bvec,
-                           int *__restrict__ info, double (*Lp)[kCB + 1],
-                           double (*Lk)[kCB + 1], double *rd, double *yb, int *bad) {
+                                           int64_t p, bool fold, bool direct,
+                                           double *__restrict__ bvec, double *__restrict__ work,
+                                           int *__restrict__ info, double (*Lp)[kCB + 1],
+                                           double (*Lk)[kCB + 1], double *rd, double *yb,
+                                           int *bad) {
     const int tid = threadIdx.x;
     // the previous block column's panel to apply (not when a panel's first
     // step follows the rank-kPanel update of the whole trailing matrix)
@@ -164,7 +171,11 @@ __device__ __forceinline__ void panel_part(double *__restrict__ A, int64_t N, in
     if (p == 0) {
         for (int idx = tid; idx < nb * nb; idx += 256) {
             const int i = idx % nb, j = idx / nb;
-            if (i >= j) A[(k0 + j) * N + k0 + i] = Lk[i][j];
+            if (i < j) continue;
+            if (direct)
+                A[(k0 + j) * N + k0 + i] = Lk[i][j];
+            else
+                work[j * kCB + i] = Lk[i][j];
         }
     }
     if (tid < 64) {
@@ -180,7 +191,12 @@ __device__ __forceinline__ void panel_part(double *__restrict__ A, int64_t N, in
                 yi = i == j ? yj : ((i > j && i < nb) ? fma(-Lk[ic][j], yj, yi) : yi);
             }
             if (i < kCB) yb[i] = yi;
-            if (p == 0 && i < nb) bvec[k0 + i] = yi;
+            if (p == 0 && i < nb) {
+                if (direct)
+                    bvec[k0 + i] = yi;
+                else
+                    work[kCB * kCB + i] = yi;
+            }
         }
     } else if (has_row) {
         // right-looking: once x_j is final, its terms leave the later
@@ -260,10 +276,13 @@ __device__ __forceinline__ void update_tile(double *__restrict__ A, int64_t N, i
 // column k with panel k-1 folded in (panel_part); the rest apply panel k-1
 // to the trailing columns beyond block k (update_tile), which panel k does
 // not touch.  Every column thus receives every earlier panel's update before
-// its own step.
+// its own step.  kflush >= 0: the full diagonal block at kflush (an earlier
+// step's) and its unknowns wait in `work`; workgroup 0 moves them into place
+// before it does anything else (no workgroup of this launch reads either).
 __global__ __launch_bounds__(256) void chol_step(double *__restrict__ A, int64_t N, int64_t k0,
                                                  int nb, int64_t gp, int fold, int64_t cp,
-                                                 double *__restrict__ bvec,
+                                                 int64_t kflush, double *__restrict__ bvec,
+                                                 double *__restrict__ work,
                                                  int *__restrict__ info) {
     __shared__ double sm[2][kCB][kCB + 1];
     __shared__ double rd[kCB];  // 1 / L(j, j)
@@ -271,8 +290,17 @@ __global__ __launch_bounds__(256) void chol_step(double *__restrict__ A, int64_t
     __shared__ int bad;
     if (*info != 0) return;
     const int64_t w = blockIdx.x;
+    if (w == 0 && kflush >= 0) {
+        for (int idx = threadIdx.x; idx < kCB * kCB; idx += 256) {
+            const int i = idx % kCB, j = idx / kCB;
+            if (i >= j) A[(kflush + j) * N + kflush + i] = work[idx];
+        }
+        if (bvec != nullptr && threadIdx.x < kCB)
+            bvec[kflush + threadIdx.x] = work[kCB * kCB + threadIdx.x];
+    }
     if (w < gp)
-        panel_part(A, N, k0, nb, w, fold != 0, bvec, info, sm[0], sm[1], rd, yb, &bad);
+        panel_part(A, N, k0, nb, w, fold != 0, gp == 1, bvec, work, info, sm[0], sm[1], rd, yb,
+                   &bad);
     else
         update_tile(A, N, k0 - kCB, k0 + nb, w - gp, cp, sm[0], sm[1]);
 }
@@ -304,13 +332,19 @@ __global__ __launch_bounds__(256) void shift_copy(double *__restrict__ dst,
 
 }  // namespace
 
-void chol_factor_dev(hipStream_t s, double *A, int N, int *info, double *b, void *blas) {
+void chol_factor_dev(hipStream_t s, double *A, int N, int *info, double *b, double *work,
+                     void *blas) {
     const int64_t n = N;
+    if (work == nullptr) fail(BKS_EINVAL, "chol_factor_dev: no workspace");
     // large orders: panels of kPanel columns factored by the steps below
     // (their trailing tiles restricted to the panel's columns), each followed
     // by one rank-kPanel update of the rest of the matrix on rocBLAS (dsyrk)
     const int64_t panel = (blas && n >= kHybridMin) ? kPanel : n;
     hipLaunchKernelGGL(clear_info, dim3(1), dim3(1), 0, s, info);
+    // the block whose factor and unknowns wait in `work` (a step with more
+    // than one panel workgroup leaves them there), or -1.  The last step has
+    // no rows below its block, hence one panel workgroup: nothing is left.
+    int64_t pending = -1;
     for (int64_t p0 = 0; p0 < n; p0 += panel) {
         const int64_t p1 = std::min(n, p0 + panel);
         for (int64_t k0 = p0; k0 < p1; k0 += kCB) {
@@ -328,7 +362,8 @@ void chol_factor_dev(hipStream_t s, double *A, int N, int *info, double *b, void
             const int64_t tiles = cp * (cp + 1) / 2 + (T - cp) * cp;
             const bool fused = gp + tiles <= kFuseMaxWg;
             hipLaunchKernelGGL(chol_step, dim3((unsigned)(gp + (fused ? tiles : 0))), dim3(256), 0,
-                               s, A, n, k0, nb, gp, fold ? 1 : 0, cp, b, info);
+                               s, A, n, k0, nb, gp, fold ? 1 : 0, cp, pending, b, work, info);
+            pending = gp == 1 ? -1 : k0;
             if (!fused && tiles > 0)
                 hipLaunchKernelGGL(chol_trail, dim3((unsigned)tiles), dim3(256), 0, s, A, n,
                                    k0 - kCB, k0 + nb, cp, info);

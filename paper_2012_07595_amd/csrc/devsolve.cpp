@@ -58,7 +58,8 @@ bool DevSolver::solve_resident(hipStream_t s, int N, double mu, double *b) {
     const size_t bytes = (size_t)N * N * 8;
     if (dH.bytes < bytes) fail(BKS_EINVAL, "Newton matrix not on the device");
     dA.ensure(bytes);
-    db.ensure((size_t)N * 8 + 64);
+    // b, then info (64 bytes), then the factorisation's workspace
+    db.ensure((size_t)N * 8 + 64 + kCholWork * 8);
     pin.ensure((size_t)N * 8 + 64);
     double *st = reinterpret_cast<double *>(pin.ptr);
     shift_copy_dev(s, dA.as<double>(), dH.as<double>(), N, mu);
@@ -71,7 +72,8 @@ bool DevSolver::solve_resident(hipStream_t s, int N, double mu, double *b) {
     // L^{-1} b); rocSOLVER's potrf beyond
     const bool own = N <= kSmallCholMax;
     if (own) {
-        chol_factor_dev(s, dA.as<double>(), N, dinfo, db.as<double>(), get_handle(s));
+        double *dwork = reinterpret_cast<double *>(db.as<char>() + (size_t)N * 8 + 64);
+        chol_factor_dev(s, dA.as<double>(), N, dinfo, db.as<double>(), dwork, get_handle(s));
     } else {
         static_assert(sizeof(rocblas_int) == sizeof(int), "info is an int");
         rocblas_handle h = static_cast<rocblas_handle>(get_handle(s));

@@ -785,7 +785,7 @@ size_t solve_footprint(int64_t m, int64_t n, int64_t nnz, const bks_params &prm)
         b += 4 * core / 4 * 5 + (k1 * k1 + k3 * k3) * 8 / 4 * 5;
     const size_t N = (size_t)prm.r * (k1 - std::min<size_t>(k1, prm.r)) +
                      (size_t)prm.r3 * (k3 - std::min<size_t>(k3, prm.r3));
-    if ((int64_t)N >= device_solve_min()) b += 2 * N * N * 8 / 4 * 5 + N * 16 + 4096;
+    if ((int64_t)N >= device_solve_min()) b += 2 * N * N * 8 / 4 * 5 + N * 16 + 16384;
     return b;
 }
 
