@@ -27,15 +27,23 @@
  *   - Streams: `stream` arguments are hipStream_t values passed as void*;
  *     NULL means the null stream.
  *
- * Environment (the first four are read once per process; results do not
+ * Environment (the first six are read once per process; results do not
  * depend on them unless stated)
  *   BKS_HOST_THREADS      host threads of the inner solve (default: hardware
  *                         concurrency, at most 8)
  *   BKS_DEVICE_CORE_MIN   cores with at least this many entries (k1^2 k3) form
  *                         their dense products on the device (default 1e5;
  *                         results change only by rounding order)
+ *   BKS_DEVICE_HOOI_MIN   of those, cores with at least this many entries also
+ *                         run the HOOI steps' and the objective's products on
+ *                         the device (default 1e5; rounding order only)
  *   BKS_DEVICE_SOLVE_MIN  Newton systems of at least this order are factorised
- *                         on the device (default 512; rounding order only)
+ *                         on the device (default 256; rounding order only)
+ *   BKS_NARROW_REG        bit mask of the narrow products that take the
+ *                         register-direct kernel instead of the LDS-staged
+ *                         one: 1 FREE3 symmetric half, 2 FREE3 with X != Y,
+ *                         4 MODE3 (and FREE1's first step), 8 FREE1's second
+ *                         step (default 8; rounding order only)
  *   BKS_DEBUG_INNER=1     one line per inner solve on stderr
  *   BKS_FAIL_NEXT_ALLOC=1 checked at every device allocation: the next one
  *                         fails with BKS_ENOMEM and the variable is cleared
