@@ -346,7 +346,10 @@ typedef struct {
  * memory footprint fits the budget and a slot is free: a free slot takes the
  * oldest waiting request that fits, passing over one that does not fit at
  * most 16 times before it waits for that one.  The device work of admitted
- * sessions runs on per-session streams and overlaps. */
+ * sessions runs on per-session streams and overlaps.  Every slot's stream is
+ * made here: BKS_EDEVICE (and no server) if one cannot be, or if the free
+ * memory query fails when no budget is given.  The calling thread's current
+ * device is left as it was. */
 int bks_server_create(bks_ctx ctx, const bks_server_params *prm, bks_server *out);
 /* Submit a solve of an uploaded tensor (the tensor must outlive the
  * request).  U, W, F are host buffers written when the request completes. */

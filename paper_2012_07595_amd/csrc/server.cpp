@@ -76,6 +76,7 @@ struct bks_server_s {
     std::condition_variable cv_queue, cv_done, cv_host;
     std::deque<Request *> queue;
     std::map<uint64_t, std::unique_ptr<Request>> reqs;
+    std::vector<hipStream_t> streams;  // one per session slot, made by create
     std::vector<std::thread> workers;
     std::atomic<uint64_t> next_id{1};
     bool stop = false;
@@ -86,7 +87,7 @@ struct bks_server_s {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
 
-    void worker() {
+    void worker(hipStream_t stream) {
         (void)hipSetDevice(ctx->device);
         // host solves run concurrently in up to host_slots workers: share the
         // host threads among them (results do not depend on the count)
@@ -105,7 +106,7 @@ struct bks_server_s {
             }
             cv_host.notify_one();
         };
-        if (hipStreamCreateWithFlags(&sc.stream, hipStreamNonBlocking) != hipSuccess) return;
+        sc.stream = stream;
         auto acct = std::make_shared<DevAccount>();
         DevAccount::current = acct;
         while (true) {
@@ -176,7 +177,7 @@ struct bks_server_s {
         }
         sc.release_workspaces();
         DevAccount::current.reset();
-        (void)hipStreamDestroy(sc.stream);
+        sc.stream = nullptr;  // the server's, destroyed after the workers end
     }
 
     // The request a free slot takes (caller holds mu): the oldest one that
@@ -236,15 +237,36 @@ int bks_server_create(bks_ctx ctx, const bks_server_params *prm, bks_server *out
     s->ctx = reinterpret_cast<Ctx *>(ctx);
     s->max_active = (prm && prm->max_active > 0) ? prm->max_active : 8;
     s->host_slots = (prm && prm->host_workers > 0) ? prm->host_workers : 4;
+    // the ctx's device for the free-memory query and the slots' streams; the
+    // caller's current device is restored before returning
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(s->ctx->device) != hipSuccess)
+        return BKS_EDEVICE;
+    int status = BKS_OK;
     size_t budget = prm ? prm->mem_budget_bytes : 0;
     if (budget == 0) {
         size_t fr = 0, tot = 0;
-        (void)hipSetDevice(s->ctx->device);
-        if (hipMemGetInfo(&fr, &tot) != hipSuccess) return BKS_EDEVICE;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) status = BKS_EDEVICE;
         budget = fr / 4 * 3;
     }
     s->budget = budget;
-    for (int i = 0; i < s->max_active; ++i) s->workers.emplace_back([p = s.get()] { p->worker(); });
+    // every slot's stream before any worker starts: a slot without one
+    // would leave the requests it was meant to take waiting for ever
+    for (int i = 0; status == BKS_OK && i < s->max_active; ++i) {
+        hipStream_t st = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
+            status = BKS_EDEVICE;
+        else
+            s->streams.push_back(st);
+    }
+    if (status != BKS_OK) {
+        for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+        (void)hipSetDevice(prev);
+        return status;
+    }
+    for (int i = 0; i < s->max_active; ++i)
+        s->workers.emplace_back([p = s.get(), st = s->streams[i]] { p->worker(st); });
+    (void)hipSetDevice(prev);
     *out = s.release();
     return BKS_OK;
 }
@@ -341,6 +363,7 @@ void bks_server_destroy(bks_server s) {
     }
     s->cv_queue.notify_all();
     for (auto &w : s->workers) w.join();
+    for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
     delete s;
 }
 
