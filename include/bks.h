@@ -26,6 +26,9 @@
  *     is used by one host thread at a time.
  *   - Streams: `stream` arguments are hipStream_t values passed as void*;
  *     NULL means the null stream.
+ *   - Devices: a call on a ctx (or on a tensor of one) makes the ctx's
+ *     device current on the calling thread and leaves it so;
+ *     bks_server_create restores the caller's.
  *
  * Environment (the first six are read once per process; results do not
  * depend on them unless stated)
