@@ -306,7 +306,8 @@ __global__ __launch_bounds__(256) void chol_step(double *__restrict__ A, int64_t
 }
 
 // The trailing update alone (the tiles of a step too many for one round of
-// the fused kernel, whose register use allows one workgroup per compute unit)
+// the fused kernel, whose register use allows two workgroups per compute
+// unit)
 __global__ __launch_bounds__(256) void chol_trail(double *__restrict__ A, int64_t N, int64_t kp,
                                                   int64_t j0, int64_t cp,
                                                   const int *__restrict__ info) {
